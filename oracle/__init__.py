@@ -1,0 +1,26 @@
+"""CPU oracle for recursive density-matrix purification (Rubensson, arXiv:1101.0265).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or link this
+package: only the test-suite, the smoke check and the benchmark's CPU-baseline leg use it.
+It shares no code with the HIP library (no kernels, headers, helpers or constant tables);
+the two meet only at the seeded inputs made by ``paper_1101_0265_amd.hamiltonians``.
+
+Everything here is plain FP64 NumPy/Python written from the paper:
+
+* ``polynomials`` -- the P_{i,j} family built from its definition (degree 1+i+j, fixed
+  points 0 and 1, i and j vanishing derivatives there) and the closed forms the algorithms
+  use (x^2, 2x-x^2, 3x^2-2x^3).
+* ``schedule``    -- the scalar parameter recurrences of Algorithms 1 and 2 (alpha, beta,
+  beta-bar, branch choice) and the trace-based choice of the unscaled trace-correcting scheme.
+* ``spectral``    -- the schemes applied to the eigenvalues of X_0 (every f_i is a
+  polynomial, so X_i = Q p_i(Lambda) Q^T); gives the branch/alpha sequence, product counts and
+  per-iteration idempotency, trace and Frobenius norm at O(n) cost per iteration.
+* ``dense``       -- the schemes on dense matrices with numpy.matmul, steps in the paper's
+  order and notation.
+* ``exact``       -- the exact projector D = theta(mu I - F) from an eigendecomposition, its
+  invariants, and the decisions of Algorithm 2 in exact rational arithmetic.
+
+Parity status of each function is stated in its module header.
+"""
+
+SCHEMES = ("sp2", "tc2", "snf_varmu", "mcweeny", "snf_fixmu")

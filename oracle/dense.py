@@ -1,0 +1,131 @@
+"""Dense FP64 matrix oracle of the purification schemes (test infrastructure only).
+
+Follows the paper's steps on n x n matrices with ``numpy.matmul``:
+
+* Algorithm 2 (varying-mu scale-and-fold) and its alpha = 0 form (unscaled trace-correcting
+  scheme with the eigenvalue-based choice): X_0 = (lambda_max I - F)/(lambda_max - lambda_min);
+  square branch X <- ((1+a) X - a I)^2, fold branch X <- 2 (1+a) X - (1+a)^2 X^2.
+* The trace-based choice ("sp2"): same f_0 and polynomials with a = 0; square iff
+  |tr(X^2) - N| < |2 tr X - tr(X^2) - N|.
+* Algorithm 1 (fixed-mu scale-and-fold) and its alpha = 1 form (McWeeny):
+  X_0 = (mu I - F)/gamma + 0.5 I; X_s = a (X - 0.5 I) + 0.5 I; X <- 3 X_s^2 - 2 X_s^3.
+
+Stopping rule (reading of the open loop length): X_{i-1}^2 is formed, and if
+||X_{i-1}^2 - X_{i-1}||_F <= tol the result is D = X_{i-1}.  The scheme's product count
+includes that certifying product; Algorithm 1 counts two products per iteration.  The oracle
+itself spends extra products (it forms X^2 for the check separately from the step) -- it is
+slow on purpose and the count it reports is the scheme's, not its own.
+
+``mask`` (optional): a callable applied to each new X, used by the block-truncation oracle
+(drop blocks below a threshold after every step, the BSR reading).
+
+Parity: pinned against the exact projector, its invariants and the spectral oracle.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import schedule as sch
+
+
+def f0(F: np.ndarray, scheme: str, lambda_min: float, lambda_max: float,
+       mu: float = None) -> np.ndarray:
+    n = F.shape[0]
+    I = np.eye(n)
+    if scheme in ("sp2", "tc2", "snf_varmu"):
+        return (lambda_max * I - F) / (lambda_max - lambda_min)       # Algorithm 2, f_0
+    gamma = sch.alg1_gamma(lambda_min, lambda_max, mu)
+    return (mu * I - F) / gamma + 0.5 * I                              # Algorithm 1, X_0
+
+
+def step(X: np.ndarray, branch: str, alpha: float) -> np.ndarray:
+    """One purification transformation f_i, as printed."""
+    I = np.eye(X.shape[0])
+    if branch == sch.SQUARE:
+        Y = (1.0 + alpha) * X - alpha * I
+        return Y @ Y
+    if branch == sch.FOLD:
+        return 2.0 * (1.0 + alpha) * X - (1.0 + alpha) ** 2 * (X @ X)
+    Xs = alpha * (X - 0.5 * I) + 0.5 * I
+    Xs2 = Xs @ Xs
+    Xs3 = Xs2 @ Xs
+    return 3.0 * Xs2 - 2.0 * Xs3
+
+
+def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
+           n_occ: int = None, homo: float = None, lumo: float = None, mu: float = None,
+           xi: float = None, tol: float = 1e-10, max_iter: int = 200, mask=None,
+           force_branches: str = None) -> dict:
+    """Purify the dense symmetric ``F``.
+
+    Returns dict(status, D, iterations, products, branches, log, e_final, trace) with the
+    same meaning as ``oracle.spectral.purify_spectrum``.  ``force_branches`` replays a given
+    branch string for the trace-based scheme (used when an FP64 near-tie of the trace rule is
+    resolved the other way by another implementation).
+    """
+    if F.ndim != 2 or F.shape[0] != F.shape[1]:
+        raise ValueError("F must be square")
+    st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi)
+    X = f0(np.asarray(F, dtype=np.float64), scheme, lambda_min, lambda_max, mu)
+    if mask is not None:
+        X = mask(X)
+    per_it = 2 if scheme in ("mcweeny", "snf_fixmu") else 1
+    log, branches = [], []
+    products = 0
+    status = "noconv"
+    for it in range(max_iter + 1):
+        X2 = X @ X
+        products += 1
+        e = float(np.linalg.norm(X2 - X))
+        t1 = float(np.trace(X))
+        t2 = float(np.trace(X2))
+        rec = dict(i=it, e=e, t1=t1, t2=t2, beta=st.beta, betabar=st.betabar)
+        if not math.isfinite(e):
+            status = "nonfinite"
+            log.append(rec)
+            break
+        if e <= tol:
+            status = "ok"
+            log.append(rec)
+            break
+        if it == max_iter:
+            log.append(rec)
+            break
+        branch, alpha = st.choose(t1, t2, n_occ)
+        if force_branches is not None and it < len(force_branches):
+            branch = force_branches[it]
+        rec.update(branch=branch, alpha=alpha,
+                   margin=(sch.trace_margin(t1, t2, n_occ) if scheme == "sp2" else None))
+        log.append(rec)
+        branches.append(branch)
+        X = step(X, branch, alpha)
+        if mask is not None:
+            X = mask(X)
+        st.advance(branch, alpha)
+        products += per_it - 1
+    if n_occ is not None and status == "ok" and abs(float(np.trace(X)) - n_occ) >= 0.5:
+        status = "mixed"
+    return dict(status=status, D=X, iterations=len(branches), products=products,
+                branches="".join(branches), log=log, e_final=log[-1]["e"],
+                trace=float(np.trace(X)))
+
+
+def block_truncation_mask(b: int, tau: float):
+    """Mask for the block-truncated iteration: after each step drop block (I,J) together with
+    its mirror (J,I) when the Frobenius norm of block (I,J), I < J, is below ``tau``; diagonal
+    blocks are never dropped.  (The paper leaves the truncation rule open; this is the reading
+    used for the block-sparse path.)"""
+
+    def apply(X: np.ndarray) -> np.ndarray:
+        n = X.shape[0]
+        nb = n // b
+        blocks = X.reshape(nb, b, nb, b)
+        norms = np.sqrt(np.einsum("ibjc,ibjc->ij", blocks, blocks))
+        keep = norms >= tau
+        keep = np.triu(keep, 1)
+        keep = keep | keep.T | np.eye(nb, dtype=bool)
+        return (blocks * keep[:, None, :, None]).reshape(n, n)
+
+    return apply

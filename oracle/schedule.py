@@ -1,0 +1,152 @@
+"""Scalar parameter schedules, in IEEE FP64 Python floats (test infrastructure only).
+
+Every expression keeps the paper's operation order, evaluated left to right with no fused
+multiply-add, so the decisions it takes are reproducible bit for bit by any FP64 code that
+evaluates the same expressions in the same order.
+
+* Algorithm 1 (McWeeny-based fixed-mu scale-and-fold): gamma, X_0 scaling and beta at set-up;
+  per iteration alpha = 3 / sqrt(12 beta^2 - 18 beta + 9), beta_s = alpha (beta - 0.5) + 0.5,
+  beta <- 3 beta_s^2 - 2 beta_s^3.  alpha solves Eq. 3 for m = 1.  alpha = 1 gives the regular
+  grand-canonical McWeeny scheme.
+* Algorithm 2 (P_{0,1} & P_{1,0} varying-mu scale-and-fold): beta = f0(lumo),
+  beta-bar = f0(homo); if beta + beta-bar > 1 square with alpha = beta / (2 - beta), else fold
+  with alpha = (1 - beta-bar) / (1 + beta-bar).  alpha = 0 gives the unscaled second-order
+  trace-correcting scheme with the eigenvalue-based choice.
+* Trace rule (the original trace-correcting choice, paragraph after Eqs. 4-5): square iff
+  |tr(X^2) - N| < |2 tr X - tr(X^2) - N|; a tie folds.
+
+Parity: pinned (Eq. 3 residual, closed-form images of the interval ends, alpha = 0 / 1
+reductions, exact-rational decisions).
+"""
+from __future__ import annotations
+
+import math
+
+SQUARE = "S"   # P_{1,0} branch: X <- ((1+a) X - a I)^2
+FOLD = "F"     # P_{0,1} branch: X <- 2 (1+a) X - (1+a)^2 X^2
+MCW = "M"      # P_{1,1} branch: X <- 3 Xs^2 - 2 Xs^3, Xs = a (X - I/2) + I/2
+
+
+# ---- Algorithm 1 -----------------------------------------------------------------------
+
+def alg1_gamma(lambda_min: float, lambda_max: float, mu: float) -> float:
+    """gamma = 2 max(lambda_max - mu, mu - lambda_min)."""
+    return 2.0 * max(lambda_max - mu, mu - lambda_min)
+
+
+def alg1_f0_scalar(lam: float, mu: float, gamma: float) -> float:
+    """Image of an eigenvalue under X_0 = (mu I - F)/gamma + 0.5 I."""
+    return (mu - lam) / gamma + 0.5
+
+
+def alg1_beta0(xi: float, gamma: float) -> float:
+    """beta = 0.5 (1 - xi / gamma): X-space image of the level nearest mu (symmetric gap)."""
+    return 0.5 * (1.0 - xi / gamma)
+
+
+def alg1_alpha(beta: float) -> float:
+    """alpha = 3 / sqrt(12 beta^2 - 18 beta + 9), the root alpha >= 1 of Eq. 3 for m = 1."""
+    return 3.0 / math.sqrt(12.0 * beta * beta - 18.0 * beta + 9.0)
+
+
+def alg1_beta_next(beta: float, alpha: float) -> float:
+    """beta_s = alpha (beta - 0.5) + 0.5; beta <- 3 beta_s^2 - 2 beta_s^3."""
+    bs = alpha * (beta - 0.5) + 0.5
+    return 3.0 * bs * bs - 2.0 * bs * bs * bs
+
+
+# ---- Algorithm 2 -----------------------------------------------------------------------
+
+def alg2_f0_scalar(lam: float, lambda_min: float, lambda_max: float) -> float:
+    """Image of an eigenvalue under X_0 = (lambda_max I - F)/(lambda_max - lambda_min)."""
+    return (lambda_max - lam) / (lambda_max - lambda_min)
+
+
+def alg2_choose_square(beta: float, betabar: float) -> bool:
+    """The branch test of Algorithm 2: square (P_{1,0}) iff beta + beta-bar > 1."""
+    return beta + betabar > 1.0
+
+
+def alg2_square_alpha(beta: float) -> float:
+    return beta / (2.0 - beta)
+
+
+def alg2_square_scalar(x: float, alpha: float) -> float:
+    """((1 + alpha) x - alpha)^2."""
+    y = (1.0 + alpha) * x - alpha
+    return y * y
+
+
+def alg2_fold_alpha(betabar: float) -> float:
+    return (1.0 - betabar) / (1.0 + betabar)
+
+
+def alg2_fold_scalar(x: float, alpha: float) -> float:
+    """2 (1 + alpha) x - (1 + alpha)^2 x^2."""
+    return 2.0 * (1.0 + alpha) * x - (1.0 + alpha) * (1.0 + alpha) * x * x
+
+
+# ---- trace rule ------------------------------------------------------------------------
+
+def trace_choose_square(tr_x: float, tr_x2: float, n_occ: int) -> bool:
+    """Square iff the trace after squaring is strictly closer to N than after folding."""
+    return abs(tr_x2 - n_occ) < abs(2.0 * tr_x - tr_x2 - n_occ)
+
+
+def trace_margin(tr_x: float, tr_x2: float, n_occ: int) -> float:
+    """Signed distance of the trace decision from a tie (positive favours folding)."""
+    return abs(tr_x2 - n_occ) - abs(2.0 * tr_x - tr_x2 - n_occ)
+
+
+# ---- one step of the scalar state (used by the spectral and dense drivers) --------------
+
+class SchemeState:
+    """beta / beta-bar tracking for a scheme, one ``step`` per iteration.
+
+    scheme: "sp2" (trace rule, no scaling), "tc2" (Algorithm 2, alpha = 0),
+    "snf_varmu" (Algorithm 2), "mcweeny" (Algorithm 1, alpha = 1), "snf_fixmu"
+    (Algorithm 1).  For "sp2" the tracked beta / beta-bar follow the branches actually taken
+    (they are reported only; the choice uses traces).
+    """
+
+    def __init__(self, scheme: str, lambda_min: float, lambda_max: float, *,
+                 homo: float = None, lumo: float = None, mu: float = None,
+                 xi: float = None):
+        self.scheme = scheme
+        if scheme in ("sp2", "tc2", "snf_varmu"):
+            self.beta = alg2_f0_scalar(lumo, lambda_min, lambda_max) if lumo is not None else 0.0
+            self.betabar = (alg2_f0_scalar(homo, lambda_min, lambda_max)
+                            if homo is not None else 1.0)
+            self.gamma = None
+        elif scheme in ("mcweeny", "snf_fixmu"):
+            self.gamma = alg1_gamma(lambda_min, lambda_max, mu)
+            self.beta = alg1_beta0(xi, self.gamma)
+            self.betabar = 1.0 - self.beta
+        else:
+            raise ValueError(f"unknown scheme {scheme!r}")
+
+    def choose(self, tr_x: float = None, tr_x2: float = None, n_occ: int = None):
+        """Return (branch, alpha) for the next iteration without changing the state."""
+        s = self.scheme
+        if s == "sp2":
+            return (SQUARE if trace_choose_square(tr_x, tr_x2, n_occ) else FOLD), 0.0
+        if s in ("tc2", "snf_varmu"):
+            if alg2_choose_square(self.beta, self.betabar):
+                return SQUARE, (alg2_square_alpha(self.beta) if s == "snf_varmu" else 0.0)
+            return FOLD, (alg2_fold_alpha(self.betabar) if s == "snf_varmu" else 0.0)
+        return MCW, (alg1_alpha(self.beta) if s == "snf_fixmu" else 1.0)
+
+    def advance(self, branch: str, alpha: float) -> None:
+        if branch == SQUARE:
+            self.beta = alg2_square_scalar(self.beta, alpha)
+            self.betabar = alg2_square_scalar(self.betabar, alpha)
+        elif branch == FOLD:
+            self.beta = alg2_fold_scalar(self.beta, alpha)
+            self.betabar = alg2_fold_scalar(self.betabar, alpha)
+        else:
+            self.beta = alg1_beta_next(self.beta, alpha)
+            self.betabar = 1.0 - self.beta
+
+    def bound(self) -> float:
+        """A-priori eigenvalue error bound max(beta, 1 - beta-bar) with exact bounds."""
+        return max(self.beta, 1.0 - self.betabar)

@@ -1,0 +1,133 @@
+"""Spectral oracle: the purification schemes applied to eigenvalues (test infrastructure only).
+
+Every f_i of Eq. 1 is a polynomial, so X_i = Q p_i(Lambda) Q^T and the iteration acts on each
+eigenvalue of X_0 independently.  This is also the paper's own argument for testing on
+diagonal Hamiltonians (remark following Fig. 3: results for a given gap and chemical potential
+hold for any Hamiltonian with that gap and potential).  Per iteration it gives, at O(n) cost:
+tr X = sum p, ||X||_F^2 = tr X^2 = sum p^2, ||X^2 - X||_F = sqrt(sum (p^2 - p)^2), the branch
+and alpha sequence, and the product count.
+
+Stopping rule (the algorithms leave the loop length open; reading used throughout): before
+applying f_i, the product X_{i-1}^2 is formed; if ||X_{i-1}^2 - X_{i-1}||_F <= tol the result is
+D = X_{i-1} and that certifying product is counted.  Algorithm 1 spends two products per
+iteration (X_s^2 and X_s^3), the other schemes one.
+
+Parity: pinned against the dense oracle and the eigendecomposition (tests).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import schedule as sch
+
+
+def f0_eigs(eigvals: np.ndarray, scheme: str, lambda_min: float, lambda_max: float,
+            mu: float = None) -> np.ndarray:
+    """Eigenvalues of X_0 = f_0(F) (Algorithm 2 / trace scheme, or Algorithm 1)."""
+    lam = np.asarray(eigvals, dtype=np.float64)
+    if scheme in ("sp2", "tc2", "snf_varmu"):
+        return (lambda_max - lam) / (lambda_max - lambda_min)
+    gamma = sch.alg1_gamma(lambda_min, lambda_max, mu)
+    return (mu - lam) / gamma + 0.5
+
+
+def apply_branch(p: np.ndarray, branch: str, alpha: float) -> np.ndarray:
+    """One f_i on eigenvalues, written as the paper's transformation."""
+    if branch == sch.SQUARE:                 # P_{1,0}((1+a) x - a), Eq. 4
+        y = (1.0 + alpha) * p - alpha
+        return y * y
+    if branch == sch.FOLD:                   # P_{0,1}((1+a) x), Eq. 5
+        z = (1.0 + alpha) * p
+        return 2.0 * z - z * z
+    xs = alpha * (p - 0.5) + 0.5             # P_{1,1}(a (x - 1/2) + 1/2), Eq. 2 with m = 1
+    return 3.0 * xs * xs - 2.0 * xs * xs * xs
+
+
+def products_per_iteration(scheme: str) -> int:
+    return 2 if scheme in ("mcweeny", "snf_fixmu") else 1
+
+
+def purify_spectrum(eigvals: np.ndarray, scheme: str, *, lambda_min: float,
+                    lambda_max: float, n_occ: int = None, homo: float = None,
+                    lumo: float = None, mu: float = None, xi: float = None,
+                    tol: float = 1e-10, max_iter: int = 200) -> dict:
+    """Run ``scheme`` on the spectrum; returns the final eigenvalues of D and the log.
+
+    Returned keys: status ("ok" | "noconv" | "nonfinite"), p (eigenvalues of D), iterations,
+    products, branches (string of S/F/M), log (list of per-iteration dicts with i, branch,
+    alpha, beta, betabar, e, t1, t2 of X_{i-1} before the step), e_final, trace.
+    """
+    st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi)
+    p = f0_eigs(eigvals, scheme, lambda_min, lambda_max, mu)
+    per_it = products_per_iteration(scheme)
+    log, branches = [], []
+    products = 0
+    status = "noconv"
+    for it in range(max_iter + 1):
+        t1 = float(np.sum(p))
+        t2 = float(np.sum(p * p))
+        e = math.sqrt(float(np.sum((p * p - p) ** 2)))
+        products += 1                              # the product X_{i-1}^2
+        rec = dict(i=it, e=e, t1=t1, t2=t2, beta=st.beta, betabar=st.betabar)
+        if not math.isfinite(e):
+            status = "nonfinite"
+            log.append(rec)
+            break
+        if e <= tol:
+            status = "ok"
+            log.append(rec)
+            break
+        if it == max_iter:
+            log.append(rec)
+            break
+        branch, alpha = st.choose(t1, t2, n_occ)
+        rec.update(branch=branch, alpha=alpha)
+        log.append(rec)
+        branches.append(branch)
+        p = apply_branch(p, branch, alpha)
+        st.advance(branch, alpha)
+        products += per_it - 1                     # Algorithm 1's second product
+    return dict(status=status, p=p, iterations=len(branches), products=products,
+                branches="".join(branches), log=log, e_final=log[-1]["e"],
+                trace=float(np.sum(p)))
+
+
+def decision_sequence(scheme: str, *, lambda_min: float, lambda_max: float, homo: float,
+                      lumo: float, mu: float = None, xi: float = None,
+                      steps: int = 64) -> list:
+    """(branch, alpha, beta, betabar) for the first ``steps`` iterations of the scalar
+    recurrence alone (Algorithms 1 and 2 decide without looking at X)."""
+    st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi)
+    out = []
+    for _ in range(steps):
+        branch, alpha = st.choose()
+        out.append((branch, alpha, st.beta, st.betabar))
+        st.advance(branch, alpha)
+    return out
+
+
+def products_to_accuracy(scheme: str, mu01: float, xi: float, acc: float = 1e-9,
+                         max_iter: int = 200) -> int:
+    """Products needed until the eigenvalue error bound max(beta, 1 - beta-bar) <= acc for a
+    spectrum in [0, 1] with a gap of width xi centred at mu01 and exact bounds (the setting of
+    Fig. 3; with exact bounds this bound equals ||D~ - D||_2 of a diagonal test matrix).
+
+    The unscaled trace scheme ("sp2") is not covered: its choice needs the whole spectrum.
+    """
+    homo, lumo = mu01 - 0.5 * xi, mu01 + 0.5 * xi
+    kw = dict(lambda_min=0.0, lambda_max=1.0, homo=homo, lumo=lumo, mu=mu01, xi=xi)
+    if scheme in ("mcweeny", "snf_fixmu"):
+        # Algorithm 1 maps mu onto 0.5; the level nearest 0.5 is xi/2 away in F-space.
+        pass
+    st = sch.SchemeState(scheme, **kw)
+    per_it = products_per_iteration(scheme)
+    prods = 0
+    for _ in range(max_iter):
+        if st.bound() <= acc:
+            return prods
+        branch, alpha = st.choose()
+        st.advance(branch, alpha)
+        prods += per_it
+    raise RuntimeError("did not reach the requested accuracy")
