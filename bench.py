@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Time-to-solution of scale-and-fold purification vs the trace-correcting scheme on MI355X.
+
+One step = one complete purification D = theta(mu I - F) of the two-orbital cubic
+tight-binding lattice with 16x16x8 sites (n = 4096, half filling) in FP64, from f_0 through
+the product that certifies ||X^2 - X||_F <= 1e-8, with F already resident in HBM.  The timed
+scheme is the varying-mu scale-and-fold scheme (Algorithm 2); the unscaled trace-correcting
+scheme (x^2 / 2x - x^2 chosen by the trace) is timed the same way beside it.
+
+Prints one JSON line.  Extra keys:
+  roofline      dominant kernel (the FP64 MFMA X.X product) against the FP64 MFMA peak;
+                algorithmic flops n^2 (n + 1) per product (the symmetric product needs only
+                the upper triangle), average product-kernel duration from HIP events recorded
+                on the library's stream over the timed solves;
+  cpu_baseline  the FP64 CPU oracle (numpy) on the same workload, one solve, host cores.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("time-to-solution ms at ‖X²−X‖≤1e-8, SnF vs SP2; "
+          "X·X TFLOP/s & GB/s")
+PEAK_FP64_TFLOPS = 78.6
+TOL = 1e-8
+LATTICE = (16, 16, 8)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xx_f64_lattice_n4096_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels_dense.hip", "snf_internal.h", "schedule_math.h"):
+        with open(os.path.join(ROOT, "paper_1101_0265_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(n_products_per_launch: int = 1):
+    """HBM bytes per product launch from the committed rocprofv3 counter summary, or None
+    if it was taken on a different version of the kernels."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(h, kw):
+    import numpy as np
+    from oracle import dense
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 1) for i in threadpool_info()
+                       if i.get("user_api") == "blas"), default=os.cpu_count())
+    except Exception:  # noqa: BLE001
+        threads = os.cpu_count()
+    t0 = time.perf_counter()
+    r = dense.purify(h.F, "snf_varmu", **kw)
+    dt = time.perf_counter() - t0
+    return dict(value=round(dt * 1e3, 1), unit="ms", cores=int(threads), kind="oracle",
+                sample=("one full solve of the same workload (n=4096 lattice, SnF varying-mu, "
+                        f"FP64 numpy, {r['products']} method products; the oracle also forms "
+                        "X^2 separately for its check)"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the method's "
+              "multi-GPU layout is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1101_0265_amd import hamiltonians as H
+    from paper_1101_0265_amd import snf
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    snf.lib()
+    dev = torch.device("cuda:0")
+    h = H.lattice_hamiltonian(LATTICE, seed=2)
+    n = h.n
+    F = torch.tensor(h.F, device=dev)
+    D = torch.empty_like(F)
+    kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
+              lumo=h.lumo, mu=h.mu, xi=h.xi, tol=TOL, max_iter=200)
+
+    def solve(scheme, flags=0):
+        _, r = snf.purify_dense(F, scheme, out=D, want_log=False, flags=flags, **kw)
+        if r["status"] != "ok":
+            raise RuntimeError(f"{scheme}: {r['status']}")
+        return r
+
+    for _ in range(args.warmup):
+        solve("snf_varmu")
+        solve("sp2")
+
+    def timed(scheme):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = [solve(scheme, flags=snf.FLAG_TIME_PRODUCTS) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps, rs
+
+    snf_ms, snf_rs = timed("snf_varmu")
+    sp2_ms, sp2_rs = timed("sp2")
+
+    flops_per_product = float(n) * n * (n + 1)
+    prod_ms = sum(r["product_ms"] for r in snf_rs + sp2_rs)
+    prods = sum(r["products"] for r in snf_rs + sp2_rs)
+    avg_launch_ms = prod_ms / prods
+    achieved = flops_per_product / (avg_launch_ms * 1e-3) / 1e12
+    traffic = load_traffic()
+    roofline = dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_FP64_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / PEAK_FP64_TFLOPS, 4),
+                    traffic=traffic, kernel="product_kernel<double> (f64 MFMA, 128x128 tiles)",
+                    avg_launch_ms=round(avg_launch_ms, 4),
+                    flops_per_launch=flops_per_product)
+    # HBM bytes an ideal product must move: read X (operand) once, write X_new, read the
+    # linear term X again in the epilogue: 3 n^2 * 8 B.
+    algo_bytes = 3.0 * n * n * 8
+    line = {
+        "metric": METRIC,
+        "value": round(snf_ms, 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(snf_ms, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dense FP64 two-orbital lattice 16x16x8 sites, n=4096, "
+                               "half filling, tol 1e-8",
+                   "scheme": "snf_varmu", "n": n, "n_occ": h.n_occ, "tol": TOL,
+                   "gap": round(h.lumo - h.homo, 6)},
+        "sp2_ms": round(sp2_ms, 3),
+        "speedup_vs_sp2": round(sp2_ms / snf_ms, 3),
+        "products": {"snf_varmu": snf_rs[0]["products"], "sp2": sp2_rs[0]["products"]},
+        "xx_tflops_fp64": round(achieved, 2),
+        "xx_algorithmic_gbps": round(algo_bytes / (avg_launch_ms * 1e-3) / 1e9, 1),
+        "idem_err": snf_rs[0]["idem_err"],
+        "trace_err": snf_rs[0]["trace_err"],
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(h, kw)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

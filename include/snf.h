@@ -1,0 +1,190 @@
+/*
+ * snf.h -- C ABI of the scale-and-fold density-matrix purification library for MI355X.
+ *
+ * The library computes the density matrix D = theta(mu I - F) of a symmetric effective
+ * Hamiltonian F (the problem statement in the introduction of Rubensson,
+ * arXiv:1101.0265) by recursive purification, Eq. 1:
+ *     X_0 = f_0(F),   X_i = f_i(X_{i-1}),  i = 1, 2, ...
+ * where f_0 is linear and every f_i costs one matrix-matrix product X.X (two for
+ * Algorithm 1).  Five schemes are offered:
+ *
+ *   SNF_SP2_TRACE   second-order trace-correcting purification, x^2 / 2x - x^2 chosen from
+ *                   the trace of X (the unscaled scheme the paper compares against).
+ *   SNF_TC2_BETA    Algorithm 2 with alpha = 0: same polynomials, chosen from the images
+ *                   beta / beta-bar of the gap edges.
+ *   SNF_SNF_VARMU   Algorithm 2: varying-mu scale-and-fold, Eqs. 4 and 5.
+ *   SNF_MCWEENY     Algorithm 1 with alpha = 1: regular grand-canonical McWeeny.
+ *   SNF_SNF_FIXMU   Algorithm 1: McWeeny-based fixed-mu scale-and-fold, Eqs. 2 and 3.
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are row-major FP64.  Only the upper triangle of F (j >= i) is read; the
+ *    lower triangle is taken as its mirror, so F is symmetric by construction.
+ *  - Device pointers are HIP device allocations on the current device (torch tensors on
+ *    cuda:N are fine).  The library never frees or retains caller memory.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  All work is enqueued
+ *    on it; calls that return results return after that work has completed.
+ *  - The library owns a per-device workspace (padded copies of X, partial sums, the
+ *    scalar state).  It grows on demand and is reused; calls that overlap in time on the
+ *    same device from different host threads are serialised by an internal lock.
+ *  - Return value: one of the SNF_* status codes below.  Negative = error, the outputs are
+ *    then unspecified (except snf_result.status); snf_strerror() gives a message, and for
+ *    SNF_EDEVICE the text of the last HIP error.
+ */
+#ifndef SNF_H
+#define SNF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------------------------- */
+#define SNF_OK          0   /* converged: ||X^2 - X||_F <= tol                                */
+#define SNF_PENDING     1   /* serving: request not finished yet                              */
+#define SNF_OK_FLOOR    2   /* stopped on stagnation above tol (precision/truncation floor)  */
+#define SNF_EINVAL     -1   /* bad argument: null pointer, n <= 0, inconsistent bounds ...    */
+#define SNF_ENOMEM     -2   /* device allocation failed / over the memory budget             */
+#define SNF_ENOCONV    -3   /* max_iter iterations without reaching tol                       */
+#define SNF_ENONFINITE -4   /* a non-finite value appeared in X (bad input or bounds)         */
+#define SNF_EMIXED     -5   /* converged, but |tr D - n_occ| >= 0.5: states were mixed        */
+#define SNF_EDEVICE    -6   /* a HIP runtime call failed                                      */
+
+/* ---- schemes and precision modes ------------------------------------------------------- */
+typedef enum {
+  SNF_SP2_TRACE = 0,
+  SNF_TC2_BETA = 1,
+  SNF_SNF_VARMU = 2,
+  SNF_MCWEENY = 3,
+  SNF_SNF_FIXMU = 4
+} snf_scheme;
+
+typedef enum {
+  SNF_P_FP64 = 0,        /* every product in FP64 (MFMA f64)                                   */
+  SNF_P_FP32 = 1,        /* FP32 products (MFMA f32) after the FP64 phase, no refinement      */
+  SNF_P_FP32_REF64 = 2,  /* FP64 phase, FP32 products, then FP64 refinement to tol             */
+  SNF_P_BF16_REF64 = 3   /* FP64 phase, BF16-input/FP32-accumulate products, FP64 refinement  */
+} snf_precision;
+
+/* Branch letters recorded per iteration. */
+#define SNF_BRANCH_SQUARE 0   /* P_{1,0}: X <- ((1+a) X - a I)^2           (Eq. 4)          */
+#define SNF_BRANCH_FOLD   1   /* P_{0,1}: X <- 2 (1+a) X - (1+a)^2 X^2      (Eq. 5)          */
+#define SNF_BRANCH_P11    2   /* P_{1,1}: X <- 3 Xs^2 - 2 Xs^3, Xs = a (X - I/2) + I/2 (Eq. 2) */
+
+/* Flags (snf_params.flags). */
+#define SNF_FLAG_TIME_PRODUCTS 1  /* bracket every product kernel with HIP events and report
+                                     their summed duration in snf_result.product_ms         */
+
+/*
+ * Inputs of a purification (Algorithm 1 needs lambda_min, lambda_max, mu, xi; Algorithm 2
+ * and its alpha = 0 form need lambda_min, lambda_max, homo, lumo; the trace scheme needs
+ * lambda_min, lambda_max, n_occ).
+ *  lambda_min/lambda_max: bounds of the whole spectrum of F (lambda_min <= eig <= lambda_max).
+ *  homo/lumo: a lower bound of the highest occupied eigenvalue and an upper bound of the
+ *             lowest unoccupied one (the gap-edge bounds the scale-and-fold scheme needs).
+ *  mu, xi:    chemical potential and band gap for the fixed-mu schemes; the gap is taken
+ *             as symmetric about mu.
+ *  n_occ:     number of occupied states; -1 if unknown (then no trace check is made;
+ *             invalid for SNF_SP2_TRACE).
+ *  tol:       stop when ||X_{i-1}^2 - X_{i-1}||_F <= tol; D = X_{i-1}.
+ *  max_iter:  at most this many f_i (1..SNF_LOG_MAX-1).
+ *  gap_switch: precision modes: products stay FP64 while the X-space gap
+ *             (beta-bar - beta) is below this value (0 = low precision from the start).
+ *  lowp_floor: precision modes: leave the low-precision phase once the a-priori
+ *             eigenvalue error max(beta, 1 - beta-bar) is below this value (0 = default
+ *             1e-4 for FP32, 1e-2 for BF16).
+ *  flags:     SNF_FLAG_* bits.
+ */
+typedef struct {
+  double lambda_min, lambda_max;
+  double mu, xi;
+  double homo, lumo;
+  int64_t n_occ;
+  double tol;
+  int32_t max_iter;
+  int32_t flags;
+  double gap_switch;
+  double lowp_floor;
+} snf_params;
+
+#define SNF_LOG_MAX 256
+
+/* One record per iteration i = 0 .. iterations (the last one is the certifying product). */
+typedef struct {
+  int32_t i;          /* iteration index: X_i was the input of this product                */
+  int32_t branch;     /* SNF_BRANCH_* applied to X_i (-1 for the last, certifying record)  */
+  int32_t precision;  /* 0 FP64, 1 FP32, 2 BF16 product for X_i^2                          */
+  int32_t reserved;
+  double alpha;       /* scaling parameter of the step                                     */
+  double beta;        /* image of the lumo bound in X_i                                     */
+  double betabar;     /* image of the homo bound in X_i                                     */
+  double e;           /* ||X_i^2 - X_i||_F                                                   */
+  double t1;          /* tr X_i                                                              */
+  double t2;          /* ||X_i||_F^2 = tr X_i^2                                              */
+} snf_log_rec;
+
+typedef struct {
+  int32_t status;         /* mirrors the return code                                    */
+  int32_t iterations;     /* f_i applied; D = X_iterations                              */
+  int32_t products;       /* matrix-matrix products, the certifying one included        */
+  int32_t products_fp64;  /* ... of which FP64                                          */
+  int32_t products_lowp;  /* ... of which FP32 or BF16                                  */
+  int32_t reserved;
+  double idem_err;        /* ||D^2 - D||_F (from the certifying product)                */
+  double trace;           /* tr D                                                       */
+  double trace_err;       /* tr D - n_occ (0 if n_occ unknown)                          */
+  double alpha_last, beta_last, betabar_last;
+  double device_ms;       /* f_0 through the copy-out of D, HIP events on `stream`      */
+  double product_ms;      /* summed product-kernel time (SNF_FLAG_TIME_PRODUCTS)        */
+  uint8_t branch[SNF_LOG_MAX]; /* SNF_BRANCH_* of iteration i                            */
+} snf_result;
+
+/*
+ * snf_purify_dense -- purify a dense symmetric F (Eq. 1 with the chosen scheme).
+ *   F_dev:  n x n FP64, row stride ld (elements), device, read-only, upper triangle used.
+ *   D_dev:  n x n FP64 output, row stride ld, device; must not alias F_dev.
+ *   n >= 1, ld >= n.
+ *   log/log_cap: optional (may be NULL/0) host array receiving min(iterations+1, log_cap)
+ *           snf_log_rec records.
+ *   out:    host struct, filled on return (required).
+ * Synchronous: returns after D and the result are complete.
+ */
+int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_params* params,
+                     snf_scheme scheme, snf_precision precision, double* D_dev,
+                     snf_result* out, snf_log_rec* log, int32_t log_cap, void* stream);
+
+/*
+ * snf_step_dense -- one purification step on a dense symmetric X, the unit of work of the
+ * loop above (rows a2+a3 of the method: product and fused combination).
+ *   Computes P = A.B (A, B symmetric n x n FP64, row stride ld, device) and
+ *     Y = c2 P + c1 A + c0 I            (written to Y_dev, row stride ld)
+ *   and, in FP64, sums[0] = ||P - A||_F^2, sums[1] = tr Y, sums[2] = ||Y||_F^2
+ *   (host array of 3 doubles).  With A == B this is one f_i of Eqs. 4-5 and the
+ *   idempotency check of A.  precision: SNF_P_FP64 (f64 MFMA), SNF_P_FP32 (f32 MFMA on
+ *   FP32-rounded copies of A and B), SNF_P_BF16_REF64 (bf16 MFMA with FP32 accumulation on
+ *   BF16-rounded copies).  Y_dev must not alias A_dev or B_dev.  Synchronous.
+ *   kernel_ms (optional, may be NULL): duration of the product kernel (HIP events).
+ */
+int snf_step_dense(const double* A_dev, const double* B_dev, int64_t n, int64_t ld,
+                   double c2, double c1, double c0, snf_precision precision, double* Y_dev,
+                   double* sums, double* kernel_ms, void* stream);
+
+/* Bytes of device workspace snf_purify_dense needs for order n (allocated on demand). */
+size_t snf_workspace_bytes(int64_t n, snf_precision precision);
+
+/* Release the calling device's cached workspace (it is re-created on the next call). */
+int snf_release_workspace(void);
+
+/* Human-readable text of a status code (static storage; SNF_EDEVICE includes the last
+   HIP error string seen by this thread). */
+const char* snf_strerror(int status);
+
+/* Library version string "major.minor.patch". */
+const char* snf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNF_H */

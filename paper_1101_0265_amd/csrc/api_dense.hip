@@ -1,0 +1,458 @@
+// Host side of the dense C ABI: validation, workspace, the launch-ahead purification loop.
+//
+// The loop is driven from the host but decided on the device: every product step is the
+// pair (product kernel, schedule kernel); the schedule kernel writes the next step's
+// coefficients, buffer indices and precision into the device-resident state, and sets a
+// stop flag once ||X^2 - X||_F <= tol (or an error / iteration limit).  Kernels enqueued after
+// the stop exit immediately.  The host keeps two chunks of steps in flight and reads the
+// stop flag of the older chunk from pinned memory, so the GPU never waits for the host and
+// at most one chunk of empty launches follows convergence.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "schedule_math.h"
+#include "snf_internal.h"
+
+namespace snf {
+
+static thread_local char g_err_text[256];
+
+static int dev_error(hipError_t e, const char* what) {
+  snprintf(g_err_text, sizeof(g_err_text), "HIP error in %s: %s", what, hipGetErrorString(e));
+  return SNF_EDEVICE;
+}
+
+#define SNF_HIP(call)                                  \
+  do {                                                 \
+    hipError_t _e = (call);                            \
+    if (_e != hipSuccess) return dev_error(_e, #call); \
+  } while (0)
+
+static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// ---- per-device workspace -------------------------------------------------------------
+struct Workspace {
+  int64_t np = 0;          // padded order the buffers hold
+  int lp_bytes = 0;        // bytes per element of the low-precision copies (0, 2, 4)
+  double* x[3] = {nullptr, nullptr, nullptr};
+  void* lp[3] = {nullptr, nullptr, nullptr};
+  double* partials = nullptr;
+  int partial_cap = 0;
+  SnfState* state = nullptr;
+  Buffers* bufs_dev = nullptr;
+  SnfState* state_host = nullptr;    // pinned
+  int32_t* flags_host = nullptr;     // pinned, [2] stop flags of in-flight chunks
+  double* sums_dev = nullptr;
+  double* sums_host = nullptr;       // pinned
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> prod_ev;
+  std::mutex mu;
+};
+
+static std::mutex g_ws_mu;
+static Workspace* g_ws[64];
+
+static Workspace* workspace_for_current_device(int* dev_out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> g(g_ws_mu);
+  if (!g_ws[dev]) g_ws[dev] = new Workspace();
+  *dev_out = dev;
+  return g_ws[dev];
+}
+
+static void free_buffers(Workspace* w) {
+  for (int i = 0; i < 3; ++i) {
+    if (w->x[i]) (void)hipFree(w->x[i]);
+    if (w->lp[i]) (void)hipFree(w->lp[i]);
+    w->x[i] = nullptr;
+    w->lp[i] = nullptr;
+  }
+  w->np = 0;
+  w->lp_bytes = 0;
+}
+
+static int ensure_workspace(Workspace* w, int64_t np, int lp_bytes, int partial_need) {
+  if (!w->state) {
+    SNF_HIP(hipMalloc(&w->state, sizeof(SnfState)));
+    SNF_HIP(hipMalloc(&w->bufs_dev, sizeof(Buffers)));
+    SNF_HIP(hipHostMalloc(&w->state_host, sizeof(SnfState), hipHostMallocDefault));
+    SNF_HIP(hipHostMalloc(&w->flags_host, 8 * sizeof(int32_t), hipHostMallocDefault));
+    SNF_HIP(hipMalloc(&w->sums_dev, 4 * sizeof(double)));
+    SNF_HIP(hipHostMalloc(&w->sums_host, 4 * sizeof(double), hipHostMallocDefault));
+    for (int i = 0; i < 4; ++i) SNF_HIP(hipEventCreate(&w->ev[i]));
+  }
+  if (partial_need > w->partial_cap) {
+    if (w->partials) (void)hipFree(w->partials);
+    w->partials = nullptr;
+    const int cap = partial_need < kF0Blocks ? kF0Blocks : partial_need;
+    if (hipMalloc(&w->partials, (size_t)cap * 4 * sizeof(double)) != hipSuccess) {
+      w->partial_cap = 0;
+      (void)hipGetLastError();
+      return SNF_ENOMEM;
+    }
+    w->partial_cap = cap;
+  }
+  if (np > w->np || lp_bytes > w->lp_bytes) {
+    free_buffers(w);
+    const size_t elems = (size_t)np * (size_t)np;
+    for (int i = 0; i < 3; ++i) {
+      if (hipMalloc(&w->x[i], elems * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        free_buffers(w);
+        return SNF_ENOMEM;
+      }
+      if (lp_bytes && hipMalloc(&w->lp[i], elems * lp_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        free_buffers(w);
+        return SNF_ENOMEM;
+      }
+    }
+    w->np = np;
+    w->lp_bytes = lp_bytes;
+  }
+  return SNF_OK;
+}
+
+static int lowp_bytes_for(snf_precision p) {
+  switch (p) {
+    case SNF_P_FP32:
+    case SNF_P_FP32_REF64: return 4;
+    case SNF_P_BF16_REF64: return 2;
+    default: return 0;
+  }
+}
+
+static int lowp_kind_for(snf_precision p) {
+  switch (p) {
+    case SNF_P_FP32:
+    case SNF_P_FP32_REF64: return kPrecF32;
+    case SNF_P_BF16_REF64: return kPrecBF16;
+    default: return -1;
+  }
+}
+
+// Buffers of the internal loop are the workspace buffers, but their padded order can be
+// larger than this call needs; the kernels use the call's np with the same base pointers,
+// so a buffer of order w->np serves any np <= w->np.
+static int upload_buffers(Workspace* w, hipStream_t s) {
+  Buffers b;
+  for (int i = 0; i < 3; ++i) {
+    b.x[i] = w->x[i];
+    b.lp[i] = w->lp[i];
+  }
+  SNF_HIP(hipMemcpyAsync(w->bufs_dev, &b, sizeof(b), hipMemcpyHostToDevice, s));
+  return SNF_OK;
+}
+
+// ---- validation -------------------------------------------------------------------------
+static bool finite(double v) { return isfinite(v) != 0; }
+
+static int validate(int64_t n, const snf_params* p, snf_scheme scheme, snf_precision prec) {
+  if (!p || n <= 0) return SNF_EINVAL;
+  if ((int)scheme < SNF_SP2_TRACE || (int)scheme > SNF_SNF_FIXMU) return SNF_EINVAL;
+  if ((int)prec < SNF_P_FP64 || (int)prec > SNF_P_BF16_REF64) return SNF_EINVAL;
+  if (!finite(p->lambda_min) || !finite(p->lambda_max) || !(p->lambda_min < p->lambda_max))
+    return SNF_EINVAL;
+  if (!(p->tol > 0.0) || !finite(p->tol)) return SNF_EINVAL;
+  if (p->max_iter < 1 || p->max_iter >= SNF_LOG_MAX) return SNF_EINVAL;
+  if (p->n_occ >= 0 && p->n_occ > n) return SNF_EINVAL;
+  const bool gap_edges = finite(p->homo) && finite(p->lumo) && p->homo < p->lumo &&
+                         p->lambda_min <= p->homo && p->lumo <= p->lambda_max;
+  switch (scheme) {
+    case SNF_SP2_TRACE:
+      if (p->n_occ < 0) return SNF_EINVAL;
+      if (prec != SNF_P_FP64 && !gap_edges) return SNF_EINVAL;
+      break;
+    case SNF_TC2_BETA:
+    case SNF_SNF_VARMU:
+      if (!gap_edges) return SNF_EINVAL;
+      break;
+    case SNF_MCWEENY:
+    case SNF_SNF_FIXMU:
+      if (!finite(p->mu) || !finite(p->xi) || !(p->mu > p->lambda_min) ||
+          !(p->mu < p->lambda_max) || !(p->xi > 0.0))
+        return SNF_EINVAL;
+      if (!(p->xi < sched::alg1_gamma(p->lambda_min, p->lambda_max, p->mu))) return SNF_EINVAL;
+      break;
+  }
+  if (prec != SNF_P_FP64) {
+    if (!finite(p->gap_switch) || p->gap_switch < 0.0 || p->gap_switch > 1.0) return SNF_EINVAL;
+    if (!finite(p->lowp_floor) || p->lowp_floor < 0.0 || p->lowp_floor >= 0.5) return SNF_EINVAL;
+  }
+  return SNF_OK;
+}
+
+static void init_state(SnfState* s, int64_t n, const snf_params* p, snf_scheme scheme,
+                       snf_precision prec) {
+  memset(s, 0, sizeof(*s));
+  s->scheme = scheme;
+  s->max_iter = p->max_iter;
+  s->mode = prec;
+  s->has_nocc = p->n_occ >= 0;
+  s->n = n;
+  s->n_occ = p->n_occ;
+  s->tol = p->tol;
+  s->lambda_min = p->lambda_min;
+  s->lambda_max = p->lambda_max;
+  s->mu = p->mu;
+  s->xi = p->xi;
+  s->homo = p->homo;
+  s->lumo = p->lumo;
+  s->gap_switch = p->gap_switch;
+  s->lowp_floor = p->lowp_floor > 0.0 ? p->lowp_floor : (prec == SNF_P_BF16_REF64 ? 1e-2 : 1e-4);
+  if (scheme == SNF_MCWEENY || scheme == SNF_SNF_FIXMU) {
+    s->gamma = sched::alg1_gamma(p->lambda_min, p->lambda_max, p->mu);
+    s->beta = sched::alg1_beta0(p->xi, s->gamma);
+    s->betabar = 1.0 - s->beta;
+  } else {
+    const bool edges = isfinite(p->homo) && isfinite(p->lumo);
+    s->beta = edges ? sched::alg2_f0(p->lumo, p->lambda_min, p->lambda_max) : 0.0;
+    s->betabar = edges ? sched::alg2_f0(p->homo, p->lambda_min, p->lambda_max) : 1.0;
+  }
+  s->phase = kPhaseHigh;
+  s->cur = 0;
+  s->e_hist[0] = s->e_hist[1] = s->e_hist[2] = INFINITY;
+}
+
+static void fill_result(const SnfState* s, snf_result* out, snf_log_rec* log, int log_cap) {
+  memset(out, 0, sizeof(*out));
+  out->status = s->status;
+  out->iterations = s->iter;
+  out->products = s->products;
+  out->products_fp64 = s->products_f64;
+  out->products_lowp = s->products_lowp;
+  out->idem_err = s->e_last;
+  out->trace = s->t1;
+  out->trace_err = s->has_nocc ? s->t1 - (double)s->n_occ : 0.0;
+  out->alpha_last = s->alpha;
+  out->beta_last = s->beta;
+  out->betabar_last = s->betabar;
+  const int nrec = s->nlog < SNF_LOG_MAX ? s->nlog : SNF_LOG_MAX;
+  for (int i = 0; i < nrec && i < SNF_LOG_MAX; ++i)
+    out->branch[i] = (uint8_t)(s->log[i].branch < 0 ? 255 : s->log[i].branch);
+  if (log && log_cap > 0) {
+    const int m = nrec < log_cap ? nrec : log_cap;
+    memcpy(log, s->log, (size_t)m * sizeof(snf_log_rec));
+  }
+}
+
+}  // namespace snf
+
+using namespace snf;
+
+extern "C" {
+
+const char* snf_version(void) { return "0.1.0"; }
+
+const char* snf_strerror(int status) {
+  switch (status) {
+    case SNF_OK: return "converged";
+    case SNF_PENDING: return "pending";
+    case SNF_OK_FLOOR: return "stopped at the precision/truncation floor above tol";
+    case SNF_EINVAL: return "invalid argument";
+    case SNF_ENOMEM: return "out of device memory or over the memory budget";
+    case SNF_ENOCONV: return "no convergence within max_iter";
+    case SNF_ENONFINITE: return "non-finite value in the iteration";
+    case SNF_EMIXED: return "converged to a projector with the wrong occupation";
+    case SNF_EDEVICE: return g_err_text[0] ? g_err_text : "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+size_t snf_workspace_bytes(int64_t n, snf_precision precision) {
+  if (n <= 0) return 0;
+  const int64_t np = round_up(n, kTile);
+  const size_t elems = (size_t)np * (size_t)np;
+  return elems * (3 * sizeof(double) + 3 * (size_t)lowp_bytes_for(precision)) +
+         (size_t)(num_product_tiles(np, 1) + kF0Blocks) * 4 * sizeof(double) + sizeof(SnfState);
+}
+
+int snf_release_workspace(void) {
+  int dev = 0;
+  Workspace* w = workspace_for_current_device(&dev);
+  if (!w) return SNF_EDEVICE;
+  std::lock_guard<std::mutex> g(w->mu);
+  free_buffers(w);
+  if (w->partials) (void)hipFree(w->partials);
+  w->partials = nullptr;
+  w->partial_cap = 0;
+  return SNF_OK;
+}
+
+int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_params* params,
+                     snf_scheme scheme, snf_precision precision, double* D_dev,
+                     snf_result* out, snf_log_rec* log, int32_t log_cap, void* stream) {
+  if (!out) return SNF_EINVAL;
+  memset(out, 0, sizeof(*out));
+  int rc = validate(n, params, scheme, precision);
+  if (rc == SNF_OK && (!F_dev || !D_dev || ld < n || (const void*)F_dev == (const void*)D_dev))
+    rc = SNF_EINVAL;
+  if (rc != SNF_OK) {
+    out->status = rc;
+    return rc;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  Workspace* w = workspace_for_current_device(&dev);
+  if (!w) {
+    out->status = SNF_EDEVICE;
+    return SNF_EDEVICE;
+  }
+  std::lock_guard<std::mutex> guard(w->mu);
+  const int64_t np = round_up(n, kTile);
+  const int sym = 1;
+  const int tiles = num_product_tiles(np, sym);
+  rc = ensure_workspace(w, np, lowp_bytes_for(precision), tiles);
+  if (rc != SNF_OK) {
+    out->status = rc;
+    return rc;
+  }
+  // A workspace of larger order is used with this call's np: the kernels index rows with
+  // np, so every buffer just needs np*np elements.
+  init_state(w->state_host, n, params, scheme, precision);
+  const bool time_products = (params->flags & SNF_FLAG_TIME_PRODUCTS) != 0;
+  const int per_it = (scheme == SNF_MCWEENY || scheme == SNF_SNF_FIXMU) ? 2 : 1;
+  const int max_steps = (params->max_iter + 1) * (per_it > 1 ? 2 : 1) + 1;
+  if (time_products && (int)w->prod_ev.size() < 2 * max_steps) {
+    const size_t old = w->prod_ev.size();
+    w->prod_ev.resize(2 * max_steps);
+    for (size_t i = old; i < w->prod_ev.size(); ++i) SNF_HIP(hipEventCreate(&w->prod_ev[i]));
+  }
+
+  rc = upload_buffers(w, s);
+  if (rc != SNF_OK) return out->status = rc;
+  SNF_HIP(hipMemcpyAsync(w->state, w->state_host, sizeof(SnfState), hipMemcpyHostToDevice, s));
+  SNF_HIP(hipEventRecord(w->ev[0], s));
+  launch_f0(F_dev, n, ld, np, w->state, w->bufs_dev, lowp_kind_for(precision), w->partials, s);
+  launch_schedule(w->state, w->partials, kF0Blocks, 1, s);
+  SNF_HIP(hipGetLastError());
+
+  // Launch-ahead loop: chunks of `chunk` steps, two chunks in flight.
+  const int chunk = np >= 2048 ? 2 : (np >= 1024 ? 4 : 8);
+  const bool lowp = precision != SNF_P_FP64;
+  int enq = 0, chunks = 0, checked = 0;
+  int ev_used = 0;
+  bool stopped = false;
+  volatile int32_t* flags = w->flags_host;
+  auto enqueue_chunk = [&]() -> int {
+    for (int k = 0; k < chunk && enq < max_steps; ++k, ++enq) {
+      if (time_products) SNF_HIP(hipEventRecord(w->prod_ev[ev_used], s));
+      launch_product(kPrecF64, w->state, w->bufs_dev, np, n, w->partials, sym, s);
+      if (lowp) launch_product(lowp_kind_for(precision), w->state, w->bufs_dev, np, n,
+                               w->partials, sym, s);
+      if (time_products) SNF_HIP(hipEventRecord(w->prod_ev[ev_used + 1], s));
+      if (time_products) ev_used += 2;
+      launch_schedule(w->state, w->partials, tiles, 0, s);
+    }
+    SNF_HIP(hipGetLastError());
+    SNF_HIP(hipMemcpyAsync((void*)(flags + (chunks & 1)), &w->state->stop, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+    SNF_HIP(hipEventRecord(w->ev[2 + (chunks & 1)], s));
+    ++chunks;
+    return SNF_OK;
+  };
+  rc = enqueue_chunk();
+  if (rc != SNF_OK) return out->status = rc;
+  while (!stopped && enq < max_steps) {
+    rc = enqueue_chunk();
+    if (rc != SNF_OK) return out->status = rc;
+    // wait for the older in-flight chunk and look at its stop flag
+    SNF_HIP(hipEventSynchronize(w->ev[2 + (checked & 1)]));
+    stopped = flags[checked & 1] != 0;
+    ++checked;
+  }
+  launch_copy_out(w->state, w->bufs_dev, n, np, D_dev, ld, s);
+  SNF_HIP(hipGetLastError());
+  SNF_HIP(hipEventRecord(w->ev[1], s));
+  SNF_HIP(hipMemcpyAsync(w->state_host, w->state, sizeof(SnfState), hipMemcpyDeviceToHost, s));
+  SNF_HIP(hipStreamSynchronize(s));
+
+  const SnfState* st = w->state_host;
+  int status = st->stop ? st->status : SNF_ENOCONV;
+  fill_result(st, out, log, log_cap);
+  out->status = status;
+  float ms = 0.f;
+  SNF_HIP(hipEventElapsedTime(&ms, w->ev[0], w->ev[1]));
+  out->device_ms = ms;
+  if (time_products) {
+    // step k of the loop ran the k-th product; steps after the stop were empty launches
+    double tot = 0.0;
+    const int real = st->products;
+    for (int k = 0; k < real && 2 * k + 1 < ev_used; ++k) {
+      float m = 0.f;
+      SNF_HIP(hipEventElapsedTime(&m, w->prod_ev[2 * k], w->prod_ev[2 * k + 1]));
+      tot += m;
+    }
+    out->product_ms = tot;
+  }
+  return status;
+}
+
+int snf_step_dense(const double* A_dev, const double* B_dev, int64_t n, int64_t ld, double c2,
+                   double c1, double c0, snf_precision precision, double* Y_dev, double* sums,
+                   double* kernel_ms, void* stream) {
+  if (!A_dev || !B_dev || !Y_dev || !sums || n <= 0 || ld < n) return SNF_EINVAL;
+  if (precision != SNF_P_FP64 && precision != SNF_P_FP32 && precision != SNF_P_BF16_REF64)
+    return SNF_EINVAL;
+  if ((const void*)Y_dev == (const void*)A_dev || (const void*)Y_dev == (const void*)B_dev)
+    return SNF_EINVAL;
+  if (!isfinite(c2) || !isfinite(c1) || !isfinite(c0)) return SNF_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  Workspace* w = workspace_for_current_device(&dev);
+  if (!w) return SNF_EDEVICE;
+  std::lock_guard<std::mutex> guard(w->mu);
+  const int64_t np = round_up(n, kTile);
+  const int sym = 1;
+  const int tiles = num_product_tiles(np, sym);
+  int rc = ensure_workspace(w, np, lowp_bytes_for(precision == SNF_P_FP32 ? SNF_P_FP32
+                                                  : precision), tiles);
+  if (rc != SNF_OK) return rc;
+  const int lk = lowp_kind_for(precision);
+  rc = upload_buffers(w, s);
+  if (rc != SNF_OK) return rc;
+  SnfState* sh = w->state_host;
+  memset(sh, 0, sizeof(*sh));
+  sh->mode = precision;
+  sh->n = n;
+  sh->prec = lk < 0 ? kPrecF64 : lk;
+  sh->c2 = c2;
+  sh->c1 = c1;
+  sh->c0 = c0;
+  sh->kind = kKindSquare;
+  sh->want_e = 1;
+  sh->ia = 0;
+  sh->ib = 1;
+  sh->ix = 0;
+  sh->io = 2;
+  sh->write_lowp = 0;
+  SNF_HIP(hipMemcpyAsync(w->state, sh, sizeof(SnfState), hipMemcpyHostToDevice, s));
+  launch_pad_copy(A_dev, n, ld, w->x[0], np, w->lp[0], lk, s);
+  launch_pad_copy(B_dev, n, ld, w->x[1], np, w->lp[1], lk, s);
+  SNF_HIP(hipEventRecord(w->ev[0], s));
+  launch_product(sh->prec, w->state, w->bufs_dev, np, n, w->partials, sym, s);
+  SNF_HIP(hipEventRecord(w->ev[1], s));
+  launch_sum_partials(w->partials, tiles, w->sums_dev, s);
+  launch_unpad_copy(w->x[2], np, n, Y_dev, ld, s);
+  SNF_HIP(hipGetLastError());
+  SNF_HIP(hipMemcpyAsync(w->sums_host, w->sums_dev, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  SNF_HIP(hipStreamSynchronize(s));
+  sums[0] = w->sums_host[0];
+  sums[1] = w->sums_host[1];
+  sums[2] = w->sums_host[2];
+  if (kernel_ms) {
+    float ms = 0.f;
+    SNF_HIP(hipEventElapsedTime(&ms, w->ev[0], w->ev[1]));
+    *kernel_ms = ms;
+  }
+  return SNF_OK;
+}
+
+}  // extern "C"

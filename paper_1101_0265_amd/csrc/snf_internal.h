@@ -1,0 +1,92 @@
+// Internal declarations shared by the HIP translation units of libsnf (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/snf.h"
+
+namespace snf {
+
+// Output tile of one workgroup of the dense product kernels, and the padding unit of
+// every internal n x n buffer (so the product main loop needs no bounds checks).
+constexpr int kTile = 128;
+constexpr int kThreads = 256;        // 4 waves of 64, arranged 2 x 2 over the tile
+constexpr int kF0Blocks = 1024;      // fixed grid of the f0 / conversion kernels
+constexpr int kReduceThreads = 256;
+
+// Precision of a product.
+enum : int32_t { kPrecF64 = 0, kPrecF32 = 1, kPrecBF16 = 2 };
+
+// Phase of the precision schedule.
+enum : int32_t { kPhaseHigh = 0, kPhaseLow = 1, kPhaseRefine = 2 };
+
+// Kind of the pending product.
+enum : int32_t {
+  kKindSquare = 0,   // P = X.X, epilogue Y = c2 P + c1 X + c0 I, idempotency of X checked
+  kKindCube = 1      // Algorithm 1 second product: R = S2.X, Y = c2 R + c1 S2
+};
+
+// Scalar state of one purification, resident in device memory.  Written by the host
+// once (configuration), then only by the schedule kernel (one thread).
+struct SnfState {
+  // ---- configuration ----
+  int32_t scheme;
+  int32_t max_iter;
+  int32_t mode;          // snf_precision
+  int32_t has_nocc;
+  int64_t n;
+  int64_t n_occ;
+  double tol, lambda_min, lambda_max, mu, xi, homo, lumo;
+  double gap_switch, lowp_floor;
+  // ---- evolving ----
+  double beta, betabar, gamma;
+  double t1, t2;          // tr X_cur, ||X_cur||_F^2
+  double alpha;           // alpha of the pending iteration
+  double c2, c1, c0;      // epilogue coefficients of the pending product
+  double e_last;
+  double e_hist[3];       // idempotency of the last three iterates (stagnation test)
+  int32_t iter;           // f_i applied; X_cur = X_iter
+  int32_t products, products_f64, products_lowp;
+  int32_t kind;           // kKind* of the pending product
+  int32_t branch;         // SNF_BRANCH_* of the pending iteration
+  int32_t prec;           // kPrec* of the pending product
+  int32_t phase;          // kPhase*
+  int32_t stop;           // 0 while running; else 1 + index into the status table below
+  int32_t status;         // final snf status code once stop != 0
+  int32_t cur;            // buffer index holding X_cur
+  int32_t ia, ib, ix, io; // operand / linear-term / output buffer indices of the pending product
+  int32_t want_e;         // pending product checks idempotency of its A operand
+  int32_t write_lowp;     // epilogue also writes the low-precision operand copy
+  int32_t nlog;
+  snf_log_rec log[SNF_LOG_MAX];
+};
+
+// Buffers of one purification: three FP64 n_pad x n_pad matrices and, for precision modes,
+// their low-precision operand copies (FP32 or BF16, same indices).
+struct Buffers {
+  double* x[3];
+  void* lp[3];
+};
+
+// ---- kernels launched by the host drivers (defined in kernels_dense.hip) ----------------
+void launch_f0(const double* F, int64_t n, int64_t ld, int64_t np, SnfState* st,
+               const Buffers* bufs_dev, int lowp_kind, double* partials, hipStream_t s);
+void launch_schedule(SnfState* st, const double* partials, int count, int init,
+                     hipStream_t s);
+// Product of the pending step; each variant exits at once unless the state asks for its
+// precision (so the host can enqueue all variants without knowing the device's choice).
+void launch_product(int prec, SnfState* st, const Buffers* bufs_dev, int64_t np, int64_t n,
+                    double* partials, int sym, hipStream_t s);
+void launch_copy_out(const SnfState* st, const Buffers* bufs_dev, int64_t n, int64_t np,
+                     double* D, int64_t ld, hipStream_t s);
+// Padded copy helpers for the stand-alone step.
+void launch_pad_copy(const double* src, int64_t n, int64_t ld, double* dst, int64_t np,
+                     void* lp_dst, int lowp_kind, hipStream_t s);
+void launch_unpad_copy(const double* src, int64_t np, int64_t n, double* dst, int64_t ld,
+                       hipStream_t s);
+void launch_sum_partials(const double* partials, int count, double* out3, hipStream_t s);
+
+int num_product_tiles(int64_t np, int sym);
+
+}  // namespace snf

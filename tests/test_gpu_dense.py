@@ -1,0 +1,284 @@
+"""GPU parity of the dense path (C ABI through the ctypes binding) against the CPU oracle.
+
+Bars:
+* integer / decision outputs (branch sequence, product count, status) -- identical to the
+  oracle; for the trace-based scheme a differing decision is accepted only at an FP64 near-tie
+  (|margin| <= 1e3 * u * n), after which the oracle is re-run forced onto the GPU's choice;
+* FP64 mode: ||D_gpu - D_oracle||_F <= 1e-8 sqrt(n) (the stated parity tolerance) and the same
+  bound against the exact projector;
+* single steps: the elementwise forward error bound of a length-n dot product,
+  (n + 2) u (|A| |B|)_ij, with u the unit roundoff of the operand / accumulation precision.
+"""
+import ctypes
+import functools
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import dense, exact, spectral  # noqa: E402
+from paper_1101_0265_amd import hamiltonians as H  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SCHEMES = ("sp2", "tc2", "snf_varmu", "mcweeny", "snf_fixmu")
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def snf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1101_0265_amd import snf as s
+    s.lib()
+    return s
+
+
+def _kw(h, tol=1e-10, max_iter=120):
+    return dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ,
+                homo=h.homo, lumo=h.lumo, mu=h.mu, xi=h.xi, tol=tol, max_iter=max_iter)
+
+
+def _dev(a):
+    return torch.tensor(a, device="cuda:0", dtype=torch.float64)
+
+
+def _compare_to_oracle(snf, h, scheme, tol=1e-10, F_oracle=None):
+    """Run GPU and oracle; check decisions, counts, per-iteration sums and D."""
+    kw = _kw(h, tol=tol)
+    D, r = snf.purify_dense(_dev(h.F), scheme, **kw)
+    o = dense.purify(h.F if F_oracle is None else F_oracle, scheme, **kw)
+    n = h.n
+    if scheme == "sp2" and r["branches"] != o["branches"]:
+        k = next(i for i, (a, b) in enumerate(zip(r["branches"], o["branches"])) if a != b)
+        margin = o["log"][k]["margin"]
+        assert abs(margin) <= 1e3 * U64 * n, (k, margin)
+        o = dense.purify(h.F, scheme, force_branches=r["branches"], **kw)
+    assert r["status"] == o["status"], (r["status"], o["status"])
+    assert r["branches"] == o["branches"]
+    assert r["products"] == o["products"] and r["iterations"] == o["iterations"]
+    for a, b in zip(r["log"], o["log"]):
+        assert a["i"] == b["i"]
+        assert abs(a["beta"] - b["beta"]) == 0.0 and abs(a["betabar"] - b["betabar"]) == 0.0
+        assert abs(a["t1"] - b["t1"]) <= 1e-9 * max(1.0, abs(b["t1"]))
+        assert abs(a["t2"] - b["t2"]) <= 1e-9 * max(1.0, abs(b["t2"]))
+        assert abs(a["e"] - b["e"]) <= 1e-8 * b["e"] + 1e-11 * math.sqrt(n)
+    Dg = D.cpu().numpy()
+    assert np.linalg.norm(Dg - o["D"]) <= 1e-8 * math.sqrt(n)
+    assert np.array_equal(Dg, Dg.T)
+    return Dg, r, o
+
+
+# ---- single steps (rows: product + fused combination and sums) --------------------------
+
+@pytest.mark.parametrize("n", [1, 17, 128, 129, 255, 256, 300, 1000])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16_ref64"])
+def test_step_matches_numpy(snf, n, prec):
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n)) / math.sqrt(n)
+    A = 0.5 * (A + A.T)
+    c2, c1, c0 = 0.7, -0.3, 0.25
+    Y, sums, _ = snf.step_dense(_dev(A), _dev(A), c2, c1, c0, prec)
+    Y = Y.cpu().numpy()
+    P = A @ A
+    Yref = c2 * P + c1 * A + c0 * np.eye(n)
+    absprod = np.abs(A) @ np.abs(A)
+    if prec == "fp64":
+        u_in, u_acc = 0.0, U64
+    elif prec == "fp32":
+        u_in, u_acc = 2.0 ** -24, 2.0 ** -24
+    else:
+        u_in, u_acc = 2.0 ** -8, 2.0 ** -24
+    bound = (2 * u_in + u_in * u_in + (n + 2) * u_acc) * absprod * abs(c2) + 1e-15
+    assert np.all(np.abs(Y - Yref) <= bound + 8 * U64 * (np.abs(Yref) + abs(c1) * np.abs(A)))
+    assert np.array_equal(Y, Y.T)
+    e2_ref = float(np.sum((P - A) ** 2))
+    rel = 1e-12 if prec == "fp64" else (1e-4 if prec == "fp32" else 5e-2)
+    assert abs(sums[0] - e2_ref) <= rel * e2_ref + 1e-300
+    assert abs(sums[1] - np.trace(Y)) <= 1e-12 * max(1.0, abs(np.trace(Y)))
+    assert abs(sums[2] - np.sum(Y * Y)) <= 1e-12 * np.sum(Y * Y)
+
+
+def test_step_commuting_operands(snf):
+    """A.B with B a polynomial in A (the second product of Algorithm 1)."""
+    n = 200
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((n, n)) / math.sqrt(n)
+    A = 0.5 * (A + A.T)
+    B = 0.5 * (A @ A) + 0.25 * A
+    B = 0.5 * (B + B.T)
+    Y, _, _ = snf.step_dense(_dev(A), _dev(B), 1.0, 0.0, 0.0, "fp64")
+    ref = A @ B
+    ref = np.triu(ref) + np.triu(ref, 1).T          # the kernel mirrors the upper triangle
+    assert np.max(np.abs(Y.cpu().numpy() - ref)) <= 1e-13
+
+
+# ---- whole purifications, FP64 -------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_small_gap_256_parity(snf, scheme):
+    h = H.small_gap_256()
+    Dg, r, o = _compare_to_oracle(snf, h, scheme)
+    D_ref = exact.projector(n_occ=h.n_occ, eigvals=h.eigvals, Q=h.Q)
+    assert np.linalg.norm(Dg - D_ref) <= 1e-8 * math.sqrt(h.n)
+    assert r["idem_err"] <= 1e-10 and abs(r["trace_err"]) <= 1e-8
+
+
+def test_small_gap_256_counts(snf):
+    """Products to ||X^2-X||_F <= 1e-10: the scaled schemes need about 40% fewer."""
+    h = H.small_gap_256()
+    kw = _kw(h)
+    got = {s: snf.purify_dense(_dev(h.F), s, **kw)[1]["products"] for s in SCHEMES}
+    spec = {s: spectral.purify_spectrum(h.eigvals, s, **kw)["products"] for s in SCHEMES}
+    assert got == spec
+    assert got["snf_varmu"] * 1.5 <= got["tc2"] and got["snf_fixmu"] * 1.5 <= got["mcweeny"]
+
+
+@pytest.mark.parametrize("n,n_occ", [(2, 1), (37, 20), (130, 40), (300, 151), (1000, 480)])
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_ragged_sizes_parity(snf, n, n_occ, scheme):
+    h = H.random_spectrum_hamiltonian(n, n_occ, -0.9, 0.02, 0.08, 1.1, seed=n)
+    _compare_to_oracle(snf, h, scheme)
+
+
+@pytest.mark.parametrize("scheme", ["sp2", "tc2", "snf_varmu", "mcweeny", "snf_fixmu"])
+def test_single_level(snf, scheme):
+    F = np.array([[0.3]])
+    kw = dict(lambda_min=-1.0, lambda_max=1.0, n_occ=1, homo=0.3, lumo=0.9, mu=0.6, xi=0.6,
+              tol=1e-12, max_iter=100)
+    D, r = snf.purify_dense(_dev(F), scheme, **kw)
+    o = dense.purify(F, scheme, **kw)
+    assert r["status"] == o["status"] == "ok"
+    assert r["branches"] == o["branches"] and r["products"] == o["products"]
+    assert abs(D.item() - 1.0) <= 1e-12
+
+
+def test_lattice_small_parity(snf):
+    """Two-orbital lattice at 8x8x4 sites (n = 512), both families."""
+    h = H.lattice_hamiltonian((8, 8, 4), seed=2)
+    for scheme in ("sp2", "snf_varmu", "snf_fixmu"):
+        _compare_to_oracle(snf, h, scheme, tol=1e-9)
+
+
+# ---- error paths ---------------------------------------------------------------------------
+
+def test_invalid_arguments(snf):
+    h = H.small_gap_256()
+    F = _dev(h.F)
+    L = snf.lib()
+    res = snf.Result()
+    p = snf.make_params(**_kw(h))
+    stream = torch.cuda.current_stream().cuda_stream
+    D = torch.empty_like(F)
+    # n <= 0, aliasing, null pointers, bad scheme
+    assert L.snf_purify_dense(F.data_ptr(), 0, 256, ctypes.byref(p), 2, 0, D.data_ptr(),
+                              ctypes.byref(res), None, 0, stream) == snf.EINVAL
+    assert L.snf_purify_dense(F.data_ptr(), 256, 256, ctypes.byref(p), 2, 0, F.data_ptr(),
+                              ctypes.byref(res), None, 0, stream) == snf.EINVAL
+    assert L.snf_purify_dense(None, 256, 256, ctypes.byref(p), 2, 0, D.data_ptr(),
+                              ctypes.byref(res), None, 0, stream) == snf.EINVAL
+    assert L.snf_purify_dense(F.data_ptr(), 256, 256, ctypes.byref(p), 9, 0, D.data_ptr(),
+                              ctypes.byref(res), None, 0, stream) == snf.EINVAL
+    for bad in (dict(lambda_min=1.0, lambda_max=-1.0), dict(homo=0.1, lumo=-0.1),
+                dict(tol=0.0), dict(max_iter=0), dict(max_iter=400)):
+        kw = _kw(h)
+        kw.update(bad)
+        p = snf.make_params(**kw)
+        assert L.snf_purify_dense(F.data_ptr(), 256, 256, ctypes.byref(p), 2, 0,
+                                  D.data_ptr(), ctypes.byref(res), None, 0,
+                                  stream) == snf.EINVAL, bad
+    kw = _kw(h)
+    kw.update(n_occ=-1)
+    p = snf.make_params(**kw)
+    assert L.snf_purify_dense(F.data_ptr(), 256, 256, ctypes.byref(p), 0, 0, D.data_ptr(),
+                              ctypes.byref(res), None, 0, stream) == snf.EINVAL
+
+
+def test_noconv_and_mixed(snf):
+    h = H.small_gap_256()
+    kw = _kw(h, max_iter=3)
+    _, r = snf.purify_dense(_dev(h.F), "snf_varmu", **kw)
+    o = spectral.purify_spectrum(h.eigvals, "snf_varmu", **kw)
+    assert r["status"] == o["status"] == "noconv"
+    assert r["iterations"] == 3 and r["products"] == 4
+    h2 = H.random_spectrum_hamiltonian(60, 30, -1.0, -0.05, 0.05, 1.0, seed=11)
+    kw = _kw(h2)
+    kw.update(homo=0.2, lumo=0.3)
+    _, r = snf.purify_dense(_dev(h2.F), "snf_varmu", **kw)
+    o = dense.purify(h2.F, "snf_varmu", **kw)
+    assert r["status"] == o["status"]
+
+
+def test_nonfinite_input(snf):
+    h = H.random_spectrum_hamiltonian(64, 30, -1.0, -0.05, 0.05, 1.0, seed=2)
+    F = h.F.copy()
+    F[3, 7] = np.nan
+    _, r = snf.purify_dense(_dev(F), "snf_varmu", **_kw(h))
+    assert r["status"] == "nonfinite"
+
+
+def test_padded_leading_dimension(snf):
+    """F and D with a row stride larger than n."""
+    h = H.random_spectrum_hamiltonian(100, 40, -1.0, -0.05, 0.05, 1.0, seed=4)
+    big = torch.zeros((100, 136), dtype=torch.float64, device="cuda:0")
+    big[:, :100] = _dev(h.F)
+    F = big[:, :100]
+    out = torch.full((100, 136), 7.0, dtype=torch.float64, device="cuda:0")
+    D, r = snf.purify_dense(F, "snf_varmu", out=out[:, :100], **_kw(h))
+    o = dense.purify(h.F, "snf_varmu", **_kw(h))
+    assert r["branches"] == o["branches"]
+    assert np.linalg.norm(out[:, :100].cpu().numpy() - o["D"]) <= 1e-8 * 10
+    assert torch.all(out[:, 100:] == 7.0)
+
+
+def test_repeat_bitwise_deterministic(snf):
+    h = H.random_spectrum_hamiltonian(384, 200, -1.0, 0.0, 0.01, 1.0, seed=9)
+    F = _dev(h.F)
+    D1, r1 = snf.purify_dense(F, "snf_varmu", **_kw(h))
+    D1 = D1.clone()
+    D2, r2 = snf.purify_dense(F, "snf_varmu", **_kw(h))
+    assert torch.equal(D1, D2) and r1["log"] == r2["log"]
+
+
+# ---- full-size workloads --------------------------------------------------------------------
+
+@functools.lru_cache(maxsize=1)
+def _lattice_4096():
+    return H.lattice_hamiltonian((16, 16, 8), seed=2)
+
+
+@pytest.mark.parametrize("scheme", ["snf_varmu", "sp2"])
+def test_lattice_4096_parity(snf, scheme):
+    """Two-orbital lattice 16x16x8 sites, n = 4096, FP64, tol 1e-8, the benchmark workload."""
+    h = _lattice_4096()
+    _compare_to_oracle(snf, h, scheme, tol=1e-8)
+
+
+@functools.lru_cache(maxsize=1)
+def _gap_8192():
+    return H.tiny_gap_8192()
+
+
+def test_gap1e3_8192_decisions_and_samples(snf):
+    """n = 8192, gap 1e-3 at mu = 0.1: decisions and counts against the spectral oracle,
+    sampled entries of D against the exact projector Q_occ Q_occ^T."""
+    h = _gap_8192()
+    kw = _kw(h, tol=1e-8, max_iter=120)
+    for scheme in ("snf_varmu", "snf_fixmu", "sp2"):
+        D, r = snf.purify_dense(_dev(h.F), scheme, **kw)
+        s = spectral.purify_spectrum(h.eigvals, scheme, **kw)
+        assert r["status"] == "ok"
+        if scheme != "sp2":
+            assert r["branches"] == s["branches"] and r["products"] == s["products"]
+        else:
+            assert abs(r["products"] - s["products"]) <= 1
+        rng = np.random.default_rng(1)
+        rows = rng.integers(0, h.n, 3000)
+        cols = rng.integers(0, h.n, 3000)
+        ref = exact.projector_entries(h.Q, h.eigvals, h.n_occ, rows, cols)
+        got = D[torch.tensor(rows, device="cuda:0"), torch.tensor(cols, device="cuda:0")]
+        assert np.max(np.abs(got.cpu().numpy() - ref)) <= 1e-8
+        assert abs(r["trace_err"]) <= 1e-8 and r["idem_err"] <= 1e-8
+        del D
