@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # v_pk_* FP32 instructions from scalar / float2 code by itself).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-command-line-argument"]
+         "-mllvm", "-amdgpu-mfma-vgpr-form", "-Wno-unused-command-line-argument"]
 
 
 def sources() -> list:

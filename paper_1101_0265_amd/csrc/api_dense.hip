@@ -44,6 +44,8 @@ struct Workspace {
   void* lp[3] = {nullptr, nullptr, nullptr};
   double* partials = nullptr;
   int partial_cap = 0;
+  double* split_buf = nullptr;       // kSplitCap slices of 64*256 doubles
+  int num_cus = 0;
   SnfState* state = nullptr;
   Buffers* bufs_dev = nullptr;
   SnfState* state_host = nullptr;    // pinned
@@ -87,6 +89,14 @@ static int ensure_workspace(Workspace* w, int64_t np, int lp_bytes, int partial_
     SNF_HIP(hipMalloc(&w->sums_dev, 4 * sizeof(double)));
     SNF_HIP(hipHostMalloc(&w->sums_host, 4 * sizeof(double), hipHostMallocDefault));
     for (int i = 0; i < 4; ++i) SNF_HIP(hipEventCreate(&w->ev[i]));
+    int dev = 0;
+    SNF_HIP(hipGetDevice(&dev));
+    SNF_HIP(hipDeviceGetAttribute(&w->num_cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (hipMalloc(&w->split_buf, (size_t)kSplitCap * 64 * kThreads * sizeof(double)) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      w->split_buf = nullptr;   // no split tail: whole tiles only
+    }
   }
   if (partial_need > w->partial_cap) {
     if (w->partials) (void)hipFree(w->partials);
@@ -314,6 +324,8 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
     out->status = rc;
     return rc;
   }
+  const ProductGrid grid = make_product_grid(np, n, sym, w->num_cus, w->partials, w->split_buf,
+                                             kSplitCap);
   // A workspace of larger order is used with this call's np: the kernels index rows with
   // np, so every buffer just needs np*np elements.
   init_state(w->state_host, n, params, scheme, precision);
@@ -344,9 +356,9 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
   auto enqueue_chunk = [&]() -> int {
     for (int k = 0; k < chunk && enq < max_steps; ++k, ++enq) {
       if (time_products) SNF_HIP(hipEventRecord(w->prod_ev[ev_used], s));
-      launch_product(kPrecF64, w->state, w->bufs_dev, np, n, w->partials, sym, s);
-      if (lowp) launch_product(lowp_kind_for(precision), w->state, w->bufs_dev, np, n,
-                               w->partials, sym, s);
+      launch_product(kPrecF64, w->state, w->bufs_dev, grid, s);
+      if (lowp) launch_product(lowp_kind_for(precision), w->state, w->bufs_dev, grid, s);
+      launch_split_fixup(w->state, w->bufs_dev, grid, s);
       if (time_products) SNF_HIP(hipEventRecord(w->prod_ev[ev_used + 1], s));
       if (time_products) ev_used += 2;
       launch_schedule(w->state, w->partials, tiles, 0, s);
@@ -412,9 +424,10 @@ int snf_step_dense(const double* A_dev, const double* B_dev, int64_t n, int64_t 
   const int64_t np = round_up(n, kTile);
   const int sym = 1;
   const int tiles = num_product_tiles(np, sym);
-  int rc = ensure_workspace(w, np, lowp_bytes_for(precision == SNF_P_FP32 ? SNF_P_FP32
-                                                  : precision), tiles);
+  int rc = ensure_workspace(w, np, lowp_bytes_for(precision), tiles);
   if (rc != SNF_OK) return rc;
+  const ProductGrid grid = make_product_grid(np, n, sym, w->num_cus, w->partials, w->split_buf,
+                                             kSplitCap);
   const int lk = lowp_kind_for(precision);
   rc = upload_buffers(w, s);
   if (rc != SNF_OK) return rc;
@@ -437,7 +450,8 @@ int snf_step_dense(const double* A_dev, const double* B_dev, int64_t n, int64_t 
   launch_pad_copy(A_dev, n, ld, w->x[0], np, w->lp[0], lk, s);
   launch_pad_copy(B_dev, n, ld, w->x[1], np, w->lp[1], lk, s);
   SNF_HIP(hipEventRecord(w->ev[0], s));
-  launch_product(sh->prec, w->state, w->bufs_dev, np, n, w->partials, sym, s);
+  launch_product(sh->prec, w->state, w->bufs_dev, grid, s);
+  launch_split_fixup(w->state, w->bufs_dev, grid, s);
   SNF_HIP(hipEventRecord(w->ev[1], s));
   launch_sum_partials(w->partials, tiles, w->sums_dev, s);
   launch_unpad_copy(w->x[2], np, n, Y_dev, ld, s);

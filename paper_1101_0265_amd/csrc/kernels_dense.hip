@@ -26,6 +26,14 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// 16-byte load through a global-address-space pointer, so the compiler emits global_load
+// (counted by vmcnt only) instead of flat_load, whose completion is also tracked by lgkmcnt
+// and would make every LDS-read wait of the main loop wait for the operand prefetch too.
+template <typename T>
+__device__ __forceinline__ u32x4 gload16(const T* p) {
+  return *(const __attribute__((address_space(1))) u32x4*)(p);
+}
+
 __device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
   // round-to-nearest-even truncation of an IEEE binary32 to bfloat16 (NaN kept quiet)
   unsigned int u = __float_as_uint(f);
@@ -187,13 +195,32 @@ template <> struct Mfma<float> {
 // Accumulator layout of lane l, register v: column l % 16 and row
 //   4 (l / 16) + v   for the f32 and bf16 MFMAs (ROWS_INTERLEAVED = false),
 //   (l / 16) + 4 v   for the f64 MFMA          (ROWS_INTERLEAVED = true).
+struct EpiArgs {
+  const double* Xt;  // linear term X (FP64)
+  double* Y;         // output (FP64)
+  void* LPY;         // low-precision copy of the output, or unused
+  int lowp_kind;     // kPrecF32 / kPrecBF16 / -1
+  int want_e;
+  double c2, c1, c0;
+};
+
+__device__ __forceinline__ EpiArgs epi_args(const SnfState* st, const Buffers* bufs) {
+  EpiArgs e;
+  e.Xt = bufs->x[st->ix];
+  e.Y = bufs->x[st->io];
+  e.LPY = bufs->lp[st->io];
+  e.lowp_kind = st->write_lowp ? (st->mode == SNF_P_BF16_REF64 ? kPrecBF16 : kPrecF32) : -1;
+  e.want_e = st->want_e;
+  e.c2 = st->c2;
+  e.c1 = st->c1;
+  e.c0 = st->c0;
+  return e;
+}
+
 template <bool ROWS_INTERLEAVED, typename AccT>
 __device__ __forceinline__ void epilogue(const AccT (&acc)[4][4], int gi0, int gj0, int sym,
-                                         int diag, int64_t n, int64_t np,
-                                         const double* __restrict__ Xt,
-                                         double* __restrict__ Y, void* __restrict__ LPY,
-                                         int lowp_kind, double c2, double c1, double c0,
-                                         int want_e, double& e2, double& t1, double& t2) {
+                                         int diag, int64_t n, int64_t np, const EpiArgs& ea,
+                                         double& e2, double& t1, double& t2) {
   const int lane = threadIdx.x & 63;
   const int rsub = ROWS_INTERLEAVED ? (lane >> 4) : 4 * (lane >> 4), csub = lane & 15;
   const int rstep = ROWS_INTERLEAVED ? 4 : 1;
@@ -211,25 +238,25 @@ __device__ __forceinline__ void epilogue(const AccT (&acc)[4][4], int gi0, int g
         const bool mirror = sym && r != c;
         const double w = mirror ? 2.0 : 1.0;
         const double p = (double)acc[m][q][v];
-        const double x = Xt[r * np + c];
-        if (want_e) {
+        const double x = ea.Xt[r * np + c];
+        if (ea.want_e) {
           const double d = p - x;
           e2 += w * (d * d);
         }
-        double y = c2 * p + c1 * x + (r == c ? c0 : 0.0);
+        double y = ea.c2 * p + ea.c1 * x + (r == c ? ea.c0 : 0.0);
         if (r >= n || c >= n) y = 0.0;
         if (r == c) t1 += y;
         t2 += w * (y * y);
-        Y[r * np + c] = y;
-        if (mirror) Y[c * np + r] = y;
-        if (lowp_kind == kPrecF32) {
+        ea.Y[r * np + c] = y;
+        if (mirror) ea.Y[c * np + r] = y;
+        if (ea.lowp_kind == kPrecF32) {
           const float yf = (float)y;
-          ((float*)LPY)[r * np + c] = yf;
-          if (mirror) ((float*)LPY)[c * np + r] = yf;
-        } else if (lowp_kind == kPrecBF16) {
+          ((float*)ea.LPY)[r * np + c] = yf;
+          if (mirror) ((float*)ea.LPY)[c * np + r] = yf;
+        } else if (ea.lowp_kind == kPrecBF16) {
           const unsigned short yb = f32_to_bf16_rne((float)y);
-          ((unsigned short*)LPY)[r * np + c] = yb;
-          if (mirror) ((unsigned short*)LPY)[c * np + r] = yb;
+          ((unsigned short*)ea.LPY)[r * np + c] = yb;
+          if (mirror) ((unsigned short*)ea.LPY)[c * np + r] = yb;
         }
       }
     }
@@ -248,12 +275,57 @@ __device__ __forceinline__ void write_partials(double e2, double t1, double t2,
   }
 }
 
+// Work decomposition of one product launch.  Workgroups [0, dp_tiles) compute whole tiles
+// (id remapped per XCD); the remaining workgroups compute one of split_s k-slices of the
+// tail tiles [dp_tiles, dp_tiles + tail_tiles) and store their raw accumulators; the
+// fix-up kernel adds the slices of a tile in a fixed order and runs the epilogue.
+struct WorkItem {
+  int tile;
+  int piece;     // -1 for a whole tile, else the slice's index into the split buffer
+  int kt_begin, kt_end;
+};
+
+__device__ __forceinline__ WorkItem work_item(const ProductGrid& g, int KT) {
+  WorkItem it;
+  const int w = blockIdx.x;
+  if (w < g.dp_tiles) {
+    it.tile = xcd_remap(w, g.dp_tiles);
+    it.piece = -1;
+    it.kt_begin = 0;
+    it.kt_end = KT;
+  } else {
+    const int q = w - g.dp_tiles;
+    const int p = q % g.split_s;
+    it.tile = g.dp_tiles + q / g.split_s;
+    it.piece = q;
+    it.kt_begin = (int)((int64_t)p * KT / g.split_s);
+    it.kt_end = (int)((int64_t)(p + 1) * KT / g.split_s);
+  }
+  return it;
+}
+
+// Raw accumulators of a k-slice: split[piece][idx][tid], idx = (m*4 + q)*4 + v.
+template <typename AccT>
+__device__ __forceinline__ void store_slice(const AccT (&acc)[4][4], double* split, int piece) {
+  double* base = split + (size_t)piece * 64 * kThreads + threadIdx.x;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) base[((m * 4 + q) * 4 + v) * kThreads] = (double)acc[m][q][v];
+}
+
+// ---------------------------------------------------------------------------------------
+// Product kernel, f64 / f32 MFMA 16x16x4.
+//   LDS tiles hold 'k-rows' of both operands: sA[k][i] = A[k0+k][i0+i] and
+//   sB[k][j] = B[k0+k][j0+j]; A[i][k] = A[k][i] because A is symmetric, so both panels are
+//   read with contiguous, coalesced rows.  MFMA operand of lane l: row/col (l % 16), k (l / 16).
+// ---------------------------------------------------------------------------------------
 template <typename T, int PREC>
-__global__ __launch_bounds__(256) void product_kernel(const SnfState* __restrict__ st,
-                                                      const Buffers* __restrict__ bufs,
-                                                      int64_t np, int64_t n,
-                                                      double* __restrict__ partials,
-                                                      int sym) {
+__global__ __launch_bounds__(256, 2) void product_kernel(const SnfState* __restrict__ st,
+                                                         const Buffers* __restrict__ bufs,
+                                                         ProductGrid g) {
   if (st->stop || st->prec != PREC) return;
   typedef Mfma<T> M;
   constexpr int BK = M::kBK, LDS_W = kTile + M::kPad;
@@ -264,22 +336,14 @@ __global__ __launch_bounds__(256) void product_kernel(const SnfState* __restrict
   __shared__ __attribute__((aligned(16))) T sA[2][BK][LDS_W];
   __shared__ __attribute__((aligned(16))) T sB[2][BK][LDS_W];
 
-  const int ia = st->ia, ib = st->ib, ixx = st->ix, io = st->io;
-  const T* A = (PREC == kPrecF64) ? (const T*)bufs->x[ia] : (const T*)bufs->lp[ia];
-  const T* B = (PREC == kPrecF64) ? (const T*)bufs->x[ib] : (const T*)bufs->lp[ib];
-  const double* Xt = bufs->x[ixx];
-  double* Y = bufs->x[io];
-  void* LPY = bufs->lp[io];
-  const int lowp_kind = st->write_lowp ? (st->mode == SNF_P_BF16_REF64 ? kPrecBF16 : kPrecF32) : -1;
-  const double c2 = st->c2, c1 = st->c1, c0 = st->c0;
-  const int want_e = st->want_e;
+  const int64_t np = g.np;
+  const T* A = (PREC == kPrecF64) ? (const T*)bufs->x[st->ia] : (const T*)bufs->lp[st->ia];
+  const T* B = (PREC == kPrecF64) ? (const T*)bufs->x[st->ib] : (const T*)bufs->lp[st->ib];
 
-  const int nt = (int)(np / kTile);
-  const int total = gridDim.x;
-  const int tile = xcd_remap(blockIdx.x, total);
+  const int KT = (int)(np / BK);
+  const WorkItem wi = work_item(g, KT);
   int bi, bj;
-  tile_coords(tile, nt, sym, bi, bj);
-  const int diag = (bi == bj);
+  tile_coords(wi.tile, (int)(np / kTile), g.sym, bi, bj);
   const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -297,8 +361,8 @@ __global__ __launch_bounds__(256) void product_kernel(const SnfState* __restrict
 #pragma unroll
     for (int p = 0; p < PASSES; ++p) {
       const int64_t k = k0 + p * RPP + lrow;
-      ra[p] = *(const u32x4*)(A + k * np + i0 + lvec * VE);
-      rb[p] = *(const u32x4*)(B + k * np + j0 + lvec * VE);
+      ra[p] = gload16(A + k * np + i0 + lvec * VE);
+      rb[p] = gload16(B + k * np + j0 + lvec * VE);
     }
   };
   auto lstore = [&](int buf) {
@@ -309,14 +373,14 @@ __global__ __launch_bounds__(256) void product_kernel(const SnfState* __restrict
     }
   };
 
-  const int KT = (int)(np / BK);
-  gload(0);
+  gload((int64_t)wi.kt_begin * BK);
   lstore(0);
   __syncthreads();
   const int fr = lane & 15, fk = lane >> 4;
-  for (int kt = 0; kt < KT; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < KT) gload((int64_t)(kt + 1) * BK);
+  for (int kt = wi.kt_begin; kt < wi.kt_end; ++kt) {
+    const int buf = (kt - wi.kt_begin) & 1;
+    const bool more = kt + 1 < wi.kt_end;
+    if (more) gload((int64_t)(kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T a[4], b[4];
@@ -329,14 +393,19 @@ __global__ __launch_bounds__(256) void product_kernel(const SnfState* __restrict
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[m][q] = M::mma(a[m], b[q], acc[m][q]);
     }
-    if (kt + 1 < KT) lstore(buf ^ 1);
+    if (more) lstore(buf ^ 1);
     __syncthreads();
   }
 
+  if (wi.piece >= 0) {
+    store_slice(acc, g.split_buf, wi.piece);
+    return;
+  }
+  const EpiArgs ea = epi_args(st, bufs);
   double e2 = 0.0, t1 = 0.0, t2 = 0.0;
-  epilogue<PREC == kPrecF64>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), sym, diag, n, np,
-                             Xt, Y, LPY, lowp_kind, c2, c1, c0, want_e, e2, t1, t2);
-  write_partials(e2, t1, t2, partials, tile);
+  epilogue<PREC == kPrecF64>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), g.sym, bi == bj,
+                             g.n, np, ea, e2, t1, t2);
+  write_partials(e2, t1, t2, g.partials, wi.tile);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -346,11 +415,9 @@ __global__ __launch_bounds__(256) void product_kernel(const SnfState* __restrict
 //   is 8 consecutive k values of one row / column: lane l holds row (l % 16),
 //   k = 8 (l / 16) .. 8 (l / 16) + 7.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void product_bf16_kernel(const SnfState* __restrict__ st,
-                                                           const Buffers* __restrict__ bufs,
-                                                           int64_t np, int64_t n,
-                                                           double* __restrict__ partials,
-                                                           int sym) {
+__global__ __launch_bounds__(256, 2) void product_bf16_kernel(const SnfState* __restrict__ st,
+                                                              const Buffers* __restrict__ bufs,
+                                                              ProductGrid g) {
   if (st->stop || st->prec != kPrecBF16) return;
   constexpr int BK = 64;                 // bf16 per LDS row per stage = 128 B
   constexpr int LDS_W = BK + 8;          // row stride 144 B
@@ -360,20 +427,14 @@ __global__ __launch_bounds__(256) void product_bf16_kernel(const SnfState* __res
   __shared__ __attribute__((aligned(16))) unsigned short sA[2][kTile][LDS_W];
   __shared__ __attribute__((aligned(16))) unsigned short sB[2][kTile][LDS_W];
 
+  const int64_t np = g.np;
   const unsigned short* A = (const unsigned short*)bufs->lp[st->ia];
   const unsigned short* B = (const unsigned short*)bufs->lp[st->ib];
-  const double* Xt = bufs->x[st->ix];
-  double* Y = bufs->x[st->io];
-  void* LPY = bufs->lp[st->io];
-  const int lowp_kind = st->write_lowp ? kPrecBF16 : -1;
-  const double c2 = st->c2, c1 = st->c1, c0 = st->c0;
-  const int want_e = st->want_e;
 
-  const int nt = (int)(np / kTile);
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int KT = (int)(np / BK);
+  const WorkItem wi = work_item(g, KT);
   int bi, bj;
-  tile_coords(tile, nt, sym, bi, bj);
-  const int diag = (bi == bj);
+  tile_coords(wi.tile, (int)(np / kTile), g.sym, bi, bj);
   const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -391,8 +452,8 @@ __global__ __launch_bounds__(256) void product_bf16_kernel(const SnfState* __res
 #pragma unroll
     for (int p = 0; p < PASSES; ++p) {
       const int64_t r = p * RPP + lrow;
-      ra[p] = *(const u32x4*)(A + (i0 + r) * np + k0 + lvec * 8);
-      rb[p] = *(const u32x4*)(B + (j0 + r) * np + k0 + lvec * 8);
+      ra[p] = gload16(A + (i0 + r) * np + k0 + lvec * 8);
+      rb[p] = gload16(B + (j0 + r) * np + k0 + lvec * 8);
     }
   };
   auto lstore = [&](int buf) {
@@ -403,14 +464,14 @@ __global__ __launch_bounds__(256) void product_bf16_kernel(const SnfState* __res
     }
   };
 
-  const int KT = (int)(np / BK);
-  gload(0);
+  gload((int64_t)wi.kt_begin * BK);
   lstore(0);
   __syncthreads();
   const int fr = lane & 15, fk = (lane >> 4) * 8;
-  for (int kt = 0; kt < KT; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < KT) gload((int64_t)(kt + 1) * BK);
+  for (int kt = wi.kt_begin; kt < wi.kt_end; ++kt) {
+    const int buf = (kt - wi.kt_begin) & 1;
+    const bool more = kt + 1 < wi.kt_end;
+    if (more) gload((int64_t)(kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 32) {
       bf16x8 a[4], b[4];
@@ -426,31 +487,101 @@ __global__ __launch_bounds__(256) void product_bf16_kernel(const SnfState* __res
         for (int q = 0; q < 4; ++q)
           acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[q], acc[m][q], 0, 0, 0);
     }
-    if (kt + 1 < KT) lstore(buf ^ 1);
+    if (more) lstore(buf ^ 1);
     __syncthreads();
   }
 
+  if (wi.piece >= 0) {
+    store_slice(acc, g.split_buf, wi.piece);
+    return;
+  }
+  const EpiArgs ea = epi_args(st, bufs);
   double e2 = 0.0, t1 = 0.0, t2 = 0.0;
-  epilogue<false>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), sym, diag, n, np, Xt, Y,
-                  LPY, lowp_kind, c2, c1, c0, want_e, e2, t1, t2);
-  write_partials(e2, t1, t2, partials, tile);
+  epilogue<false>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), g.sym, bi == bj, g.n, np, ea,
+                  e2, t1, t2);
+  write_partials(e2, t1, t2, g.partials, wi.tile);
 }
 
-void launch_product(int prec, SnfState* st, const Buffers* bufs_dev, int64_t np, int64_t n,
-                    double* partials, int sym, hipStream_t s) {
+// Fix-up of the split tail tiles: sum the k-slices in slice order, then the epilogue.
+__global__ __launch_bounds__(256) void split_fixup_kernel(const SnfState* __restrict__ st,
+                                                          const Buffers* __restrict__ bufs,
+                                                          ProductGrid g) {
+  if (st->stop) return;
+  const int tile = g.dp_tiles + blockIdx.x;
+  int bi, bj;
+  tile_coords(tile, (int)(g.np / kTile), g.sym, bi, bj);
+  const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
+  const int wid = threadIdx.x >> 6, wr = wid >> 1, wc = wid & 1;
+  dbl4 acc[4][4];
+  const double* base = g.split_buf + (size_t)blockIdx.x * g.split_s * 64 * kThreads + threadIdx.x;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int idx = (m * 4 + q) * 4 + v;
+        double s = 0.0;
+        for (int p = 0; p < g.split_s; ++p) s += base[((size_t)p * 64 + idx) * kThreads];
+        acc[m][q][v] = s;
+      }
+  const EpiArgs ea = epi_args(st, bufs);
+  double e2 = 0.0, t1 = 0.0, t2 = 0.0;
+  if (st->prec == kPrecF64)
+    epilogue<true>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), g.sym, bi == bj, g.n, g.np,
+                   ea, e2, t1, t2);
+  else
+    epilogue<false>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), g.sym, bi == bj, g.n, g.np,
+                    ea, e2, t1, t2);
+  write_partials(e2, t1, t2, g.partials, tile);
+}
+
+ProductGrid make_product_grid(int64_t np, int64_t n, int sym, int num_cus, double* partials,
+                              double* split_buf, int split_cap) {
+  ProductGrid g;
+  g.np = np;
+  g.n = n;
+  g.sym = sym;
+  g.partials = partials;
+  g.split_buf = split_buf;
   const int tiles = num_product_tiles(np, sym);
+  g.dp_tiles = tiles;
+  g.tail_tiles = 0;
+  g.split_s = 1;
+  if (num_cus <= 0 || !split_buf) return g;
+  const int rem = tiles % num_cus;
+  const int kt_min = (int)(np / 64);     // k-stages of the deepest stage (bf16: 64 per stage)
+  if (rem == 0 || rem > num_cus / 2) return g;
+  int s = num_cus / rem;
+  if (s > kt_min) s = kt_min;
+  if (s > 16) s = 16;
+  if (s < 2 || rem * s > split_cap) return g;
+  g.dp_tiles = tiles - rem;
+  g.tail_tiles = rem;
+  g.split_s = s;
+  return g;
+}
+
+void launch_product(int prec, SnfState* st, const Buffers* bufs_dev, const ProductGrid& g,
+                    hipStream_t s) {
+  const int grid = g.dp_tiles + g.tail_tiles * g.split_s;
   if (prec == kPrecF64) {
-    hipLaunchKernelGGL((product_kernel<double, kPrecF64>), dim3(tiles), dim3(kThreads), 0, s,
-                       st, bufs_dev, np, n, partials, sym);
+    hipLaunchKernelGGL((product_kernel<double, kPrecF64>), dim3(grid), dim3(kThreads), 0, s,
+                       st, bufs_dev, g);
   } else if (prec == kPrecF32) {
-    hipLaunchKernelGGL((product_kernel<float, kPrecF32>), dim3(tiles), dim3(kThreads), 0, s,
-                       st, bufs_dev, np, n, partials, sym);
+    hipLaunchKernelGGL((product_kernel<float, kPrecF32>), dim3(grid), dim3(kThreads), 0, s,
+                       st, bufs_dev, g);
   } else {
-    hipLaunchKernelGGL(product_bf16_kernel, dim3(tiles), dim3(kThreads), 0, s, st, bufs_dev,
-                       np, n, partials, sym);
+    hipLaunchKernelGGL(product_bf16_kernel, dim3(grid), dim3(kThreads), 0, s, st, bufs_dev, g);
   }
 }
 
+void launch_split_fixup(SnfState* st, const Buffers* bufs_dev, const ProductGrid& g,
+                        hipStream_t s) {
+  if (g.tail_tiles == 0) return;
+  hipLaunchKernelGGL(split_fixup_kernel, dim3(g.tail_tiles), dim3(kThreads), 0, s, st, bufs_dev,
+                     g);
+}
 // ---------------------------------------------------------------------------------------
 // Schedule: reduce the partials in a fixed order, then advance the scalar state.
 // ---------------------------------------------------------------------------------------

@@ -74,10 +74,29 @@ void launch_f0(const double* F, int64_t n, int64_t ld, int64_t np, SnfState* st,
                const Buffers* bufs_dev, int lowp_kind, double* partials, hipStream_t s);
 void launch_schedule(SnfState* st, const double* partials, int count, int init,
                      hipStream_t s);
+// Work decomposition of one product launch (see make_product_grid).
+struct ProductGrid {
+  int64_t np, n;       // padded and true order
+  int sym;             // 1: upper-triangle tiles, mirrored output
+  int dp_tiles;        // tiles computed whole, one workgroup each
+  int tail_tiles;      // following tiles, each split into split_s k-slices
+  int split_s;
+  double* partials;    // [tiles][4] per-tile FP64 sums
+  double* split_buf;   // [tail_tiles * split_s][64][256] raw accumulators of the slices
+};
+
+// Split the last (tiles mod num_cus) tiles into k-slices when that tail would leave most
+// compute units idle; split_cap = slices the split buffer holds.
+ProductGrid make_product_grid(int64_t np, int64_t n, int sym, int num_cus, double* partials,
+                              double* split_buf, int split_cap);
+constexpr int kSplitCap = 512;   // slices held by the split buffer (64*256 doubles each)
+
 // Product of the pending step; each variant exits at once unless the state asks for its
 // precision (so the host can enqueue all variants without knowing the device's choice).
-void launch_product(int prec, SnfState* st, const Buffers* bufs_dev, int64_t np, int64_t n,
-                    double* partials, int sym, hipStream_t s);
+void launch_product(int prec, SnfState* st, const Buffers* bufs_dev, const ProductGrid& g,
+                    hipStream_t s);
+void launch_split_fixup(SnfState* st, const Buffers* bufs_dev, const ProductGrid& g,
+                        hipStream_t s);
 void launch_copy_out(const SnfState* st, const Buffers* bufs_dev, int64_t n, int64_t np,
                      double* D, int64_t ld, hipStream_t s);
 // Padded copy helpers for the stand-alone step.
