@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="for hardware-counter runs: a plain 512 MiB device copy (counter "
+                         "calibration), then three FP64 products of the workload's X_0")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the method's "
@@ -100,6 +103,21 @@ def main():
     D = torch.empty_like(F)
     kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
               lumo=h.lumo, mu=h.mu, xi=h.xi, tol=TOL, max_iter=200)
+
+    if args.traffic_probe:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        lmax, lmin = h.lambda_max, h.lambda_min
+        X0 = (lmax * torch.eye(n, dtype=torch.float64, device=dev) - F) / (lmax - lmin)
+        for _ in range(3):
+            snf.step_dense(X0, X0, 1.0, 0.0, 0.0, "fp64")
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_probe": True, "copy_bytes": src.numel() * 8,
+                          "n": n, "kernel_source_hash": kernel_source_hash()}), flush=True)
+        return
 
     def solve(scheme, flags=0):
         _, r = snf.purify_dense(F, scheme, out=D, want_log=False, flags=flags, **kw)

@@ -319,7 +319,7 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
   const int64_t np = round_up(n, kTile);
   const int sym = 1;
   const int tiles = num_product_tiles(np, sym);
-  rc = ensure_workspace(w, np, lowp_bytes_for(precision), tiles);
+  rc = ensure_workspace(w, np, lowp_bytes_for(precision), tiles + 16 * kSplitCap);
   if (rc != SNF_OK) {
     out->status = rc;
     return rc;
@@ -361,7 +361,7 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
       launch_split_fixup(w->state, w->bufs_dev, grid, s);
       if (time_products) SNF_HIP(hipEventRecord(w->prod_ev[ev_used + 1], s));
       if (time_products) ev_used += 2;
-      launch_schedule(w->state, w->partials, tiles, 0, s);
+      launch_schedule(w->state, w->partials, grid.partial_count, 0, s);
     }
     SNF_HIP(hipGetLastError());
     SNF_HIP(hipMemcpyAsync((void*)(flags + (chunks & 1)), &w->state->stop, sizeof(int32_t),
@@ -424,7 +424,7 @@ int snf_step_dense(const double* A_dev, const double* B_dev, int64_t n, int64_t 
   const int64_t np = round_up(n, kTile);
   const int sym = 1;
   const int tiles = num_product_tiles(np, sym);
-  int rc = ensure_workspace(w, np, lowp_bytes_for(precision), tiles);
+  int rc = ensure_workspace(w, np, lowp_bytes_for(precision), tiles + 16 * kSplitCap);
   if (rc != SNF_OK) return rc;
   const ProductGrid grid = make_product_grid(np, n, sym, w->num_cus, w->partials, w->split_buf,
                                              kSplitCap);
@@ -453,7 +453,7 @@ int snf_step_dense(const double* A_dev, const double* B_dev, int64_t n, int64_t 
   launch_product(sh->prec, w->state, w->bufs_dev, grid, s);
   launch_split_fixup(w->state, w->bufs_dev, grid, s);
   SNF_HIP(hipEventRecord(w->ev[1], s));
-  launch_sum_partials(w->partials, tiles, w->sums_dev, s);
+  launch_sum_partials(w->partials, grid.partial_count, w->sums_dev, s);
   launch_unpad_copy(w->x[2], np, n, Y_dev, ld, s);
   SNF_HIP(hipGetLastError());
   SNF_HIP(hipMemcpyAsync(w->sums_host, w->sums_dev, 3 * sizeof(double), hipMemcpyDeviceToHost, s));

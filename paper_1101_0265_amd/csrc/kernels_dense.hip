@@ -217,50 +217,58 @@ __device__ __forceinline__ EpiArgs epi_args(const SnfState* st, const Buffers* b
   return e;
 }
 
+// One 16x16 MFMA block (m, q) of the wave tile: acc4 holds its four values of this lane.
+template <bool ROWS_INTERLEAVED, typename Acc4>
+__device__ __forceinline__ void epilogue_block(const Acc4& acc4, int m, int q, int gi0, int gj0,
+                                               int sym, int diag, int64_t n, int64_t np,
+                                               const EpiArgs& ea, double& e2, double& t1,
+                                               double& t2) {
+  const int lane = threadIdx.x & 63;
+  const int rsub = ROWS_INTERLEAVED ? (lane >> 4) : 4 * (lane >> 4), csub = lane & 15;
+  const int rstep = ROWS_INTERLEAVED ? 4 : 1;
+  const int64_t c = gj0 + q * 16 + csub;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t r = gi0 + m * 16 + rsub + v * rstep;
+    // In symmetric mode a diagonal tile keeps its upper half and mirrors it, so the
+    // result is exactly symmetric; every off-diagonal entry then stands for two.
+    if (diag && sym && r > c) continue;
+    const bool mirror = sym && r != c;
+    const double w = mirror ? 2.0 : 1.0;
+    const double p = (double)acc4[v];
+    const double x = ea.Xt[r * np + c];
+    if (ea.want_e) {
+      const double d = p - x;
+      e2 += w * (d * d);
+    }
+    double y = ea.c2 * p + ea.c1 * x + (r == c ? ea.c0 : 0.0);
+    if (r >= n || c >= n) y = 0.0;
+    if (r == c) t1 += y;
+    t2 += w * (y * y);
+    ea.Y[r * np + c] = y;
+    if (mirror) ea.Y[c * np + r] = y;
+    if (ea.lowp_kind == kPrecF32) {
+      const float yf = (float)y;
+      ((float*)ea.LPY)[r * np + c] = yf;
+      if (mirror) ((float*)ea.LPY)[c * np + r] = yf;
+    } else if (ea.lowp_kind == kPrecBF16) {
+      const unsigned short yb = f32_to_bf16_rne((float)y);
+      ((unsigned short*)ea.LPY)[r * np + c] = yb;
+      if (mirror) ((unsigned short*)ea.LPY)[c * np + r] = yb;
+    }
+  }
+}
+
 template <bool ROWS_INTERLEAVED, typename AccT>
 __device__ __forceinline__ void epilogue(const AccT (&acc)[4][4], int gi0, int gj0, int sym,
                                          int diag, int64_t n, int64_t np, const EpiArgs& ea,
                                          double& e2, double& t1, double& t2) {
-  const int lane = threadIdx.x & 63;
-  const int rsub = ROWS_INTERLEAVED ? (lane >> 4) : 4 * (lane >> 4), csub = lane & 15;
-  const int rstep = ROWS_INTERLEAVED ? 4 : 1;
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t c = gj0 + q * 16 + csub;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t r = gi0 + m * 16 + rsub + v * rstep;
-        // In symmetric mode a diagonal tile keeps its upper half and mirrors it, so the
-        // result is exactly symmetric; every off-diagonal entry then stands for two.
-        if (diag && sym && r > c) continue;
-        const bool mirror = sym && r != c;
-        const double w = mirror ? 2.0 : 1.0;
-        const double p = (double)acc[m][q][v];
-        const double x = ea.Xt[r * np + c];
-        if (ea.want_e) {
-          const double d = p - x;
-          e2 += w * (d * d);
-        }
-        double y = ea.c2 * p + ea.c1 * x + (r == c ? ea.c0 : 0.0);
-        if (r >= n || c >= n) y = 0.0;
-        if (r == c) t1 += y;
-        t2 += w * (y * y);
-        ea.Y[r * np + c] = y;
-        if (mirror) ea.Y[c * np + r] = y;
-        if (ea.lowp_kind == kPrecF32) {
-          const float yf = (float)y;
-          ((float*)ea.LPY)[r * np + c] = yf;
-          if (mirror) ((float*)ea.LPY)[c * np + r] = yf;
-        } else if (ea.lowp_kind == kPrecBF16) {
-          const unsigned short yb = f32_to_bf16_rne((float)y);
-          ((unsigned short*)ea.LPY)[r * np + c] = yb;
-          if (mirror) ((unsigned short*)ea.LPY)[c * np + r] = yb;
-        }
-      }
-    }
-  }
+    for (int q = 0; q < 4; ++q)
+      epilogue_block<ROWS_INTERLEAVED>(acc[m][q], m, q, gi0, gj0, sym, diag, n, np, ea, e2, t1,
+                                       t2);
 }
 
 __device__ __forceinline__ void write_partials(double e2, double t1, double t2,
@@ -502,38 +510,44 @@ __global__ __launch_bounds__(256, 2) void product_bf16_kernel(const SnfState* __
   write_partials(e2, t1, t2, g.partials, wi.tile);
 }
 
-// Fix-up of the split tail tiles: sum the k-slices in slice order, then the epilogue.
+// Fix-up of the split tail tiles: workgroup (t, b) handles MFMA block b = (m, q) of every
+// wave of tail tile t; it adds the k-slices in slice order (all loads in flight at once),
+// then runs the epilogue of that block and stores its sums in its own partials slot.
+constexpr int kMaxSplit = 16;
 __global__ __launch_bounds__(256) void split_fixup_kernel(const SnfState* __restrict__ st,
                                                           const Buffers* __restrict__ bufs,
                                                           ProductGrid g) {
   if (st->stop) return;
-  const int tile = g.dp_tiles + blockIdx.x;
+  const int t = blockIdx.x >> 4, b = blockIdx.x & 15, m = b >> 2, q = b & 3;
+  const int tile = g.dp_tiles + t;
   int bi, bj;
   tile_coords(tile, (int)(g.np / kTile), g.sym, bi, bj);
   const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
   const int wid = threadIdx.x >> 6, wr = wid >> 1, wc = wid & 1;
-  dbl4 acc[4][4];
-  const double* base = g.split_buf + (size_t)blockIdx.x * g.split_s * 64 * kThreads + threadIdx.x;
+  const double* base =
+      g.split_buf + (size_t)t * g.split_s * 64 * kThreads + (size_t)(b * 4) * kThreads + threadIdx.x;
+  double part[kMaxSplit][4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int p = 0; p < kMaxSplit; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int v = 0; v < 4; ++v)
+      part[p][v] = (p < g.split_s) ? base[((size_t)p * 64 + v) * kThreads] : 0.0;
+  dbl4 acc4;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int idx = (m * 4 + q) * 4 + v;
-        double s = 0.0;
-        for (int p = 0; p < g.split_s; ++p) s += base[((size_t)p * 64 + idx) * kThreads];
-        acc[m][q][v] = s;
-      }
+  for (int v = 0; v < 4; ++v) {
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < kMaxSplit; ++p) s += part[p][v];
+    acc4[v] = s;
+  }
   const EpiArgs ea = epi_args(st, bufs);
   double e2 = 0.0, t1 = 0.0, t2 = 0.0;
+  const int gi0 = (int)(i0 + wr * 64), gj0 = (int)(j0 + wc * 64);
   if (st->prec == kPrecF64)
-    epilogue<true>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), g.sym, bi == bj, g.n, g.np,
-                   ea, e2, t1, t2);
+    epilogue_block<true>(acc4, m, q, gi0, gj0, g.sym, bi == bj, g.n, g.np, ea, e2, t1, t2);
   else
-    epilogue<false>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), g.sym, bi == bj, g.n, g.np,
-                    ea, e2, t1, t2);
-  write_partials(e2, t1, t2, g.partials, tile);
+    epilogue_block<false>(acc4, m, q, gi0, gj0, g.sym, bi == bj, g.n, g.np, ea, e2, t1, t2);
+  write_partials(e2, t1, t2, g.partials, g.dp_tiles + blockIdx.x);
 }
 
 ProductGrid make_product_grid(int64_t np, int64_t n, int sym, int num_cus, double* partials,
@@ -548,17 +562,19 @@ ProductGrid make_product_grid(int64_t np, int64_t n, int sym, int num_cus, doubl
   g.dp_tiles = tiles;
   g.tail_tiles = 0;
   g.split_s = 1;
+  g.partial_count = tiles;
   if (num_cus <= 0 || !split_buf) return g;
   const int rem = tiles % num_cus;
   const int kt_min = (int)(np / 64);     // k-stages of the deepest stage (bf16: 64 per stage)
   if (rem == 0 || rem > num_cus / 2) return g;
   int s = num_cus / rem;
   if (s > kt_min) s = kt_min;
-  if (s > 16) s = 16;
+  if (s > kMaxSplit) s = kMaxSplit;
   if (s < 2 || rem * s > split_cap) return g;
   g.dp_tiles = tiles - rem;
   g.tail_tiles = rem;
   g.split_s = s;
+  g.partial_count = g.dp_tiles + 16 * rem;   // one slot per fix-up workgroup
   return g;
 }
 
@@ -579,8 +595,8 @@ void launch_product(int prec, SnfState* st, const Buffers* bufs_dev, const Produ
 void launch_split_fixup(SnfState* st, const Buffers* bufs_dev, const ProductGrid& g,
                         hipStream_t s) {
   if (g.tail_tiles == 0) return;
-  hipLaunchKernelGGL(split_fixup_kernel, dim3(g.tail_tiles), dim3(kThreads), 0, s, st, bufs_dev,
-                     g);
+  hipLaunchKernelGGL(split_fixup_kernel, dim3(g.tail_tiles * 16), dim3(kThreads), 0, s, st,
+                     bufs_dev, g);
 }
 // ---------------------------------------------------------------------------------------
 // Schedule: reduce the partials in a fixed order, then advance the scalar state.

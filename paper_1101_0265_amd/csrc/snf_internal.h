@@ -81,7 +81,8 @@ struct ProductGrid {
   int dp_tiles;        // tiles computed whole, one workgroup each
   int tail_tiles;      // following tiles, each split into split_s k-slices
   int split_s;
-  double* partials;    // [tiles][4] per-tile FP64 sums
+  int partial_count;   // partial-sum slots written: dp_tiles + 16 * tail_tiles (or tiles)
+  double* partials;    // [partial_count][4] FP64 sums per tile / fix-up workgroup
   double* split_buf;   // [tail_tiles * split_s][64][256] raw accumulators of the slices
 };
 
