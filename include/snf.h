@@ -170,6 +170,58 @@ int snf_step_dense(const double* A_dev, const double* B_dev, int64_t n, int64_t 
                    double c2, double c1, double c0, snf_precision precision, double* Y_dev,
                    double* sums, double* kernel_ms, void* stream);
 
+/* ---- block-sparse (BSR) path ----------------------------------------------------------
+ * The linear-scaling regime (the sparsity paragraph of the paper: the schemes are of the
+ * form of Eq. 1, so they combine with truncation of small matrix elements).  X is stored in
+ * block-sparse row form with square FP32 blocks; after every step the blocks of X_new with
+ * Frobenius norm below trunc_tau are dropped (block (I,J) together with (J,I); diagonal
+ * blocks are always kept), so the pattern, the memory and the work follow the decay of D.
+ */
+typedef struct {
+  int64_t n;          /* order; a multiple of b                                             */
+  int32_t b;          /* block size; must be 32                                             */
+  int32_t nb;         /* block rows = n / b                                                 */
+  int64_t nnzb;       /* stored blocks                                                      */
+  int32_t* row_ptr;   /* device, nb + 1 entries, row_ptr[0] = 0, row_ptr[nb] = nnzb         */
+  int32_t* col_idx;   /* device, nnzb block-column indices, strictly ascending in each row  */
+  float* val;         /* device, nnzb * b * b values, each block row-major                  */
+} snf_bsr;
+
+/*
+ * snf_purify_bsr -- purify a block-sparse symmetric F (schemes SNF_SP2_TRACE, SNF_TC2_BETA,
+ * SNF_SNF_VARMU: one product per iteration; the Algorithm 1 schemes return SNF_EINVAL).
+ *   F:      caller-owned, device arrays; the pattern must be symmetric with every diagonal
+ *           block present; only blocks (I,J) with I <= J (and the upper triangle of diagonal
+ *           blocks) are read, the rest is taken as their transpose.
+ *   trunc_tau: block truncation threshold (Frobenius norm), >= 0 (0 = no truncation).
+ *   D_out:  receives a library-allocated snf_bsr (host struct, device arrays) holding D;
+ *           release it with snf_bsr_free.  NULL on error.
+ *   Stops with SNF_OK at ||X^2 - X||_F <= tol, or SNF_OK_FLOOR once the a-priori error
+ *   bound max(beta, 1 - beta-bar) is below params->lowp_floor (0 = default 1e-3) and the
+ *   idempotency error stopped shrinking (e_i > 0.5 e_{i-2}): the truncation floor.
+ *   Synchronous; reads pattern sizes back to the host once per iteration.
+ */
+int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme,
+                   double trunc_tau, snf_bsr** D_out, snf_result* out, snf_log_rec* log,
+                   int32_t log_cap, void* stream);
+
+/*
+ * snf_step_bsr -- one block-sparse step: Y = trunc_tau-truncation of (c2 X.X + c1 X + c0 I),
+ * the unit of work of the loop above; sums[0] = ||X.X - X||_F^2, sums[1] = tr Y,
+ * sums[2] = ||Y||_F^2 (after truncation).  X as F above; *Y_out library-allocated.
+ * kernel_ms (optional): duration of the numeric product kernel.
+ */
+int snf_step_bsr(const snf_bsr* X, double c2, double c1, double c0, double trunc_tau,
+                 snf_bsr** Y_out, double* sums, double* kernel_ms, void* stream);
+
+/* Copy the arrays of a (library-allocated) snf_bsr into caller device buffers of sizes
+   nb + 1, nnzb and nnzb * b * b; enqueued on `stream`, returns after completion. */
+int snf_bsr_copy_out(const snf_bsr* src, int32_t* row_ptr, int32_t* col_idx, float* val,
+                     void* stream);
+
+/* Free a library-allocated snf_bsr (device arrays and the struct).  NULL is ignored. */
+void snf_bsr_free(snf_bsr* m);
+
 /* Bytes of device workspace snf_purify_dense needs for order n (allocated on demand). */
 size_t snf_workspace_bytes(int64_t n, snf_precision precision);
 

@@ -1,0 +1,940 @@
+// Block-sparse (BSR, 32x32 FP32 blocks) purification step and driver for gfx950.
+//
+// Per iteration, for the current X (symmetric pattern, every diagonal block present):
+//   1. bsr_bitmap_kernel    per block row: bitmap of its block columns + prefix popcounts,
+//                           so block (K, c) is found at row_ptr[K] + rank_K(c) in O(1).
+//   2. bsr_symbolic_kernel  candidate pattern of X.X: row I = OR of the bitmaps of the rows
+//                           K in row I (integer work).
+//   3. bsr_tile_flags       128x128 super-tiles (4x4 blocks) of the upper triangle that hold
+//                           a candidate block.
+//   4. bsr_product_kernel   one workgroup per super-tile: the f32-MFMA 128x128 tile engine of
+//                           the dense path, whose k-stages are the block columns K present in
+//                           both row unions; stage K gathers blocks (K, I_a) and (K, J_b) of
+//                           block row K (X symmetric: X_{I,K} = X_{K,I}^T), zero when absent.
+//                           Fused epilogue: Y = c2 P + c1 X + c0 I, FP64 sums, block norms;
+//                           upper blocks written with their transposed mirror.
+//   5. bsr_truncate_kernel  keep (I,J) and (J,I) iff ||Y_IJ||_F >= tau (diagonal always);
+//                           ranks in row order; per-row FP64 sum of kept squared norms.
+//   6. bsr_compact_kernel   copy the kept blocks into the next X.
+//   7. the dense path's schedule kernel (same on-device scalar state machine).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "schedule_math.h"
+#include "snf_internal.h"
+
+namespace snf {
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kB = 32;            // block size
+constexpr int kBB = kB * kB;      // values per block
+constexpr int kSup = 4;           // blocks per super-tile side (128 = 4 x 32)
+
+__device__ __forceinline__ u32x4 bsr_gload16(const float* p) {
+  return *(const __attribute__((address_space(1))) u32x4*)(p);
+}
+
+__device__ __forceinline__ double bsr_wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// position of block (row, c) or -1, from the row's bitmap and prefix popcounts
+__device__ __forceinline__ int bsr_find(const int32_t* __restrict__ row_ptr,
+                                        const uint32_t* __restrict__ bm,
+                                        const int32_t* __restrict__ pre, int W, int row, int c) {
+  const uint32_t word = bm[(size_t)row * W + (c >> 5)];
+  const uint32_t bit = 1u << (c & 31);
+  if (!(word & bit)) return -1;
+  return row_ptr[row] + pre[(size_t)row * W + (c >> 5)] + __popc(word & (bit - 1u));
+}
+
+// ---- 1. bitmaps -------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void bsr_bitmap_kernel(const int32_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ col_idx,
+                                                        int W, uint32_t* __restrict__ bm,
+                                                        int32_t* __restrict__ pre) {
+  extern __shared__ uint32_t words[];
+  const int I = blockIdx.x;
+  for (int w = threadIdx.x; w < W; w += blockDim.x) words[w] = 0u;
+  __syncthreads();
+  for (int p = row_ptr[I] + threadIdx.x; p < row_ptr[I + 1]; p += blockDim.x) {
+    const int c = col_idx[p];
+    atomicOr(&words[c >> 5], 1u << (c & 31));
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < W; w += blockDim.x) bm[(size_t)I * W + w] = words[w];
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < W; ++w) {
+      pre[(size_t)I * W + w] = s;
+      s += __popc(words[w]);
+    }
+  }
+}
+
+// ---- 2. symbolic ------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void bsr_symbolic_kernel(const int32_t* __restrict__ row_ptr,
+                                                          const int32_t* __restrict__ col_idx,
+                                                          const uint32_t* __restrict__ bm, int W,
+                                                          uint32_t* __restrict__ bmP,
+                                                          int32_t* __restrict__ preP,
+                                                          int32_t* __restrict__ cntP) {
+  extern __shared__ uint32_t acc[];
+  const int I = blockIdx.x;
+  for (int w = threadIdx.x; w < W; w += blockDim.x) acc[w] = 0u;
+  for (int p = row_ptr[I]; p < row_ptr[I + 1]; ++p) {
+    const int K = col_idx[p];
+    for (int w = threadIdx.x; w < W; w += blockDim.x) acc[w] |= bm[(size_t)K * W + w];
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < W; w += blockDim.x) bmP[(size_t)I * W + w] = acc[w];
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < W; ++w) {
+      preP[(size_t)I * W + w] = s;
+      s += __popc(acc[w]);
+    }
+    cntP[I] = s;
+  }
+}
+
+__global__ __launch_bounds__(64) void bsr_fill_cols_kernel(const uint32_t* __restrict__ bmP,
+                                                           const int32_t* __restrict__ preP,
+                                                           const int32_t* __restrict__ row_ptrP,
+                                                           int W, int32_t* __restrict__ colP) {
+  const int I = blockIdx.x;
+  for (int w = threadIdx.x; w < W; w += blockDim.x) {
+    uint32_t bits = bmP[(size_t)I * W + w];
+    int pos = row_ptrP[I] + preP[(size_t)I * W + w];
+    while (bits) {
+      const int b = __ffs(bits) - 1;
+      colP[pos++] = w * 32 + b;
+      bits &= bits - 1u;
+    }
+  }
+}
+
+// ---- 3. super-tiles ---------------------------------------------------------------------
+__global__ void bsr_tile_flags_kernel(const uint32_t* __restrict__ bmP, int nb, int W, int NT,
+                                      uint8_t* __restrict__ flags) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)NT * NT) return;
+  const int TI = (int)(t / NT), TJ = (int)(t % NT);
+  uint8_t f = 0;
+  if (TI <= TJ) {
+    const int c0 = kSup * TJ;
+    const uint32_t mask = 0xFu << (c0 & 31);
+    for (int a = 0; a < kSup; ++a) {
+      const int I = kSup * TI + a;
+      if (I < nb && (bmP[(size_t)I * W + (c0 >> 5)] & mask)) f = 1;
+    }
+  }
+  flags[t] = f;
+}
+
+// ---- 4. numeric product -----------------------------------------------------------------
+struct BsrMat {                    // device view of one BSR matrix with its lookup tables
+  const int32_t* row_ptr;
+  const uint32_t* bm;
+  const int32_t* pre;
+  float* val;
+};
+
+struct BsrProductArgs {
+  BsrMat X;            // operand (both sides) and linear term
+  BsrMat P;            // candidate pattern of the output, values written here
+  double* normP;       // squared Frobenius norm per candidate block
+  const int32_t* tiles;  // (TI << 16) | TJ
+  double* partials;    // [tiles][4]
+  int nb, W;
+};
+
+constexpr int kBsrLdsW = 128 + 16;   // LDS row stride (floats), as the dense f32 kernel
+constexpr int kChunkWords = 64;     // bitmap words per k-stage list chunk (2048 columns)
+
+__global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __restrict__ st,
+                                                             BsrProductArgs g) {
+  if (st->stop) return;
+  __shared__ __attribute__((aligned(16))) float sA[2][kB][kBsrLdsW];
+  __shared__ __attribute__((aligned(16))) float sB[2][kB][kBsrLdsW];
+  __shared__ uint16_t klist[kChunkWords * 32];
+  __shared__ uint32_t sw[kChunkWords];
+  __shared__ int offs[kChunkWords + 1];
+  __shared__ double red[12];
+
+  const int packed = g.tiles[blockIdx.x];
+  const int TI = packed >> 16, TJ = packed & 0xFFFF;
+  const int W = g.W, nb = g.nb;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int ci0 = kSup * TI, cj0 = kSup * TJ;   // first block column of the A / B panels
+
+  flt4 acc[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[m][q] = flt4{0.f, 0.f, 0.f, 0.f};
+
+  // Each thread moves one 16-byte piece of each of the 8 blocks of a stage:
+  // block row k = tid / 8, columns 4 (tid % 8) .. +3.
+  const int lk = tid >> 3, lc = (tid & 7) * 4;
+  u32x4 ra[kSup], rb[kSup];
+  auto gload = [&](int K) {
+    // the 4 panel columns of each side share one bitmap word of block row K
+    const int rp = g.X.row_ptr[K];
+    const uint32_t wa = g.X.bm[(size_t)K * W + (ci0 >> 5)];
+    const uint32_t wb = g.X.bm[(size_t)K * W + (cj0 >> 5)];
+    const int pa0 = rp + g.X.pre[(size_t)K * W + (ci0 >> 5)];
+    const int pb0 = rp + g.X.pre[(size_t)K * W + (cj0 >> 5)];
+#pragma unroll
+    for (int a = 0; a < kSup; ++a) {
+      const uint32_t bia = 1u << ((ci0 + a) & 31), bib = 1u << ((cj0 + a) & 31);
+      ra[a] = (wa & bia) ? bsr_gload16(g.X.val + (size_t)(pa0 + __popc(wa & (bia - 1u))) * kBB +
+                                       lk * kB + lc)
+                         : u32x4{0, 0, 0, 0};
+      rb[a] = (wb & bib) ? bsr_gload16(g.X.val + (size_t)(pb0 + __popc(wb & (bib - 1u))) * kBB +
+                                       lk * kB + lc)
+                         : u32x4{0, 0, 0, 0};
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int a = 0; a < kSup; ++a) {
+      *(u32x4*)(&sA[buf][lk][a * kB + lc]) = ra[a];
+      *(u32x4*)(&sB[buf][lk][a * kB + lc]) = rb[a];
+    }
+  };
+
+  const int fr = lane & 15, fk = lane >> 4;
+  // k-stages: block columns K present in both (rows I_a) and (rows J_b), taken in chunks
+  // of kChunkWords bitmap words
+  for (int w0 = 0; w0 < W; w0 += kChunkWords) {
+    __syncthreads();                       // the previous chunk is done with klist / LDS
+    if (tid < kChunkWords) {
+      const int w = w0 + tid;
+      uint32_t ua = 0u, ub = 0u;
+      if (w < W) {
+        for (int a = 0; a < kSup; ++a) {
+          if (ci0 + a < nb) ua |= g.X.bm[(size_t)(ci0 + a) * W + w];
+          if (cj0 + a < nb) ub |= g.X.bm[(size_t)(cj0 + a) * W + w];
+        }
+      }
+      sw[tid] = ua & ub;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int acc_n = 0;
+      for (int t = 0; t < kChunkWords; ++t) {
+        offs[t] = acc_n;
+        acc_n += __popc(sw[t]);
+      }
+      offs[kChunkWords] = acc_n;
+    }
+    __syncthreads();
+    if (tid < kChunkWords) {
+      uint32_t bits = sw[tid];
+      int pos = offs[tid];
+      while (bits) {
+        const int b = __ffs(bits) - 1;
+        klist[pos++] = (uint16_t)((w0 + tid) * 32 + b);
+        bits &= bits - 1u;
+      }
+    }
+    __syncthreads();
+    const int nk = offs[kChunkWords];
+    if (nk == 0) continue;
+    gload(klist[0]);
+    lstore(0);
+    __syncthreads();
+    for (int s = 0; s < nk; ++s) {
+      const int buf = s & 1;
+      const bool more = s + 1 < nk;
+      if (more) gload(klist[s + 1]);
+#pragma unroll
+      for (int kk = 0; kk < kB; kk += 4) {
+        float a[4], b[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) a[m] = sA[buf][kk + fk][wr * 64 + m * 16 + fr];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = sB[buf][kk + fk][wc * 64 + q * 16 + fr];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], b[q], acc[m][q], 0, 0, 0);
+      }
+      if (more) lstore(buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // Epilogue.  Wave (wr, wc) holds blocks (2 wr + bi, 2 wc + bj) of the super-tile; the
+  // f32 MFMA accumulator of lane l, register v is row 4 (l / 16) + v, column l % 16 of its
+  // 16x16 piece (m, q): block bi = m / 2, row (m % 2) 16 + ..., block bj = q / 2.
+  const double c2 = st->c2, c1 = st->c1, c0 = st->c0;
+  const int want_e = st->want_e;
+  double e2 = 0.0, t1 = 0.0;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi) {
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int I = kSup * TI + 2 * wr + bi, J = kSup * TJ + 2 * wc + bj;
+      if (I >= nb || J >= nb) continue;
+      if (I > J) continue;                       // lower blocks come from their mirror
+      const int pp = bsr_find(g.P.row_ptr, g.P.bm, g.P.pre, W, I, J);
+      if (pp < 0) continue;                      // no candidate: nothing contributes
+      const int ppT = (I == J) ? pp : bsr_find(g.P.row_ptr, g.P.bm, g.P.pre, W, J, I);
+      const int px = bsr_find(g.X.row_ptr, g.X.bm, g.X.pre, W, I, J);
+      float* Y = g.P.val + (size_t)pp * kBB;
+      float* YT = g.P.val + (size_t)ppT * kBB;
+      const float* Xb = px >= 0 ? g.X.val + (size_t)px * kBB : nullptr;
+      double nrm2 = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < 2; ++mm) {
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq) {
+          const int m = 2 * bi + mm, q = 2 * bj + qq;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = mm * 16 + 4 * (lane >> 4) + v;
+            const int c = qq * 16 + (lane & 15);
+            if (I == J && r > c) continue;       // diagonal block: upper half, mirrored
+            const bool mirror = (I != J) || (r != c);
+            const double w = mirror ? 2.0 : 1.0;
+            const double p = (double)acc[m][q][v];
+            const double x = Xb ? (double)Xb[r * kB + c] : 0.0;
+            if (want_e) {
+              const double d = p - x;
+              e2 += w * (d * d);
+            }
+            const double y = c2 * p + c1 * x + ((I == J && r == c) ? c0 : 0.0);
+            if (I == J && r == c) t1 += y;
+            const float yf = (float)y;
+            nrm2 += (I == J ? w : 1.0) * ((double)yf * (double)yf);
+            Y[r * kB + c] = yf;
+            if (mirror) YT[c * kB + r] = yf;
+          }
+        }
+      }
+      nrm2 = bsr_wave_sum(nrm2);
+      if (lane == 0) {
+        g.normP[pp] = nrm2;
+        g.normP[ppT] = nrm2;
+      }
+    }
+  }
+  // block_sum of e2, t1 (fixed order)
+  double t2 = 0.0;
+  e2 = bsr_wave_sum(e2);
+  t1 = bsr_wave_sum(t1);
+  if (lane == 0) {
+    red[wid * 3 + 0] = e2;
+    red[wid * 3 + 1] = t1;
+    red[wid * 3 + 2] = t2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    g.partials[blockIdx.x * 4 + 0] = ((red[0] + red[3]) + red[6]) + red[9];
+    g.partials[blockIdx.x * 4 + 1] = ((red[1] + red[4]) + red[7]) + red[10];
+    g.partials[blockIdx.x * 4 + 2] = 0.0;
+    g.partials[blockIdx.x * 4 + 3] = 0.0;
+  }
+}
+
+// ---- 5. truncation ----------------------------------------------------------------------
+// One workgroup per block row; thread 0 walks the row in order (ranks and the FP64 sum of
+// kept squared norms in a fixed order).
+__global__ __launch_bounds__(64) void bsr_truncate_kernel(const int32_t* __restrict__ row_ptrP,
+                                                          const int32_t* __restrict__ colP,
+                                                          const double* __restrict__ normP,
+                                                          double tau2, int32_t* __restrict__ rank,
+                                                          int32_t* __restrict__ cnt,
+                                                          double* __restrict__ partials,
+                                                          int slot0) {
+  const int I = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  int k = 0;
+  double t2 = 0.0;
+  for (int p = row_ptrP[I]; p < row_ptrP[I + 1]; ++p) {
+    const bool keep = (colP[p] == I) || (normP[p] >= tau2);
+    rank[p] = keep ? k : -1;
+    if (keep) {
+      ++k;
+      t2 += normP[p];
+    }
+  }
+  cnt[I] = k;
+  partials[(slot0 + I) * 4 + 0] = 0.0;
+  partials[(slot0 + I) * 4 + 1] = 0.0;
+  partials[(slot0 + I) * 4 + 2] = t2;
+  partials[(slot0 + I) * 4 + 3] = 0.0;
+}
+
+// ---- 6. compaction ----------------------------------------------------------------------
+__global__ __launch_bounds__(256) void bsr_compact_kernel(const int32_t* __restrict__ row_ptrP,
+                                                          const int32_t* __restrict__ colP,
+                                                          const float* __restrict__ valP,
+                                                          const int32_t* __restrict__ rank,
+                                                          const int32_t* __restrict__ row_ptrN,
+                                                          int32_t* __restrict__ colN,
+                                                          float* __restrict__ valN) {
+  const int I = blockIdx.x;
+  for (int p = row_ptrP[I]; p < row_ptrP[I + 1]; ++p) {
+    const int k = rank[p];
+    if (k < 0) continue;
+    const int dst = row_ptrN[I] + k;
+    if (threadIdx.x == 0) colN[dst] = colP[p];
+    const u32x4 v = *(const u32x4*)(valP + (size_t)p * kBB + threadIdx.x * 4);
+    *(u32x4*)(valN + (size_t)dst * kBB + threadIdx.x * 4) = v;
+  }
+}
+
+// ---- f0 on blocks -----------------------------------------------------------------------
+// X_0 = (lambda_max I - F)/(lambda_max - lambda_min), block by block, reading only F's
+// upper blocks (I <= J, upper half of diagonal blocks) and mirroring.
+__global__ __launch_bounds__(256) void bsr_f0_kernel(const int32_t* __restrict__ row_ptrF,
+                                                     const int32_t* __restrict__ colF,
+                                                     const uint32_t* __restrict__ bmF,
+                                                     const int32_t* __restrict__ preF,
+                                                     const float* __restrict__ valF, int W,
+                                                     const SnfState* __restrict__ st,
+                                                     float* __restrict__ valX,
+                                                     double* __restrict__ partials, int nbrows) {
+  __shared__ double red[12];
+  const double lmin = st->lambda_min, lmax = st->lambda_max;
+  double t1 = 0.0, t2 = 0.0;
+  // grid-stride over block rows; every thread handles 4 values of each block
+  for (int I = blockIdx.x; I < nbrows; I += gridDim.x) {
+    for (int p = row_ptrF[I]; p < row_ptrF[I + 1]; ++p) {
+      const int J = colF[p];
+      const int src = (I <= J) ? p : bsr_find(row_ptrF, bmF, preF, W, J, I);
+      for (int e = threadIdx.x; e < kBB; e += blockDim.x) {
+        const int r = e / kB, c = e % kB;
+        float fv;
+        if (I < J) fv = valF[(size_t)src * kBB + r * kB + c];
+        else if (I > J) fv = valF[(size_t)src * kBB + c * kB + r];
+        else fv = (r <= c) ? valF[(size_t)src * kBB + r * kB + c] : valF[(size_t)src * kBB + c * kB + r];
+        const bool d = (I == J && r == c);
+        const double x = ((d ? lmax : 0.0) - (double)fv) / (lmax - lmin);
+        const float xf = (float)x;
+        valX[(size_t)p * kBB + e] = xf;
+        if (d) t1 += (double)xf;
+        t2 += (double)xf * (double)xf;
+      }
+    }
+  }
+  double e0 = 0.0;
+  // fixed-order block sum
+  e0 = bsr_wave_sum(e0);
+  t1 = bsr_wave_sum(t1);
+  t2 = bsr_wave_sum(t2);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wid * 3 + 0] = e0;
+    red[wid * 3 + 1] = t1;
+    red[wid * 3 + 2] = t2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 4 + 0] = 0.0;
+    partials[blockIdx.x * 4 + 1] = ((red[1] + red[4]) + red[7]) + red[10];
+    partials[blockIdx.x * 4 + 2] = ((red[2] + red[5]) + red[8]) + red[11];
+    partials[blockIdx.x * 4 + 3] = 0.0;
+  }
+}
+
+// =========================================================================================
+// Host side
+// =========================================================================================
+static thread_local char g_bsr_err[256];
+
+static int bsr_dev_error(hipError_t e, const char* what) {
+  snprintf(g_bsr_err, sizeof(g_bsr_err), "HIP error in %s: %s", what, hipGetErrorString(e));
+  return SNF_EDEVICE;
+}
+
+#define BSR_HIP(call)                                      \
+  do {                                                     \
+    hipError_t _e = (call);                                \
+    if (_e != hipSuccess) return bsr_dev_error(_e, #call); \
+  } while (0)
+
+// Growable device array.
+template <typename T>
+struct DevArr {
+  T* p = nullptr;
+  size_t cap = 0;
+  int reserve(size_t n) {
+    if (n <= cap) return SNF_OK;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    size_t want = n + n / 4 + 16;
+    if (hipMalloc(&p, want * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      return SNF_ENOMEM;
+    }
+    cap = want;
+    return SNF_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+struct BsrBuf {                 // one BSR matrix owned by the library, with lookup tables
+  DevArr<int32_t> row_ptr, col;
+  DevArr<float> val;
+  DevArr<uint32_t> bm;
+  DevArr<int32_t> pre;
+  int64_t nnzb = 0;
+  void release() {
+    row_ptr.release();
+    col.release();
+    val.release();
+    bm.release();
+    pre.release();
+    nnzb = 0;
+  }
+  BsrMat view() const { return BsrMat{row_ptr.p, bm.p, pre.p, val.p}; }
+};
+
+struct BsrWorkspace {
+  BsrBuf X[2], P, Fl;           // current / next X, candidate product, F's lookup tables
+  DevArr<double> normP, partials, sums;
+  DevArr<int32_t> cnt, rank, tiles;
+  DevArr<uint8_t> flags;
+  SnfState* state = nullptr;
+  SnfState* state_host = nullptr;
+  int32_t* pinned = nullptr;    // scratch for small read-backs
+  size_t pinned_cap = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::mutex mu;
+};
+
+static std::mutex g_bsr_mu;
+static BsrWorkspace* g_bsr_ws[64];
+
+static BsrWorkspace* bsr_workspace() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> g(g_bsr_mu);
+  if (!g_bsr_ws[dev]) g_bsr_ws[dev] = new BsrWorkspace();
+  return g_bsr_ws[dev];
+}
+
+static int ensure_pinned(BsrWorkspace* w, size_t bytes) {
+  if (bytes <= w->pinned_cap) return SNF_OK;
+  if (w->pinned) (void)hipHostFree(w->pinned);
+  w->pinned = nullptr;
+  w->pinned_cap = 0;
+  BSR_HIP(hipHostMalloc((void**)&w->pinned, bytes, hipHostMallocDefault));
+  w->pinned_cap = bytes;
+  return SNF_OK;
+}
+
+// Host-side validation of a BSR pattern: sizes, ascending columns, symmetric pattern and
+// every diagonal block present.
+static int validate_pattern(const snf_bsr* m, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
+                            hipStream_t s) {
+  if (!m || m->b != kB || m->n <= 0 || m->n % kB || m->nb != m->n / kB || m->nnzb < m->nb ||
+      !m->row_ptr || !m->col_idx || !m->val || m->nb > 65535)
+    return SNF_EINVAL;
+  rp.resize(m->nb + 1);
+  ci.resize(m->nnzb);
+  BSR_HIP(hipMemcpyAsync(rp.data(), m->row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, s));
+  BSR_HIP(hipMemcpyAsync(ci.data(), m->col_idx, ci.size() * 4, hipMemcpyDeviceToHost, s));
+  BSR_HIP(hipStreamSynchronize(s));
+  if (rp[0] != 0 || rp[m->nb] != m->nnzb) return SNF_EINVAL;
+  std::vector<std::pair<int, int>> up, lo;
+  for (int i = 0; i < m->nb; ++i) {
+    if (rp[i + 1] < rp[i]) return SNF_EINVAL;
+    bool diag = false;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      const int j = ci[p];
+      if (j < 0 || j >= m->nb) return SNF_EINVAL;
+      if (p > rp[i] && ci[p - 1] >= j) return SNF_EINVAL;
+      if (j == i) diag = true;
+      if (j > i) up.emplace_back(i, j);
+      if (j < i) lo.emplace_back(j, i);
+    }
+    if (!diag) return SNF_EINVAL;
+  }
+  std::sort(lo.begin(), lo.end());
+  if (up != lo) return SNF_EINVAL;   // up is already in (i, j) order
+  return SNF_OK;
+}
+
+static int build_lookup(BsrBuf& b, int nb, int W, hipStream_t s) {
+  int rc = b.bm.reserve((size_t)nb * W);
+  if (rc) return rc;
+  rc = b.pre.reserve((size_t)nb * W);
+  if (rc) return rc;
+  hipLaunchKernelGGL(bsr_bitmap_kernel, dim3(nb), dim3(64), W * sizeof(uint32_t), s, b.row_ptr.p,
+                     b.col.p, W, b.bm.p, b.pre.p);
+  BSR_HIP(hipGetLastError());
+  return SNF_OK;
+}
+
+// exclusive scan of cnt (device, nb) into row_ptr (device, nb + 1) through pinned memory;
+// returns the total
+static int scan_counts(BsrWorkspace* w, const int32_t* cnt_dev, int nb, DevArr<int32_t>& row_ptr,
+                       int64_t* total, hipStream_t s) {
+  int rc = ensure_pinned(w, (size_t)(2 * nb + 2) * sizeof(int32_t));
+  if (rc) return rc;
+  int32_t* h = w->pinned;
+  BSR_HIP(hipMemcpyAsync(h, cnt_dev, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  BSR_HIP(hipStreamSynchronize(s));
+  int32_t* rp = h + nb + 1;
+  int64_t acc = 0;
+  for (int i = 0; i < nb; ++i) {
+    rp[i] = (int32_t)acc;
+    acc += h[i];
+  }
+  rp[nb] = (int32_t)acc;
+  if (acc > INT32_MAX) return SNF_ENOMEM;
+  rc = row_ptr.reserve(nb + 1);
+  if (rc) return rc;
+  BSR_HIP(hipMemcpyAsync(row_ptr.p, rp, (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  *total = acc;
+  return SNF_OK;
+}
+
+// One step on w->X[cur] (lookup tables built): candidate pattern, numeric product (reads
+// the coefficients in the state), truncation, compaction into w->X[1 - cur].  Partial sums
+// land in slots [0, tiles) (product) and [tiles, tiles + nb) (kept norms); *slots = total.
+static int bsr_step(BsrWorkspace* w, int cur, int nb, int W, double tau2, int* slots,
+                    hipEvent_t ev_a, hipEvent_t ev_b, hipStream_t s) {
+  BsrBuf& X = w->X[cur];
+  BsrBuf& N = w->X[1 - cur];
+  BsrBuf& P = w->P;
+  int rc;
+  // 2. symbolic
+  if ((rc = P.bm.reserve((size_t)nb * W)) || (rc = P.pre.reserve((size_t)nb * W)) ||
+      (rc = w->cnt.reserve(nb)))
+    return rc;
+  hipLaunchKernelGGL(bsr_symbolic_kernel, dim3(nb), dim3(64), W * sizeof(uint32_t), s,
+                     X.row_ptr.p, X.col.p, X.bm.p, W, P.bm.p, P.pre.p, w->cnt.p);
+  BSR_HIP(hipGetLastError());
+  int64_t nnzP = 0;
+  if ((rc = scan_counts(w, w->cnt.p, nb, P.row_ptr, &nnzP, s))) return rc;
+  if ((rc = P.col.reserve(nnzP)) || (rc = P.val.reserve((size_t)nnzP * kBB)) ||
+      (rc = w->normP.reserve(nnzP)) || (rc = w->rank.reserve(nnzP)))
+    return rc;
+  P.nnzb = nnzP;
+  hipLaunchKernelGGL(bsr_fill_cols_kernel, dim3(nb), dim3(64), 0, s, P.bm.p, P.pre.p,
+                     P.row_ptr.p, W, P.col.p);
+  // 3. super-tiles
+  const int NT = (nb + kSup - 1) / kSup;
+  if ((rc = w->flags.reserve((size_t)NT * NT))) return rc;
+  const int64_t nflags = (int64_t)NT * NT;
+  hipLaunchKernelGGL(bsr_tile_flags_kernel, dim3((unsigned)((nflags + 255) / 256)), dim3(256), 0,
+                     s, P.bm.p, nb, W, NT, w->flags.p);
+  BSR_HIP(hipGetLastError());
+  if ((rc = ensure_pinned(w, (size_t)nflags + (size_t)nflags * 4 + 128))) return rc;
+  uint8_t* hf = (uint8_t*)w->pinned;
+  BSR_HIP(hipMemcpyAsync(hf, w->flags.p, nflags, hipMemcpyDeviceToHost, s));
+  BSR_HIP(hipStreamSynchronize(s));
+  int32_t* tl = (int32_t*)(hf + ((nflags + 63) / 64) * 64);
+  int ntiles = 0;
+  for (int64_t t = 0; t < nflags; ++t)
+    if (hf[t]) tl[ntiles++] = (int32_t)(((t / NT) << 16) | (t % NT));
+  if ((rc = w->tiles.reserve(ntiles + 1)) || (rc = w->partials.reserve((size_t)(ntiles + nb) * 4)))
+    return rc;
+  // pinned source: the copy runs in stream order, before any later read-back reuses it
+  BSR_HIP(hipMemcpyAsync(w->tiles.p, tl, ntiles * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  // 4. numeric
+  BsrProductArgs args;
+  args.X = X.view();
+  args.P = P.view();
+  args.normP = w->normP.p;
+  args.tiles = w->tiles.p;
+  args.partials = w->partials.p;
+  args.nb = nb;
+  args.W = W;
+  if (ev_a) BSR_HIP(hipEventRecord(ev_a, s));
+  if (ntiles > 0)
+    hipLaunchKernelGGL(bsr_product_kernel, dim3(ntiles), dim3(256), 0, s, w->state, args);
+  if (ev_b) BSR_HIP(hipEventRecord(ev_b, s));
+  BSR_HIP(hipGetLastError());
+  // 5. truncation
+  hipLaunchKernelGGL(bsr_truncate_kernel, dim3(nb), dim3(64), 0, s, P.row_ptr.p, P.col.p,
+                     w->normP.p, tau2, w->rank.p, w->cnt.p, w->partials.p, ntiles);
+  BSR_HIP(hipGetLastError());
+  int64_t nnzN = 0;
+  if ((rc = scan_counts(w, w->cnt.p, nb, N.row_ptr, &nnzN, s))) return rc;
+  if ((rc = N.col.reserve(nnzN)) || (rc = N.val.reserve((size_t)nnzN * kBB))) return rc;
+  N.nnzb = nnzN;
+  // 6. compaction
+  hipLaunchKernelGGL(bsr_compact_kernel, dim3(nb), dim3(256), 0, s, P.row_ptr.p, P.col.p, P.val.p,
+                     w->rank.p, N.row_ptr.p, N.col.p, N.val.p);
+  BSR_HIP(hipGetLastError());
+  *slots = ntiles + nb;
+  return SNF_OK;
+}
+
+static int copy_in(BsrWorkspace* w, const snf_bsr* F, hipStream_t s) {
+  BsrBuf& Fl = w->Fl;
+  int rc;
+  if ((rc = Fl.row_ptr.reserve(F->nb + 1)) || (rc = Fl.col.reserve(F->nnzb))) return rc;
+  BSR_HIP(hipMemcpyAsync(Fl.row_ptr.p, F->row_ptr, (F->nb + 1) * 4, hipMemcpyDeviceToDevice, s));
+  BSR_HIP(hipMemcpyAsync(Fl.col.p, F->col_idx, F->nnzb * 4, hipMemcpyDeviceToDevice, s));
+  Fl.nnzb = F->nnzb;
+  return SNF_OK;
+}
+
+static int make_output(const BsrBuf& X, int64_t n, int nb, snf_bsr** out, hipStream_t s) {
+  snf_bsr* m = (snf_bsr*)calloc(1, sizeof(snf_bsr));
+  if (!m) return SNF_ENOMEM;
+  m->n = n;
+  m->b = kB;
+  m->nb = nb;
+  m->nnzb = X.nnzb;
+  if (hipMalloc(&m->row_ptr, (nb + 1) * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&m->col_idx, (size_t)X.nnzb * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&m->val, (size_t)X.nnzb * kBB * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    snf_bsr_free(m);
+    return SNF_ENOMEM;
+  }
+  BSR_HIP(hipMemcpyAsync(m->row_ptr, X.row_ptr.p, (nb + 1) * 4, hipMemcpyDeviceToDevice, s));
+  BSR_HIP(hipMemcpyAsync(m->col_idx, X.col.p, X.nnzb * 4, hipMemcpyDeviceToDevice, s));
+  BSR_HIP(hipMemcpyAsync(m->val, X.val.p, (size_t)X.nnzb * kBB * 4, hipMemcpyDeviceToDevice, s));
+  *out = m;
+  return SNF_OK;
+}
+
+static int ensure_state(BsrWorkspace* w) {
+  if (!w->state) {
+    BSR_HIP(hipMalloc(&w->state, sizeof(SnfState)));
+    BSR_HIP(hipHostMalloc(&w->state_host, sizeof(SnfState), hipHostMallocDefault));
+    for (int i = 0; i < 4; ++i) BSR_HIP(hipEventCreate(&w->ev[i]));
+  }
+  return SNF_OK;
+}
+
+// X_0 = f_0(F) into w->X[0] (pattern of F) with its lookup tables; partial sums of
+// tr X_0 and ||X_0||_F^2 in slots [0, kF0Blocks).
+static int bsr_init(BsrWorkspace* w, const snf_bsr* F, int W, hipStream_t s) {
+  int rc;
+  const int nb = F->nb;
+  if ((rc = copy_in(w, F, s))) return rc;
+  if ((rc = build_lookup(w->Fl, nb, W, s))) return rc;
+  BsrBuf& X = w->X[0];
+  if ((rc = X.row_ptr.reserve(nb + 1)) || (rc = X.col.reserve(F->nnzb)) ||
+      (rc = X.val.reserve((size_t)F->nnzb * kBB)) || (rc = w->partials.reserve(kF0Blocks * 4)))
+    return rc;
+  X.nnzb = F->nnzb;
+  BSR_HIP(hipMemcpyAsync(X.row_ptr.p, F->row_ptr, (nb + 1) * 4, hipMemcpyDeviceToDevice, s));
+  BSR_HIP(hipMemcpyAsync(X.col.p, F->col_idx, F->nnzb * 4, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(bsr_f0_kernel, dim3(kF0Blocks), dim3(256), 0, s, w->Fl.row_ptr.p,
+                     w->Fl.col.p, w->Fl.bm.p, w->Fl.pre.p, F->val, W, w->state, X.val.p,
+                     w->partials.p, nb);
+  BSR_HIP(hipGetLastError());
+  return build_lookup(X, nb, W, s);
+}
+
+}  // namespace snf
+
+using namespace snf;
+
+extern "C" {
+
+int snf_bsr_copy_out(const snf_bsr* src, int32_t* row_ptr, int32_t* col_idx, float* val,
+                     void* stream) {
+  if (!src || !row_ptr || (src->nnzb > 0 && (!col_idx || !val))) return SNF_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  BSR_HIP(hipMemcpyAsync(row_ptr, src->row_ptr, (src->nb + 1) * sizeof(int32_t),
+                         hipMemcpyDeviceToDevice, s));
+  if (src->nnzb > 0) {
+    BSR_HIP(hipMemcpyAsync(col_idx, src->col_idx, src->nnzb * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, s));
+    BSR_HIP(hipMemcpyAsync(val, src->val, (size_t)src->nnzb * kBB * sizeof(float),
+                           hipMemcpyDeviceToDevice, s));
+  }
+  BSR_HIP(hipStreamSynchronize(s));
+  return SNF_OK;
+}
+
+void snf_bsr_free(snf_bsr* m) {
+  if (!m) return;
+  if (m->row_ptr) (void)hipFree(m->row_ptr);
+  if (m->col_idx) (void)hipFree(m->col_idx);
+  if (m->val) (void)hipFree(m->val);
+  free(m);
+}
+
+int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme,
+                   double trunc_tau, snf_bsr** D_out, snf_result* out, snf_log_rec* log,
+                   int32_t log_cap, void* stream) {
+  if (!out) return SNF_EINVAL;
+  memset(out, 0, sizeof(*out));
+  if (D_out) *D_out = nullptr;
+  auto fail = [&](int rc) {
+    out->status = rc;
+    return rc;
+  };
+  if (!F || !params || !D_out || !(trunc_tau >= 0.0) || !isfinite(trunc_tau)) return fail(SNF_EINVAL);
+  if (scheme != SNF_SP2_TRACE && scheme != SNF_TC2_BETA && scheme != SNF_SNF_VARMU)
+    return fail(SNF_EINVAL);
+  const snf_params& p = *params;
+  if (!isfinite(p.lambda_min) || !isfinite(p.lambda_max) || !(p.lambda_min < p.lambda_max) ||
+      !(p.tol > 0.0) || p.max_iter < 1 || p.max_iter >= SNF_LOG_MAX ||
+      !isfinite(p.homo) || !isfinite(p.lumo) || !(p.homo < p.lumo) ||
+      p.homo < p.lambda_min || p.lumo > p.lambda_max || p.lowp_floor < 0.0 ||
+      !(p.lowp_floor < 0.5) || (scheme == SNF_SP2_TRACE && p.n_occ < 0))
+    return fail(SNF_EINVAL);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> rp, ci;
+  int rc = validate_pattern(F, rp, ci, s);
+  if (rc) return fail(rc);
+  if (p.n_occ > F->n) return fail(SNF_EINVAL);
+  BsrWorkspace* w = bsr_workspace();
+  if (!w) return fail(SNF_EDEVICE);
+  std::lock_guard<std::mutex> guard(w->mu);
+  if ((rc = ensure_state(w))) return fail(rc);
+  const int nb = F->nb, W = (nb + 31) / 32;
+
+  // scalar state: FP32 products, no refinement phase, stagnation stop at the floor
+  SnfState* sh = w->state_host;
+  memset(sh, 0, sizeof(*sh));
+  sh->scheme = scheme;
+  sh->max_iter = p.max_iter;
+  sh->mode = SNF_P_FP32;
+  sh->has_nocc = p.n_occ >= 0;
+  sh->n = F->n;
+  sh->n_occ = p.n_occ;
+  sh->tol = p.tol;
+  sh->lambda_min = p.lambda_min;
+  sh->lambda_max = p.lambda_max;
+  sh->mu = p.mu;
+  sh->xi = p.xi;
+  sh->homo = p.homo;
+  sh->lumo = p.lumo;
+  sh->gap_switch = 0.0;
+  sh->lowp_floor = p.lowp_floor > 0.0 ? p.lowp_floor : 1e-3;
+  sh->beta = sched::alg2_f0(p.lumo, p.lambda_min, p.lambda_max);
+  sh->betabar = sched::alg2_f0(p.homo, p.lambda_min, p.lambda_max);
+  sh->e_hist[0] = sh->e_hist[1] = sh->e_hist[2] = INFINITY;
+  BSR_HIP(hipMemcpyAsync(w->state, sh, sizeof(SnfState), hipMemcpyHostToDevice, s));
+  BSR_HIP(hipEventRecord(w->ev[0], s));
+  if ((rc = bsr_init(w, F, W, s))) return fail(rc);
+  launch_schedule(w->state, w->partials.p, kF0Blocks, 1, s);
+  BSR_HIP(hipGetLastError());
+
+  const double tau2 = trunc_tau * trunc_tau;
+  const bool timing = (p.flags & SNF_FLAG_TIME_PRODUCTS) != 0;
+  double prod_ms = 0.0;
+  int cur = 0;
+  for (int it = 0; it <= p.max_iter; ++it) {
+    int slots = 0;
+    rc = bsr_step(w, cur, nb, W, tau2, &slots, timing ? w->ev[2] : nullptr,
+                  timing ? w->ev[3] : nullptr, s);
+    if (rc) return fail(rc);
+    launch_schedule(w->state, w->partials.p, slots, 0, s);
+    BSR_HIP(hipGetLastError());
+    BSR_HIP(hipMemcpyAsync(sh, w->state, sizeof(SnfState), hipMemcpyDeviceToHost, s));
+    BSR_HIP(hipStreamSynchronize(s));
+    if (timing) {
+      float ms = 0.f;
+      BSR_HIP(hipEventElapsedTime(&ms, w->ev[2], w->ev[3]));
+      prod_ms += ms;
+    }
+    if (sh->stop) break;
+    cur = 1 - cur;
+    if ((rc = build_lookup(w->X[cur], nb, W, s))) return fail(rc);
+  }
+  // the result is the X whose idempotency was certified (the input of the last product)
+  rc = make_output(w->X[cur], F->n, nb, D_out, s);
+  if (rc) return fail(rc);
+  BSR_HIP(hipEventRecord(w->ev[1], s));
+  BSR_HIP(hipStreamSynchronize(s));
+  const int status = sh->stop ? sh->status : SNF_ENOCONV;
+  out->status = status;
+  out->iterations = sh->iter;
+  out->products = sh->products;
+  out->products_fp64 = sh->products_f64;
+  out->products_lowp = sh->products_lowp;
+  out->idem_err = sh->e_last;
+  out->trace = sh->t1;
+  out->trace_err = sh->has_nocc ? sh->t1 - (double)sh->n_occ : 0.0;
+  out->alpha_last = sh->alpha;
+  out->beta_last = sh->beta;
+  out->betabar_last = sh->betabar;
+  const int nrec = sh->nlog < SNF_LOG_MAX ? sh->nlog : SNF_LOG_MAX;
+  for (int i = 0; i < nrec; ++i)
+    out->branch[i] = (uint8_t)(sh->log[i].branch < 0 ? 255 : sh->log[i].branch);
+  if (log && log_cap > 0) memcpy(log, sh->log, (size_t)std::min(nrec, (int)log_cap) * sizeof(snf_log_rec));
+  float ms = 0.f;
+  BSR_HIP(hipEventElapsedTime(&ms, w->ev[0], w->ev[1]));
+  out->device_ms = ms;
+  out->product_ms = prod_ms;
+  out->reserved = (int32_t)std::min<int64_t>(w->X[cur].nnzb, INT32_MAX);  // blocks of D
+  return status;
+}
+
+int snf_step_bsr(const snf_bsr* Xin, double c2, double c1, double c0, double trunc_tau,
+                 snf_bsr** Y_out, double* sums, double* kernel_ms, void* stream) {
+  if (!Y_out || !sums || !(trunc_tau >= 0.0) || !isfinite(c2) || !isfinite(c1) || !isfinite(c0))
+    return SNF_EINVAL;
+  *Y_out = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> rp, ci;
+  int rc = validate_pattern(Xin, rp, ci, s);
+  if (rc) return rc;
+  BsrWorkspace* w = bsr_workspace();
+  if (!w) return SNF_EDEVICE;
+  std::lock_guard<std::mutex> guard(w->mu);
+  if ((rc = ensure_state(w))) return rc;
+  const int nb = Xin->nb, W = (nb + 31) / 32;
+  SnfState* sh = w->state_host;
+  memset(sh, 0, sizeof(*sh));
+  sh->c2 = c2;
+  sh->c1 = c1;
+  sh->c0 = c0;
+  sh->want_e = 1;
+  BSR_HIP(hipMemcpyAsync(w->state, sh, sizeof(SnfState), hipMemcpyHostToDevice, s));
+  BsrBuf& X = w->X[0];
+  if ((rc = X.row_ptr.reserve(nb + 1)) || (rc = X.col.reserve(Xin->nnzb)) ||
+      (rc = X.val.reserve((size_t)Xin->nnzb * kBB)))
+    return rc;
+  X.nnzb = Xin->nnzb;
+  BSR_HIP(hipMemcpyAsync(X.row_ptr.p, Xin->row_ptr, (nb + 1) * 4, hipMemcpyDeviceToDevice, s));
+  BSR_HIP(hipMemcpyAsync(X.col.p, Xin->col_idx, Xin->nnzb * 4, hipMemcpyDeviceToDevice, s));
+  BSR_HIP(hipMemcpyAsync(X.val.p, Xin->val, (size_t)Xin->nnzb * kBB * 4, hipMemcpyDeviceToDevice, s));
+  if ((rc = build_lookup(X, nb, W, s))) return rc;
+  int slots = 0;
+  if ((rc = bsr_step(w, 0, nb, W, trunc_tau * trunc_tau, &slots, w->ev[2], w->ev[3], s))) return rc;
+  if ((rc = ensure_pinned(w, 64)) || (rc = w->sums.reserve(4))) return rc;
+  launch_sum_partials(w->partials.p, slots, w->sums.p, s);
+  BSR_HIP(hipGetLastError());
+  BSR_HIP(hipMemcpyAsync(w->pinned, w->sums.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  rc = make_output(w->X[1], Xin->n, nb, Y_out, s);
+  BSR_HIP(hipStreamSynchronize(s));
+  if (rc) return rc;
+  const double* hs = (const double*)w->pinned;
+  sums[0] = hs[0];
+  sums[1] = hs[1];
+  sums[2] = hs[2];
+  if (kernel_ms) {
+    float ms = 0.f;
+    BSR_HIP(hipEventElapsedTime(&ms, w->ev[2], w->ev[3]));
+    *kernel_ms = ms;
+  }
+  return SNF_OK;
+}
+
+}  // extern "C"

@@ -56,6 +56,12 @@ class Result(ctypes.Structure):
                 ("branch", ctypes.c_uint8 * LOG_MAX)]
 
 
+class Bsr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("b", ctypes.c_int32), ("nb", ctypes.c_int32),
+                ("nnzb", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -76,6 +82,19 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double), vp]
     L.snf_step_dense.restype = ctypes.c_int
+    L.snf_purify_bsr.argtypes = [ctypes.POINTER(Bsr), ctypes.POINTER(Params), i32, dbl,
+                                 ctypes.POINTER(ctypes.POINTER(Bsr)), ctypes.POINTER(Result),
+                                 ctypes.POINTER(LogRec), i32, vp]
+    L.snf_purify_bsr.restype = ctypes.c_int
+    L.snf_step_bsr.argtypes = [ctypes.POINTER(Bsr), dbl, dbl, dbl, dbl,
+                               ctypes.POINTER(ctypes.POINTER(Bsr)),
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                               vp]
+    L.snf_step_bsr.restype = ctypes.c_int
+    L.snf_bsr_copy_out.argtypes = [ctypes.POINTER(Bsr), vp, vp, vp, vp]
+    L.snf_bsr_copy_out.restype = ctypes.c_int
+    L.snf_bsr_free.argtypes = [ctypes.POINTER(Bsr)]
+    L.snf_bsr_free.restype = None
     L.snf_workspace_bytes.argtypes = [i64, i32]
     L.snf_workspace_bytes.restype = ctypes.c_size_t
     L.snf_release_workspace.argtypes = []
@@ -192,3 +211,68 @@ def release_workspace() -> None:
 
 def version() -> str:
     return lib().snf_version().decode()
+
+
+# ---- block-sparse path -------------------------------------------------------------------
+
+def _bsr_struct(row_ptr, col_idx, val, n: int, b: int = 32) -> Bsr:
+    import torch
+    for t, dt, nm in ((row_ptr, torch.int32, "row_ptr"), (col_idx, torch.int32, "col_idx"),
+                      (val, torch.float32, "val")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise TypeError(f"{nm} must be a contiguous {dt} CUDA (HIP) tensor")
+    nb = n // b
+    return Bsr(int(n), int(b), int(nb), int(col_idx.numel()), row_ptr.data_ptr(),
+               col_idx.data_ptr(), val.data_ptr())
+
+
+def _take_bsr(ptr, stream) -> tuple:
+    """Copy a library-allocated snf_bsr into torch tensors and free it."""
+    import torch
+    m = ptr.contents
+    dev = torch.device("cuda", torch.cuda.current_device())
+    rp = torch.empty(m.nb + 1, dtype=torch.int32, device=dev)
+    ci = torch.empty(max(m.nnzb, 1), dtype=torch.int32, device=dev)
+    va = torch.empty((max(m.nnzb, 1), m.b, m.b), dtype=torch.float32, device=dev)
+    rc = lib().snf_bsr_copy_out(ptr, rp.data_ptr(), ci.data_ptr(), va.data_ptr(), stream)
+    lib().snf_bsr_free(ptr)
+    if rc != OK:
+        raise RuntimeError(f"snf_bsr_copy_out: {strerror(rc)}")
+    return rp, ci[:m.nnzb], va[:m.nnzb]
+
+
+def purify_bsr(row_ptr, col_idx, val, n: int, scheme: str = "snf_varmu", *, trunc_tau=1e-6,
+               stream=None, want_log: bool = True, **params) -> tuple:
+    """Purify a symmetric block-sparse F (32x32 FP32 blocks, device tensors).
+    Returns ((row_ptr, col_idx, val) of D as torch tensors, result-dict)."""
+    m = _bsr_struct(row_ptr, col_idx, val, n)
+    p = make_params(**params)
+    res = Result()
+    logs = (LogRec * LOG_MAX)() if want_log else None
+    out = ctypes.POINTER(Bsr)()
+    sh = _stream_handle(stream)
+    rc = lib().snf_purify_bsr(ctypes.byref(m), ctypes.byref(p), SCHEMES[scheme],
+                              float(trunc_tau), ctypes.byref(out), ctypes.byref(res), logs,
+                              LOG_MAX if want_log else 0, sh)
+    if not out:
+        raise RuntimeError(f"snf_purify_bsr: {strerror(rc)} ({rc})")
+    D = _take_bsr(out, sh)
+    d = result_dict(res, logs)
+    d["nnzb"] = int(D[1].numel())
+    return D, d
+
+
+def step_bsr(row_ptr, col_idx, val, n: int, c2: float, c1: float, c0: float,
+             trunc_tau: float = 0.0, stream=None) -> tuple:
+    """Y = truncation of (c2 X.X + c1 X + c0 I).  Returns ((row_ptr, col_idx, val), sums,
+    product-kernel ms)."""
+    m = _bsr_struct(row_ptr, col_idx, val, n)
+    out = ctypes.POINTER(Bsr)()
+    sums = (ctypes.c_double * 3)()
+    ms = ctypes.c_double(0.0)
+    sh = _stream_handle(stream)
+    rc = lib().snf_step_bsr(ctypes.byref(m), c2, c1, c0, float(trunc_tau), ctypes.byref(out),
+                            sums, ctypes.byref(ms), sh)
+    if rc != OK:
+        raise RuntimeError(f"snf_step_bsr: {strerror(rc)} ({rc})")
+    return _take_bsr(out, sh), (sums[0], sums[1], sums[2]), ms.value
