@@ -222,6 +222,45 @@ int snf_bsr_copy_out(const snf_bsr* src, int32_t* row_ptr, int32_t* col_idx, flo
 /* Free a library-allocated snf_bsr (device arrays and the struct).  NULL is ignored. */
 void snf_bsr_free(snf_bsr* m);
 
+/* ---- serving: many independent purifications, continuous batching --------------------
+ * A server owns one device arena of hbm_budget_bytes, a HIP stream and a scheduler thread.
+ * Submitted requests wait in a FIFO queue and are admitted while a slot is free and their
+ * workspace fits in the arena; admitted requests advance together, one product step per
+ * grouped launch (each request keeps its own X, scalar state and partial sums on the
+ * device), finished requests leave and queued ones join between steps.  A request's tile
+ * decomposition and reduction order do not depend on the other requests in flight, so its
+ * result is bitwise the same alone and in any mix.  Created on the current device.
+ */
+typedef struct snf_server snf_server;
+
+/* hbm_budget_bytes: arena size (device memory for all in-flight requests);
+   max_slots: at most this many requests in flight (1..4096).  *out receives the server. */
+int snf_serve_create(size_t hbm_budget_bytes, int32_t max_slots, snf_server** out);
+
+/* Device bytes one request of order n and this precision occupies in the arena. */
+size_t snf_serve_request_bytes(int64_t n, snf_precision precision);
+
+/* Queue a purification of the host n x n FP64 matrix F_host (row-major, copied before the
+ * call returns, so the caller may reuse it).  D_host_out (n x n FP64, row-major) receives D
+ * and must stay valid until snf_serve_poll reports completion.  Never waits for the GPU.
+ * Returns SNF_OK and a ticket; SNF_EINVAL for bad arguments (checked as for
+ * snf_purify_dense); SNF_ENOMEM if the request alone exceeds the budget. */
+int snf_serve_submit(snf_server* server, const double* F_host, int64_t n,
+                     const snf_params* params, snf_scheme scheme, snf_precision precision,
+                     double* D_host_out, uint64_t* ticket);
+
+/* SNF_PENDING while the request is queued or running; otherwise its final status, with
+ * *out filled (when out is not NULL) as snf_purify_dense would fill it.  device_ms = time
+ * from admission to completion.  SNF_EINVAL for an unknown ticket. */
+int snf_serve_poll(snf_server* server, uint64_t ticket, snf_result* out);
+
+/* Per-request latency in milliseconds: ms[0] queued (submit -> admit), ms[1] running
+   (admit -> done), ms[2] total (submit -> done).  SNF_PENDING until done. */
+int snf_serve_timing(snf_server* server, uint64_t ticket, double* ms);
+
+/* Finish every queued and running request, stop the scheduler, release the arena. */
+int snf_serve_destroy(snf_server* server);
+
 /* Bytes of device workspace snf_purify_dense needs for order n (allocated on demand). */
 size_t snf_workspace_bytes(int64_t n, snf_precision precision);
 

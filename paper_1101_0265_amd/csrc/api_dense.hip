@@ -130,7 +130,7 @@ static int ensure_workspace(Workspace* w, int64_t np, int lp_bytes, int partial_
   return SNF_OK;
 }
 
-static int lowp_bytes_for(snf_precision p) {
+int lowp_bytes_for(snf_precision p) {
   switch (p) {
     case SNF_P_FP32:
     case SNF_P_FP32_REF64: return 4;
@@ -139,7 +139,7 @@ static int lowp_bytes_for(snf_precision p) {
   }
 }
 
-static int lowp_kind_for(snf_precision p) {
+int lowp_kind_for(snf_precision p) {
   switch (p) {
     case SNF_P_FP32:
     case SNF_P_FP32_REF64: return kPrecF32;
@@ -164,7 +164,7 @@ static int upload_buffers(Workspace* w, hipStream_t s) {
 // ---- validation -------------------------------------------------------------------------
 static bool finite(double v) { return isfinite(v) != 0; }
 
-static int validate(int64_t n, const snf_params* p, snf_scheme scheme, snf_precision prec) {
+int validate(int64_t n, const snf_params* p, snf_scheme scheme, snf_precision prec) {
   if (!p || n <= 0) return SNF_EINVAL;
   if ((int)scheme < SNF_SP2_TRACE || (int)scheme > SNF_SNF_FIXMU) return SNF_EINVAL;
   if ((int)prec < SNF_P_FP64 || (int)prec > SNF_P_BF16_REF64) return SNF_EINVAL;
@@ -199,8 +199,8 @@ static int validate(int64_t n, const snf_params* p, snf_scheme scheme, snf_preci
   return SNF_OK;
 }
 
-static void init_state(SnfState* s, int64_t n, const snf_params* p, snf_scheme scheme,
-                       snf_precision prec) {
+void init_state(SnfState* s, int64_t n, const snf_params* p, snf_scheme scheme,
+                snf_precision prec) {
   memset(s, 0, sizeof(*s));
   s->scheme = scheme;
   s->max_iter = p->max_iter;
@@ -231,7 +231,7 @@ static void init_state(SnfState* s, int64_t n, const snf_params* p, snf_scheme s
   s->e_hist[0] = s->e_hist[1] = s->e_hist[2] = INFINITY;
 }
 
-static void fill_result(const SnfState* s, snf_result* out, snf_log_rec* log, int log_cap) {
+void fill_result(const SnfState* s, snf_result* out, snf_log_rec* log, int log_cap) {
   memset(out, 0, sizeof(*out));
   out->status = s->status;
   out->iterations = s->iter;

@@ -145,6 +145,11 @@ int num_product_tiles(int64_t np, int sym) {
   return (int)(sym ? nt * (nt + 1) / 2 : nt * nt);
 }
 
+__device__ __forceinline__ int num_product_tiles_dev(int64_t np) {
+  const int64_t nt = np / kTile;
+  return (int)(nt * (nt + 1) / 2);
+}
+
 __device__ __forceinline__ int xcd_remap(int w, int total) {
   const int xcd = w & 7, slot = w >> 3;
   const int base = total >> 3, rem = total & 7;
@@ -331,10 +336,9 @@ __device__ __forceinline__ void store_slice(const AccT (&acc)[4][4], double* spl
 //   read with contiguous, coalesced rows.  MFMA operand of lane l: row/col (l % 16), k (l / 16).
 // ---------------------------------------------------------------------------------------
 template <typename T, int PREC>
-__global__ __launch_bounds__(256, 2) void product_kernel(const SnfState* __restrict__ st,
-                                                         const Buffers* __restrict__ bufs,
-                                                         ProductGrid g) {
-  if (st->stop || st->prec != PREC) return;
+__device__ __forceinline__ void product_body(const SnfState* __restrict__ st,
+                                             const Buffers* __restrict__ bufs,
+                                             const ProductGrid& g, const WorkItem& wi) {
   typedef Mfma<T> M;
   constexpr int BK = M::kBK, LDS_W = kTile + M::kPad;
   constexpr int VE = 16 / sizeof(T);          // elements per 16-byte vector
@@ -348,8 +352,6 @@ __global__ __launch_bounds__(256, 2) void product_kernel(const SnfState* __restr
   const T* A = (PREC == kPrecF64) ? (const T*)bufs->x[st->ia] : (const T*)bufs->lp[st->ia];
   const T* B = (PREC == kPrecF64) ? (const T*)bufs->x[st->ib] : (const T*)bufs->lp[st->ib];
 
-  const int KT = (int)(np / BK);
-  const WorkItem wi = work_item(g, KT);
   int bi, bj;
   tile_coords(wi.tile, (int)(np / kTile), g.sym, bi, bj);
   const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
@@ -423,10 +425,9 @@ __global__ __launch_bounds__(256, 2) void product_kernel(const SnfState* __restr
 //   is 8 consecutive k values of one row / column: lane l holds row (l % 16),
 //   k = 8 (l / 16) .. 8 (l / 16) + 7.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 2) void product_bf16_kernel(const SnfState* __restrict__ st,
-                                                              const Buffers* __restrict__ bufs,
-                                                              ProductGrid g) {
-  if (st->stop || st->prec != kPrecBF16) return;
+__device__ __forceinline__ void product_bf16_body(const SnfState* __restrict__ st,
+                                                  const Buffers* __restrict__ bufs,
+                                                  const ProductGrid& g, const WorkItem& wi) {
   constexpr int BK = 64;                 // bf16 per LDS row per stage = 128 B
   constexpr int LDS_W = BK + 8;          // row stride 144 B
   constexpr int VPR = BK / 8;            // 16-byte vectors per row = 8
@@ -439,8 +440,6 @@ __global__ __launch_bounds__(256, 2) void product_bf16_kernel(const SnfState* __
   const unsigned short* A = (const unsigned short*)bufs->lp[st->ia];
   const unsigned short* B = (const unsigned short*)bufs->lp[st->ib];
 
-  const int KT = (int)(np / BK);
-  const WorkItem wi = work_item(g, KT);
   int bi, bj;
   tile_coords(wi.tile, (int)(np / kTile), g.sym, bi, bj);
   const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
@@ -508,6 +507,21 @@ __global__ __launch_bounds__(256, 2) void product_bf16_kernel(const SnfState* __
   epilogue<false>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), g.sym, bi == bj, g.n, np, ea,
                   e2, t1, t2);
   write_partials(e2, t1, t2, g.partials, wi.tile);
+}
+
+template <typename T, int PREC>
+__global__ __launch_bounds__(256, 2) void product_kernel(const SnfState* __restrict__ st,
+                                                         const Buffers* __restrict__ bufs,
+                                                         ProductGrid g) {
+  if (st->stop || st->prec != PREC) return;
+  product_body<T, PREC>(st, bufs, g, work_item(g, (int)(g.np / Mfma<T>::kBK)));
+}
+
+__global__ __launch_bounds__(256, 2) void product_bf16_kernel(const SnfState* __restrict__ st,
+                                                              const Buffers* __restrict__ bufs,
+                                                              ProductGrid g) {
+  if (st->stop || st->prec != kPrecBF16) return;
+  product_bf16_body(st, bufs, g, work_item(g, (int)(g.np / 64)));
 }
 
 // Fix-up of the split tail tiles: workgroup (t, b) handles MFMA block b = (m, q) of every
@@ -677,10 +691,8 @@ __device__ void finish(SnfState* s, int status) {
   s->stop = 1;
 }
 
-__global__ __launch_bounds__(kReduceThreads) void schedule_kernel(SnfState* __restrict__ s,
-                                                                  const double* __restrict__ partials,
-                                                                  int count, int init) {
-  if (s->stop) return;
+__device__ void schedule_body(SnfState* __restrict__ s, const double* __restrict__ partials,
+                              int count, int init) {
   __shared__ double red[12];
   double e2 = 0.0, t1 = 0.0, t2 = 0.0;
   for (int i = threadIdx.x; i < count; i += kReduceThreads) {
@@ -761,6 +773,13 @@ __global__ __launch_bounds__(kReduceThreads) void schedule_kernel(SnfState* __re
     s->t2 = t2;
     decide(s);
   }
+}
+
+__global__ __launch_bounds__(kReduceThreads) void schedule_kernel(SnfState* __restrict__ s,
+                                                                  const double* __restrict__ partials,
+                                                                  int count, int init) {
+  if (s->stop) return;
+  schedule_body(s, partials, count, init);
 }
 
 void launch_schedule(SnfState* st, const double* partials, int count, int init,
@@ -844,6 +863,101 @@ __global__ void sum_partials_kernel(const double* __restrict__ partials, int cou
 void launch_sum_partials(const double* partials, int count, double* out3, hipStream_t s) {
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kReduceThreads), 0, s, partials, count,
                      out3);
+}
+
+// ---------------------------------------------------------------------------------------
+// Grouped launches over many independent purifications (the serving loop): workgroup b of
+// a launch belongs to active request a with offs[a] <= b < offs[a+1] and computes whole
+// tile b - offs[a] of that request's pending product, exactly as the single-request
+// kernels do (same decomposition, same partial-sum slots), so a request's results do not
+// depend on which other requests share the launch.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ int group_find(const int* __restrict__ offs, int nactive, int b) {
+  int lo = 0, hi = nactive;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (offs[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ ProductGrid slot_grid(const SlotDesc& sd) {
+  ProductGrid g;
+  g.np = sd.np;
+  g.n = sd.n;
+  g.sym = 1;
+  g.dp_tiles = num_product_tiles_dev(sd.np);
+  g.tail_tiles = 0;
+  g.split_s = 1;
+  g.partial_count = g.dp_tiles;
+  g.partials = sd.partials;
+  g.split_buf = nullptr;
+  return g;
+}
+
+template <typename T, int PREC>
+__global__ __launch_bounds__(256, 2) void grouped_product_kernel(const SlotDesc* __restrict__ slots,
+                                                                 const int* __restrict__ active,
+                                                                 const int* __restrict__ offs,
+                                                                 int nactive) {
+  const int a = group_find(offs, nactive, blockIdx.x);
+  const SlotDesc sd = slots[active[a]];
+  if (sd.st->stop || sd.st->prec != PREC) return;
+  const ProductGrid g = slot_grid(sd);
+  WorkItem wi;
+  wi.tile = blockIdx.x - offs[a];
+  wi.piece = -1;
+  wi.kt_begin = 0;
+  wi.kt_end = (int)(sd.np / Mfma<T>::kBK);
+  product_body<T, PREC>(sd.st, sd.bufs, g, wi);
+}
+
+__global__ __launch_bounds__(256, 2) void grouped_product_bf16_kernel(const SlotDesc* __restrict__ slots,
+                                                                      const int* __restrict__ active,
+                                                                      const int* __restrict__ offs,
+                                                                      int nactive) {
+  const int a = group_find(offs, nactive, blockIdx.x);
+  const SlotDesc sd = slots[active[a]];
+  if (sd.st->stop || sd.st->prec != kPrecBF16) return;
+  const ProductGrid g = slot_grid(sd);
+  WorkItem wi;
+  wi.tile = blockIdx.x - offs[a];
+  wi.piece = -1;
+  wi.kt_begin = 0;
+  wi.kt_end = (int)(sd.np / 64);
+  product_bf16_body(sd.st, sd.bufs, g, wi);
+}
+
+__global__ __launch_bounds__(kReduceThreads) void grouped_schedule_kernel(const SlotDesc* __restrict__ slots,
+                                                                          const int* __restrict__ active) {
+  const SlotDesc sd = slots[active[blockIdx.x]];
+  if (sd.st->stop) return;
+  schedule_body(sd.st, sd.partials, num_product_tiles_dev(sd.np), 0);
+}
+
+__global__ void grouped_stop_kernel(const SlotDesc* __restrict__ slots, const int* __restrict__ active,
+                                    int nactive, int32_t* __restrict__ stop_out) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a < nactive) stop_out[a] = slots[active[a]].st->stop;
+}
+
+void launch_grouped_step(int prec_mask, const SlotDesc* slots, const int* active,
+                         const int* offs, int nactive, int total_tiles, int32_t* stop_out,
+                         hipStream_t s) {
+  if (nactive <= 0) return;
+  if (prec_mask & (1 << kPrecF64))
+    hipLaunchKernelGGL((grouped_product_kernel<double, kPrecF64>), dim3(total_tiles),
+                       dim3(kThreads), 0, s, slots, active, offs, nactive);
+  if (prec_mask & (1 << kPrecF32))
+    hipLaunchKernelGGL((grouped_product_kernel<float, kPrecF32>), dim3(total_tiles),
+                       dim3(kThreads), 0, s, slots, active, offs, nactive);
+  if (prec_mask & (1 << kPrecBF16))
+    hipLaunchKernelGGL(grouped_product_bf16_kernel, dim3(total_tiles), dim3(kThreads), 0, s,
+                       slots, active, offs, nactive);
+  hipLaunchKernelGGL(grouped_schedule_kernel, dim3(nactive), dim3(kReduceThreads), 0, s, slots,
+                     active);
+  hipLaunchKernelGGL(grouped_stop_kernel, dim3((nactive + 255) / 256), dim3(256), 0, s, slots,
+                     active, nactive, stop_out);
 }
 
 }  // namespace snf

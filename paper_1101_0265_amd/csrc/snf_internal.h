@@ -109,4 +109,27 @@ void launch_sum_partials(const double* partials, int count, double* out3, hipStr
 
 int num_product_tiles(int64_t np, int sym);
 
+// Host helpers of the dense driver, shared with the serving loop (api_dense.hip).
+int validate(int64_t n, const snf_params* p, snf_scheme scheme, snf_precision prec);
+void init_state(SnfState* s, int64_t n, const snf_params* p, snf_scheme scheme,
+                snf_precision prec);
+void fill_result(const SnfState* s, snf_result* out, snf_log_rec* log, int log_cap);
+int lowp_bytes_for(snf_precision p);
+int lowp_kind_for(snf_precision p);
+
+// One request of a grouped launch (device array, one entry per serving slot).
+struct SlotDesc {
+  SnfState* st;
+  Buffers* bufs;       // device
+  double* partials;    // [tiles][4]
+  int64_t np, n;
+};
+
+// One step of every active request: product variants selected by prec_mask (bit kPrec*),
+// each request's schedule, and the stop flags gathered into stop_out[nactive].
+// offs[a] = first workgroup of active request a (offs[nactive] = total_tiles).
+void launch_grouped_step(int prec_mask, const SlotDesc* slots, const int* active,
+                         const int* offs, int nactive, int total_tiles, int32_t* stop_out,
+                         hipStream_t s);
+
 }  // namespace snf

@@ -95,6 +95,19 @@ def lib() -> ctypes.CDLL:
     L.snf_bsr_copy_out.restype = ctypes.c_int
     L.snf_bsr_free.argtypes = [ctypes.POINTER(Bsr)]
     L.snf_bsr_free.restype = None
+    L.snf_serve_create.argtypes = [ctypes.c_size_t, i32, ctypes.POINTER(vp)]
+    L.snf_serve_create.restype = ctypes.c_int
+    L.snf_serve_request_bytes.argtypes = [i64, i32]
+    L.snf_serve_request_bytes.restype = ctypes.c_size_t
+    L.snf_serve_submit.argtypes = [vp, vp, i64, ctypes.POINTER(Params), i32, i32, vp,
+                                   ctypes.POINTER(ctypes.c_uint64)]
+    L.snf_serve_submit.restype = ctypes.c_int
+    L.snf_serve_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Result)]
+    L.snf_serve_poll.restype = ctypes.c_int
+    L.snf_serve_timing.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+    L.snf_serve_timing.restype = ctypes.c_int
+    L.snf_serve_destroy.argtypes = [vp]
+    L.snf_serve_destroy.restype = ctypes.c_int
     L.snf_workspace_bytes.argtypes = [i64, i32]
     L.snf_workspace_bytes.restype = ctypes.c_size_t
     L.snf_release_workspace.argtypes = []
@@ -276,3 +289,73 @@ def step_bsr(row_ptr, col_idx, val, n: int, c2: float, c1: float, c0: float,
     if rc != OK:
         raise RuntimeError(f"snf_step_bsr: {strerror(rc)} ({rc})")
     return _take_bsr(out, sh), (sums[0], sums[1], sums[2]), ms.value
+
+
+# ---- serving -----------------------------------------------------------------------------
+
+class Server:
+    """Continuous-batching purification server (snf_serve_*): host matrices in, host D out."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 64):
+        self._h = ctypes.c_void_p()
+        rc = lib().snf_serve_create(int(budget_bytes), int(max_slots), ctypes.byref(self._h))
+        if rc != OK:
+            raise RuntimeError(f"snf_serve_create: {strerror(rc)} ({rc})")
+        self._out = {}
+
+    @staticmethod
+    def request_bytes(n: int, precision: str = "fp64") -> int:
+        return int(lib().snf_serve_request_bytes(n, PRECISIONS[precision]))
+
+    def submit(self, F, scheme: str = "snf_varmu", precision: str = "fp64", **params) -> int:
+        import numpy as np
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        n = F.shape[0]
+        D = np.empty((n, n), dtype=np.float64)
+        p = make_params(**params)
+        t = ctypes.c_uint64(0)
+        rc = lib().snf_serve_submit(self._h, F.ctypes.data, n, ctypes.byref(p), SCHEMES[scheme],
+                                    PRECISIONS[precision], D.ctypes.data, ctypes.byref(t))
+        if rc != OK:
+            raise RuntimeError(f"snf_serve_submit: {strerror(rc)} ({rc})")
+        self._out[t.value] = D
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else (D, result-dict)."""
+        res = Result()
+        rc = lib().snf_serve_poll(self._h, ticket, ctypes.byref(res))
+        if rc == PENDING:
+            return None
+        if rc == EINVAL and ticket not in self._out:
+            raise KeyError(ticket)
+        return self._out[ticket], result_dict(res)
+
+    def timing(self, ticket: int) -> tuple:
+        ms = (ctypes.c_double * 3)()
+        rc = lib().snf_serve_timing(self._h, ticket, ms)
+        if rc != OK:
+            raise RuntimeError(f"snf_serve_timing: {strerror(rc)} ({rc})")
+        return ms[0], ms[1], ms[2]
+
+    def wait(self, ticket: int, timeout_s: float = 120.0, sleep_s: float = 2e-4):
+        import time
+        t0 = time.monotonic()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.monotonic() - t0 > timeout_s:
+                raise TimeoutError(f"request {ticket} not done after {timeout_s} s")
+            time.sleep(sleep_s)
+
+    def close(self) -> None:
+        if self._h:
+            lib().snf_serve_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,108 @@
+"""Serving loop (continuous batching) on the GPU.
+
+* a request's D is bitwise the same alone and in a mix of requests of other sizes, schemes
+  and precisions submitted before, with and after it;
+* results match the FP64 oracle (decisions, products, D within 1e-8 sqrt(n) in FP64 mode);
+* admission respects the memory budget: with room for one request at a time the run
+  intervals do not overlap; a request larger than the budget fails at submit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import dense  # noqa: E402
+from paper_1101_0265_amd import hamiltonians as H  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def snf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1101_0265_amd import snf as s
+    s.lib()
+    return s
+
+
+def _req(n, n_occ, seed, gap=0.04):
+    mu = -1.0 + 2.0 * n_occ / n
+    return H.random_spectrum_hamiltonian(n, n_occ, -1.0, mu - gap / 2, mu + gap / 2, 1.0, seed)
+
+
+def _kw(h, tol=1e-10):
+    return dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
+                lumo=h.lumo, mu=h.mu, xi=h.xi, tol=tol, max_iter=150)
+
+
+GB = 1 << 30
+
+
+@pytest.mark.parametrize("scheme,prec", [("snf_varmu", "fp64"), ("snf_fixmu", "fp64"),
+                                         ("snf_varmu", "fp32_ref64"), ("sp2", "bf16_ref64")])
+def test_alone_equals_mix_bitwise(snf, scheme, prec):
+    target = _req(300, 140, seed=42)
+    others = [(_req(n, n // 2 + 3, seed=n), s, p) for n, s, p in
+              [(64, "sp2", "fp64"), (900, "snf_varmu", "fp32_ref64"), (130, "mcweeny", "fp64"),
+               (513, "tc2", "fp64"), (77, "snf_fixmu", "bf16_ref64"), (1000, "snf_varmu", "fp64")]]
+    with snf.Server(4 * GB, max_slots=16) as sv:
+        t = sv.submit(target.F, scheme, prec, **_kw(target))
+        D_alone, r_alone = sv.wait(t)
+        D_alone = D_alone.copy()
+    with snf.Server(4 * GB, max_slots=16) as sv:
+        tickets = [sv.submit(h.F, s, p, **_kw(h)) for h, s, p in others[:3]]
+        t = sv.submit(target.F, scheme, prec, **_kw(target))
+        tickets += [sv.submit(h.F, s, p, **_kw(h)) for h, s, p in others[3:]]
+        D_mix, r_mix = sv.wait(t)
+        others_res = [sv.wait(x) for x in tickets]
+    assert r_alone["status"] == r_mix["status"] == "ok"
+    assert np.array_equal(D_alone, D_mix)
+    assert r_alone["products"] == r_mix["products"] and r_alone["branches"] == r_mix["branches"]
+    for (h, s, p), (D, r) in zip(others, others_res):
+        assert r["status"] == "ok", (h.n, s, p, r["status"])
+        assert abs(r["trace_err"]) <= 1e-8
+    o = dense.purify(target.F, scheme, **_kw(target))
+    err = np.linalg.norm(D_mix - o["D"])
+    print(f"\n{scheme} {prec}: |D-D_oracle|_F = {err:.2e}")
+    if prec == "fp64":
+        assert r_mix["branches"] == o["branches"] and r_mix["products"] == o["products"]
+        assert err <= 1e-8 * math.sqrt(target.n)
+
+
+def test_results_match_oracle_fp64(snf):
+    hs = [_req(n, n // 2 - 5, seed=100 + n, gap=0.08) for n in (64, 200, 385, 640)]
+    with snf.Server(2 * GB, max_slots=8) as sv:
+        tickets = [sv.submit(h.F, "snf_varmu", "fp64", **_kw(h)) for h in hs]
+        results = [sv.wait(t) for t in tickets]
+    for h, (D, r) in zip(hs, results):
+        o = dense.purify(h.F, "snf_varmu", **_kw(h))
+        assert r["status"] == o["status"] == "ok"
+        assert r["branches"] == o["branches"] and r["products"] == o["products"]
+        assert np.linalg.norm(D - o["D"]) <= 1e-8 * math.sqrt(h.n)
+
+
+def test_budget_serialises_admission(snf):
+    n = 500
+    one = snf.Server.request_bytes(n, "fp64")
+    hs = [_req(n, 240, seed=s) for s in range(4)]
+    with snf.Server(int(one * 1.5), max_slots=8) as sv:
+        tickets = [sv.submit(h.F, "snf_varmu", "fp64", **_kw(h)) for h in hs]
+        for t in tickets:
+            _, r = sv.wait(t)
+            assert r["status"] == "ok"
+        times = [sv.timing(t) for t in tickets]
+        with pytest.raises(RuntimeError):                  # larger than the whole budget
+            sv.submit(_req(900, 400, seed=9).F, "snf_varmu", "fp64",
+                      **_kw(_req(900, 400, seed=9)))
+    # queued time grows along the FIFO: each request waited for the previous one
+    q = [t[0] for t in times]
+    assert q[1] > 0 and q[3] > q[1]
+
+
+def test_unknown_ticket(snf):
+    with snf.Server(GB // 4, max_slots=2) as sv:
+        with pytest.raises(KeyError):
+            sv.poll(12345)
