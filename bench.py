@@ -72,12 +72,196 @@ def cpu_baseline(h, kw):
                         "X^2 separately for its check)"))
 
 
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max((i.get("num_threads", 1) for i in threadpool_info()
+                    if i.get("user_api") == "blas"), default=os.cpu_count())
+    except Exception:  # noqa: BLE001
+        return os.cpu_count()
+
+
+def _base_line(metric, value, unit, args, higher, dtype, config):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": None, "higher_is_better": higher,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": config}
+
+
+def run_small(args):
+    """n = 256, gap 0.05 about mu = 0, tol 1e-10: latency of each scheme (FP64)."""
+    import torch
+    from paper_1101_0265_amd import hamiltonians as H
+    from paper_1101_0265_amd import snf
+    h = H.small_gap_256()
+    F = torch.tensor(h.F, device="cuda:0")
+    D = torch.empty_like(F)
+    kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
+              lumo=h.lumo, mu=h.mu, xi=h.xi, tol=1e-10, max_iter=100)
+    out = {}
+    for scheme in ("snf_varmu", "snf_fixmu", "sp2", "tc2", "mcweeny"):
+        for _ in range(args.warmup):
+            snf.purify_dense(F, scheme, out=D, want_log=False, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, r = snf.purify_dense(F, scheme, out=D, want_log=False, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        out[scheme] = dict(ms=round(ms, 4), products=r["products"], status=r["status"],
+                           device_ms=round(r["device_ms"], 4))
+    line = _base_line("time-to-solution ms at ‖X²−X‖≤1e-10, SnF vs SP2 (n=256)",
+                      out["snf_varmu"]["ms"], "ms", args, False, "f64",
+                      {"workload": "dense FP64 n=256, spectrum [-1,-0.025] u [0.025,1], Haar Q "
+                                   "(seed 1101), N_occ=128, tol 1e-10"})
+    line["ms_per_step"] = out["snf_varmu"]["ms"]
+    line["schemes"] = out
+    line["speedup_vs_sp2"] = round(out["sp2"]["ms"] / out["snf_varmu"]["ms"], 3)
+    from oracle import dense
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        dense.purify(h.F, "snf_varmu", **kw)
+    cpu_ms = (time.perf_counter() - t0) * 1e3 / reps
+    line["cpu_baseline"] = dict(value=round(cpu_ms, 3), unit="ms", cores=int(_blas_threads()),
+                                kind="oracle", sample=f"{reps} solves of the same n=256 input")
+    return line
+
+
+def run_bsr(args):
+    """Block-sparse lattice 32x32x32 sites (n = 65536, 32x32 FP32 blocks, tau = 1e-6):
+    time to the truncation floor, SnF varying-mu vs the trace scheme."""
+    import numpy as np
+    import torch
+    from paper_1101_0265_amd import hamiltonians as H
+    from paper_1101_0265_amd import snf
+    L = (32, 32, 32)
+    m, h = H.lattice_bsr(L, seed=3)
+    rp = torch.tensor(m.row_ptr, device="cuda:0")
+    ci = torch.tensor(m.col_idx, device="cuda:0")
+    va = torch.tensor(m.val, device="cuda:0")
+    kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
+              lumo=h.lumo, tol=1e-9, max_iter=80, flags=snf.FLAG_TIME_PRODUCTS)
+    res = {}
+    for scheme in ("snf_varmu", "sp2"):
+        for _ in range(args.warmup):
+            snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=1e-6, want_log=False, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = max(1, args.steps)
+        for _ in range(steps):
+            D, r = snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=1e-6, want_log=False, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[scheme] = dict(ms=round(ms, 1), products=r["products"], status=r["status"],
+                           idem_err=r["idem_err"], trace_err=r["trace_err"],
+                           blocks_D=r["blocks"], blocks_per_row=round(r["blocks"] / m.nb, 1),
+                           product_ms=round(r["product_ms"], 1),
+                           useful_tflops=round(r["flops"] / (r["product_ms"] * 1e-3) / 1e12, 2))
+        del D
+    s = res["snf_varmu"]
+    line = _base_line("time-to-solution ms at the truncation floor (block-sparse), SnF vs SP2",
+                      s["ms"], "ms", args, False, "f32",
+                      {"workload": "BSR two-orbital lattice 32x32x32 sites, n=65536, 32x32 "
+                                   "blocks (4x2x2-site bricks, Morton order), tau=1e-6, half "
+                                   "filling", "scheme": "snf_varmu"})
+    line["ms_per_step"] = s["ms"]
+    line["schemes"] = res
+    line["speedup_vs_sp2"] = round(res["sp2"]["ms"] / s["ms"], 3)
+    line["roofline"] = dict(bound="mfma", achieved=s["useful_tflops"], peak=157.3,
+                            unit="TFLOP/s", frac=round(s["useful_tflops"] / 157.3, 4),
+                            traffic=None, kernel="bsr_product_kernel (f32 MFMA super-tiles)",
+                            note="achieved = 2*32^3 flops per stored-block triple (I,K,J), "
+                                 "I<=J, over the summed numeric-kernel time")
+    line["cpu_baseline"] = None
+    return line
+
+
+def run_serve(args):
+    """512 requests: n log-uniform in [64, 2048], gap log-uniform in [1e-3, 1e-1],
+    N_occ = n/2 (1 +- 0.1), FP32 products + FP64 refinement, SnF varying-mu; a closed-loop
+    pass measures saturated throughput, then Poisson arrivals at 0.8 of it."""
+    import numpy as np
+    import torch
+    from paper_1101_0265_amd import hamiltonians as H
+    from paper_1101_0265_amd import snf
+    count = 512
+    trace = H.serving_trace(count=count, rate_per_s=1.0, seed=5)
+    mats = [H.request_hamiltonian_torch(r, device="cuda:0") for r in trace]
+    torch.cuda.synchronize()
+
+    def kw(h):
+        return dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ,
+                    homo=h.homo, lumo=h.lumo, tol=1e-8, max_iter=120, gap_switch=0.0)
+
+    budget = 24 << 30
+    flops = 0.0
+    with snf.Server(budget, max_slots=64) as sv:
+        # warm-up on a few requests
+        for h in mats[:args.warmup * 4]:
+            sv.wait(sv.submit(h.F, "snf_varmu", "fp32_ref64", **kw(h)))
+        t0 = time.perf_counter()
+        tickets = [sv.submit(h.F, "snf_varmu", "fp32_ref64", **kw(h)) for h in mats]
+        for t in tickets:
+            _, r = sv.wait(t)
+            flops += r["flops"]
+        closed_s = time.perf_counter() - t0
+    closed_rate = count / closed_s
+    rate = 0.8 * closed_rate
+    gaps = np.random.default_rng(55).exponential(1.0 / rate, size=count)
+    arrivals = np.cumsum(gaps)
+    lat, statuses = [], []
+    with snf.Server(budget, max_slots=64) as sv:
+        tickets = []
+        t0 = time.perf_counter()
+        for h, ta in zip(mats, arrivals):
+            while time.perf_counter() - t0 < ta:
+                time.sleep(5e-5)
+            tickets.append(sv.submit(h.F, "snf_varmu", "fp32_ref64", **kw(h)))
+        for t in tickets:
+            _, r = sv.wait(t)
+            statuses.append(r["status"])
+            lat.append(sv.timing(t)[2])
+        open_s = time.perf_counter() - t0
+    lat = np.array(lat)
+    line = _base_line("solves/s, continuous batching (512 requests, FP32 + FP64 refinement)",
+                      round(count / open_s, 2), "solves/s", args, True, "f32+f64",
+                      {"workload": "serving: 512 requests, n log-uniform [64,2048], gap "
+                                   "log-uniform [1e-3,1e-1], N_occ=n/2(1+-0.1), Haar Q per "
+                                   "request, SnF varying-mu, fp32_ref64",
+                       "arrival_rate_per_s": round(rate, 2), "hbm_budget_gb": budget >> 30,
+                       "max_slots": 64})
+    line["latency_ms"] = dict(p50=round(float(np.percentile(lat, 50)), 2),
+                              p99=round(float(np.percentile(lat, 99)), 2),
+                              mean=round(float(lat.mean()), 2))
+    line["closed_loop_solves_per_s"] = round(closed_rate, 2)
+    line["closed_loop_tflops"] = round(flops / closed_s / 1e12, 2)
+    line["statuses"] = {s_: statuses.count(s_) for s_ in set(statuses)}
+    # oracle on a bounded sample of the same trace (the requests with n <= 700)
+    from oracle import dense
+    sample = [(mats[i], trace[i]) for i in range(count) if trace[i].n <= 700][:24]
+    t0 = time.perf_counter()
+    for h, _ in sample:
+        dense.purify(h.F, "snf_varmu", **{k: v for k, v in kw(h).items() if k != "gap_switch"})
+    cpu_s = time.perf_counter() - t0
+    line["cpu_baseline"] = dict(value=round(len(sample) / cpu_s, 2), unit="solves/s",
+                                cores=int(_blas_threads()), kind="oracle",
+                                sample=f"{len(sample)} requests of the trace with n <= 700 "
+                                       "(FP64 numpy), solved one after another")
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="dense",
+                    choices=["dense", "small", "bsr", "serve"],
+                    help="dense: n=4096 lattice (default line); small: n=256 gap-0.05 latency "
+                         "of all five schemes; bsr: block-sparse 32^3-site lattice n=65536; "
+                         "serve: 512-request continuous-batching trace")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for hardware-counter runs: a plain 512 MiB device copy (counter "
                          "calibration), then three FP64 products of the workload's X_0")
@@ -97,6 +281,10 @@ def main():
         sys.exit(1)
     snf.lib()
     dev = torch.device("cuda:0")
+    if args.workload != "dense":
+        line = {"small": run_small, "bsr": run_bsr, "serve": run_serve}[args.workload](args)
+        print(json.dumps(line), flush=True)
+        return
     h = H.lattice_hamiltonian(LATTICE, seed=2)
     n = h.n
     F = torch.tensor(h.F, device=dev)

@@ -138,6 +138,10 @@ typedef struct {
   double device_ms;       /* f_0 through the copy-out of D, HIP events on `stream`      */
   double product_ms;      /* summed product-kernel time (SNF_FLAG_TIME_PRODUCTS)        */
   uint8_t branch[SNF_LOG_MAX]; /* SNF_BRANCH_* of iteration i                            */
+  double flops;           /* algorithmic flops of all products: n^2 (n+1) each (only the
+                             upper triangle of a symmetric product is needed); block-sparse:
+                             2 b^3 per block triple (I,K,J), I <= J, of stored blocks      */
+  int64_t blocks;         /* block-sparse: stored blocks of D (0 for dense)             */
 } snf_result;
 
 /*

@@ -244,6 +244,9 @@ void fill_result(const SnfState* s, snf_result* out, snf_log_rec* log, int log_c
   out->alpha_last = s->alpha;
   out->beta_last = s->beta;
   out->betabar_last = s->betabar;
+  const double nd = (double)s->n;
+  out->flops = (double)s->products * nd * nd * (nd + 1.0);
+  out->blocks = 0;
   const int nrec = s->nlog < SNF_LOG_MAX ? s->nlog : SNF_LOG_MAX;
   for (int i = 0; i < nrec && i < SNF_LOG_MAX; ++i)
     out->branch[i] = (uint8_t)(s->log[i].branch < 0 ? 255 : s->log[i].branch);

@@ -87,16 +87,25 @@ __global__ __launch_bounds__(64) void bsr_bitmap_kernel(const int32_t* __restric
 __global__ __launch_bounds__(64) void bsr_symbolic_kernel(const int32_t* __restrict__ row_ptr,
                                                           const int32_t* __restrict__ col_idx,
                                                           const uint32_t* __restrict__ bm, int W,
+                                                          const int32_t* __restrict__ pre,
                                                           uint32_t* __restrict__ bmP,
                                                           int32_t* __restrict__ preP,
-                                                          int32_t* __restrict__ cntP) {
+                                                          int32_t* __restrict__ cntP,
+                                                          int64_t* __restrict__ triples) {
   extern __shared__ uint32_t acc[];
   const int I = blockIdx.x;
   for (int w = threadIdx.x; w < W; w += blockDim.x) acc[w] = 0u;
+  int64_t tri = 0;   // block triples (I, K, J), J >= I: the useful work of row I
   for (int p = row_ptr[I]; p < row_ptr[I + 1]; ++p) {
     const int K = col_idx[p];
     for (int w = threadIdx.x; w < W; w += blockDim.x) acc[w] |= bm[(size_t)K * W + w];
+    if (threadIdx.x == 0) {
+      const uint32_t word = bm[(size_t)K * W + (I >> 5)];
+      const int below = pre[(size_t)K * W + (I >> 5)] + __popc(word & ((1u << (I & 31)) - 1u));
+      tri += (row_ptr[K + 1] - row_ptr[K]) - below;
+    }
   }
+  if (threadIdx.x == 0) triples[I] = tri;
   __syncthreads();
   for (int w = threadIdx.x; w < W; w += blockDim.x) bmP[(size_t)I * W + w] = acc[w];
   if (threadIdx.x == 0) {
@@ -516,6 +525,8 @@ struct BsrWorkspace {
   BsrBuf X[2], P, Fl;           // current / next X, candidate product, F's lookup tables
   DevArr<double> normP, partials, sums;
   DevArr<int32_t> cnt, rank, tiles;
+  DevArr<int64_t> triples;
+  int64_t last_triples = 0;
   DevArr<uint8_t> flags;
   SnfState* state = nullptr;
   SnfState* state_host = nullptr;
@@ -626,11 +637,21 @@ static int bsr_step(BsrWorkspace* w, int cur, int nb, int W, double tau2, int* s
   if ((rc = P.bm.reserve((size_t)nb * W)) || (rc = P.pre.reserve((size_t)nb * W)) ||
       (rc = w->cnt.reserve(nb)))
     return rc;
+  if ((rc = w->triples.reserve(nb))) return rc;
   hipLaunchKernelGGL(bsr_symbolic_kernel, dim3(nb), dim3(64), W * sizeof(uint32_t), s,
-                     X.row_ptr.p, X.col.p, X.bm.p, W, P.bm.p, P.pre.p, w->cnt.p);
+                     X.row_ptr.p, X.col.p, X.bm.p, W, X.pre.p, P.bm.p, P.pre.p, w->cnt.p,
+                     w->triples.p);
   BSR_HIP(hipGetLastError());
   int64_t nnzP = 0;
   if ((rc = scan_counts(w, w->cnt.p, nb, P.row_ptr, &nnzP, s))) return rc;
+  {
+    // useful block triples of this product (the symbolic kernel finished: scan synced)
+    std::vector<int64_t> tri(nb);
+    BSR_HIP(hipMemcpy(tri.data(), w->triples.p, nb * sizeof(int64_t), hipMemcpyDeviceToHost));
+    int64_t t = 0;
+    for (int i = 0; i < nb; ++i) t += tri[i];
+    w->last_triples = t;
+  }
   if ((rc = P.col.reserve(nnzP)) || (rc = P.val.reserve((size_t)nnzP * kBB)) ||
       (rc = w->normP.reserve(nnzP)) || (rc = w->rank.reserve(nnzP)))
     return rc;
@@ -837,7 +858,7 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
 
   const double tau2 = trunc_tau * trunc_tau;
   const bool timing = (p.flags & SNF_FLAG_TIME_PRODUCTS) != 0;
-  double prod_ms = 0.0;
+  double prod_ms = 0.0, flops = 0.0;
   int cur = 0;
   for (int it = 0; it <= p.max_iter; ++it) {
     int slots = 0;
@@ -853,6 +874,7 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
       BSR_HIP(hipEventElapsedTime(&ms, w->ev[2], w->ev[3]));
       prod_ms += ms;
     }
+    flops += 2.0 * kB * kB * kB * (double)w->last_triples;
     if (sh->stop) break;
     cur = 1 - cur;
     if ((rc = build_lookup(w->X[cur], nb, W, s))) return fail(rc);
@@ -882,7 +904,8 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
   BSR_HIP(hipEventElapsedTime(&ms, w->ev[0], w->ev[1]));
   out->device_ms = ms;
   out->product_ms = prod_ms;
-  out->reserved = (int32_t)std::min<int64_t>(w->X[cur].nnzb, INT32_MAX);  // blocks of D
+  out->flops = flops;
+  out->blocks = w->X[cur].nnzb;
   return status;
 }
 

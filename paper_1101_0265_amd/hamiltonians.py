@@ -402,3 +402,29 @@ def request_hamiltonian(req: Request) -> Hamiltonian:
     homo, lumo = centre - 0.5 * xi, centre + 0.5 * xi
     return random_spectrum_hamiltonian(n, k, -1.0, homo, lumo, 1.0, req.seed,
                                        name=f"req-n{n}")
+
+
+def request_hamiltonian_torch(req: Request, device: str = "cuda:0") -> Hamiltonian:
+    """As ``request_hamiltonian`` but with the Haar rotation drawn and applied on the GPU
+    (torch, seeded per request), for traces too large for host QR; F is returned on the host.
+    """
+    import torch
+
+    n, k, xi = req.n, req.n_occ, req.xi
+    centre = -1.0 + 2.0 * k / n
+    centre = min(max(centre, -1.0 + xi), 1.0 - xi)
+    homo, lumo = centre - 0.5 * xi, centre + 0.5 * xi
+    rng = np.random.default_rng(req.seed)
+    lam = two_interval_spectrum(k, n - k, -1.0, homo, lumo, 1.0, rng)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(req.seed))
+    z = torch.randn(n, n, generator=g, device=device, dtype=torch.float64)
+    q, r = torch.linalg.qr(z)
+    d = torch.sign(torch.diagonal(r))
+    d[d == 0] = 1.0
+    q = q * d[None, :]
+    f = (q * torch.tensor(lam, device=device)[None, :]) @ q.T
+    f = 0.5 * (f + f.T)
+    return Hamiltonian(name=f"req-n{n}", F=f.cpu().numpy(), n_occ=k, lambda_min=-1.0,
+                       lambda_max=1.0, homo=float(homo), lumo=float(lumo),
+                       mu=0.5 * (homo + lumo), xi=float(lumo - homo), eigvals=lam, Q=None)

@@ -53,7 +53,8 @@ class Result(ctypes.Structure):
                 ("trace_err", ctypes.c_double), ("alpha_last", ctypes.c_double),
                 ("beta_last", ctypes.c_double), ("betabar_last", ctypes.c_double),
                 ("device_ms", ctypes.c_double), ("product_ms", ctypes.c_double),
-                ("branch", ctypes.c_uint8 * LOG_MAX)]
+                ("branch", ctypes.c_uint8 * LOG_MAX), ("flops", ctypes.c_double),
+                ("blocks", ctypes.c_int64)]
 
 
 class Bsr(ctypes.Structure):
@@ -159,7 +160,7 @@ def result_dict(res: Result, log_arr=None) -> dict:
              idem_err=res.idem_err, trace=res.trace, trace_err=res.trace_err,
              alpha_last=res.alpha_last, beta_last=res.beta_last,
              betabar_last=res.betabar_last, device_ms=res.device_ms,
-             product_ms=res.product_ms,
+             product_ms=res.product_ms, flops=res.flops, blocks=res.blocks,
              branches="".join(BRANCH_LETTERS.get(res.branch[i], "")
                               for i in range(res.iterations)))
     if log_arr is not None:

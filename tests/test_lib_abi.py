@@ -47,7 +47,7 @@ def test_binding_structs_match_header():
     from paper_1101_0265_amd import snf
     assert ctypes.sizeof(snf.Params) == 6 * 8 + 8 + 8 + 4 + 4 + 8 + 8
     assert ctypes.sizeof(snf.LogRec) == 4 * 4 + 6 * 8
-    assert ctypes.sizeof(snf.Result) == 6 * 4 + 8 * 8 + snf.LOG_MAX
+    assert ctypes.sizeof(snf.Result) == 6 * 4 + 8 * 8 + snf.LOG_MAX + 8 + 8
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
