@@ -253,6 +253,14 @@ int snf_serve_submit(snf_server* server, const double* F_host, int64_t n,
                      const snf_params* params, snf_scheme scheme, snf_precision precision,
                      double* D_host_out, uint64_t* ticket);
 
+/* As snf_serve_submit, for inputs already resident on the server's device: F_dev (n x n
+ * FP64, row-major, device) is read when the request is admitted and must stay unchanged
+ * until completion; D_dev_out (n x n FP64, row-major, device, not aliasing F_dev) receives
+ * D.  No host staging and no PCIe transfer of the matrices. */
+int snf_serve_submit_device(snf_server* server, const double* F_dev, int64_t n,
+                            const snf_params* params, snf_scheme scheme,
+                            snf_precision precision, double* D_dev_out, uint64_t* ticket);
+
 /* SNF_PENDING while the request is queued or running; otherwise its final status, with
  * *out filled (when out is not NULL) as snf_purify_dense would fill it.  device_ms = time
  * from admission to completion.  SNF_EINVAL for an unknown ticket. */

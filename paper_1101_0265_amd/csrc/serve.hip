@@ -78,11 +78,20 @@ struct ServeRequest {
   snf_params params;
   snf_scheme scheme;
   snf_precision prec;
-  std::vector<double> F;
+  bool device_io = false;        // F and D are device buffers of the caller
+  const double* F_dev = nullptr;
+  double* D_dev = nullptr;
   double* D_host = nullptr;
+  std::vector<double> F_pageable;   // host F when no pinned staging was free at submit
+  bool pinned = false;              // pinned block [F | D | state] (host) or [state] (device)
+  size_t pin_off = 0, pin_bytes = 0;
+  double* F_pin = nullptr;
+  double* D_pin = nullptr;
+  SnfState* st_pin = nullptr;
   Clock::time_point t_submit, t_admit, t_done;
   int slot = -1;
   size_t off = 0, bytes = 0;
+  hipEvent_t ev = nullptr;
   int status = SNF_PENDING;
   snf_result result;
 };
@@ -113,6 +122,13 @@ static RequestLayout request_layout(int64_t n, snf_precision prec) {
   return L;
 }
 
+static size_t pinned_bytes(const ServeRequest* r) {
+  const size_t st = (sizeof(SnfState) + 255) & ~(size_t)255;
+  if (r->device_io) return st;
+  const size_t mat = ((size_t)r->n * r->n * sizeof(double) + 255) & ~(size_t)255;
+  return 2 * mat + st;
+}
+
 }  // namespace snf
 
 using namespace snf;
@@ -122,8 +138,11 @@ struct snf_server {
   hipStream_t stream = nullptr;
   size_t budget = 0;
   int max_slots = 0;
-  char* arena_base = nullptr;
+  char* arena_base = nullptr;     // device arena (the HBM budget)
   Arena arena;
+  char* pin_base = nullptr;       // pinned host staging arena
+  size_t pin_size = 0;
+  Arena pin_arena;
   // device tables, one entry per slot
   SnfState* states = nullptr;
   Buffers* bufs = nullptr;
@@ -131,21 +150,23 @@ struct snf_server {
   int* active_dev = nullptr;     // [max_slots]
   int* offs_dev = nullptr;       // [max_slots + 1]
   int32_t* stop_dev = nullptr;   // [max_slots]
-  // pinned host staging
+  // pinned host staging of the tables
   SnfState* state_stage = nullptr;   // [max_slots]
   Buffers* bufs_stage = nullptr;     // [max_slots]
   SlotDesc* desc_stage = nullptr;    // [max_slots]
   int* index_stage = nullptr;        // [2 * max_slots + 1]
   int32_t* stop_stage = nullptr;     // [max_slots]
   // host bookkeeping
-  std::thread thread;
+  std::thread thread, finisher;
   std::mutex mu;
-  std::condition_variable cv;
+  std::condition_variable cv, fin_cv;
   std::deque<ServeRequest*> pending;
+  std::deque<ServeRequest*> finishing;
   std::vector<ServeRequest*> slot_req;
   std::unordered_map<uint64_t, ServeRequest*> by_ticket;
+  std::vector<hipEvent_t> free_events;
   uint64_t next_ticket = 1;
-  bool stopping = false;
+  bool stopping = false, sched_done = false;
   int sticky_error = SNF_OK;
 };
 
@@ -153,27 +174,56 @@ namespace snf {
 
 static void fail_all_locked(snf_server* sv, int rc) {
   sv->sticky_error = rc;
-  for (ServeRequest* r : sv->slot_req)
-    if (r) {
-      r->status = rc;
-      r->result.status = rc;
-      r->t_done = Clock::now();
-    }
-  std::fill(sv->slot_req.begin(), sv->slot_req.end(), nullptr);
-  for (ServeRequest* r : sv->pending) {
+  auto fail = [&](ServeRequest* r) {
     r->status = rc;
     r->result.status = rc;
     r->t_done = Clock::now();
-  }
+  };
+  for (ServeRequest* r : sv->slot_req)
+    if (r) fail(r);
+  std::fill(sv->slot_req.begin(), sv->slot_req.end(), nullptr);
+  for (ServeRequest* r : sv->pending) fail(r);
   sv->pending.clear();
 }
 
-#define SV_HIP(call)                          \
-  do {                                        \
+// Pinned staging for a request (caller holds the lock).  Host mode copies F in here.
+static bool take_pinned_locked(snf_server* sv, ServeRequest* r) {
+  size_t off = 0;
+  const size_t bytes = pinned_bytes(r);
+  if (!sv->pin_base || !sv->pin_arena.alloc(bytes, &off)) return false;
+  r->pinned = true;
+  r->pin_off = off;
+  r->pin_bytes = bytes;
+  char* b = sv->pin_base + off;
+  if (r->device_io) {
+    r->st_pin = (SnfState*)b;
+  } else {
+    const size_t mat = ((size_t)r->n * r->n * sizeof(double) + 255) & ~(size_t)255;
+    r->F_pin = (double*)b;
+    r->D_pin = (double*)(b + mat);
+    r->st_pin = (SnfState*)(b + 2 * mat);
+  }
+  return true;
+}
+
+static hipEvent_t take_event_locked(snf_server* sv) {
+  if (!sv->free_events.empty()) {
+    hipEvent_t e = sv->free_events.back();
+    sv->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+#define SV_HIP(call)                              \
+  do {                                            \
     if ((call) != hipSuccess) return SNF_EDEVICE; \
   } while (0)
 
-// Stage 1 for one admitted request (stream-ordered, no host waits except the pageable F copy).
+// Admission of one request into slot r->slot: tables, F into x[2] (row stride n), f_0 and
+// the initial schedule -- all stream-ordered, no host waits.
 static int start_request(snf_server* sv, ServeRequest* r) {
   const int k = r->slot;
   const RequestLayout L = request_layout(r->n, r->prec);
@@ -195,34 +245,68 @@ static int start_request(snf_server* sv, ServeRequest* r) {
   SV_HIP(hipMemcpyAsync(sv->slots + k, &d, sizeof(SlotDesc), hipMemcpyHostToDevice, s));
   SV_HIP(hipMemcpyAsync(sv->states + k, &sv->state_stage[k], sizeof(SnfState),
                         hipMemcpyHostToDevice, s));
-  // F is staged in x[2] (row stride n), read by f_0, which writes X_0 into x[0]
-  SV_HIP(hipMemcpyAsync(b.x[2], r->F.data(), (size_t)r->n * r->n * sizeof(double),
-                        hipMemcpyHostToDevice, s));
+  const size_t fbytes = (size_t)r->n * r->n * sizeof(double);
+  if (r->device_io)
+    SV_HIP(hipMemcpyAsync(b.x[2], r->F_dev, fbytes, hipMemcpyDeviceToDevice, s));
+  else
+    SV_HIP(hipMemcpyAsync(b.x[2], r->F_pin, fbytes, hipMemcpyHostToDevice, s));
   launch_f0(b.x[2], r->n, r->n, r->np, sv->states + k, sv->bufs + k, lowp_kind_for(r->prec),
             d.partials, s);
   launch_schedule(sv->states + k, d.partials, kF0Blocks, 1, s);
   SV_HIP(hipGetLastError());
-  r->F.clear();
-  r->F.shrink_to_fit();
   return SNF_OK;
 }
 
-// Stage 3 for one finished request: D to the host, result into *res / *status (published
-// to pollers by the caller, under the lock).
-static int finish_request(snf_server* sv, ServeRequest* r, snf_result* res, int* status) {
+// Retirement of a finished request: D out (device copy, or through x[2] to the pinned D
+// staging), the state to pinned memory, an event behind them; the finisher thread completes
+// it on the host.  Stream order keeps a later admission into the same memory behind these.
+static int retire_request(snf_server* sv, ServeRequest* r) {
   const int k = r->slot;
   hipStream_t s = sv->stream;
-  SnfState* hs = &sv->state_stage[k];
-  SV_HIP(hipMemcpyAsync(hs, sv->states + k, sizeof(SnfState), hipMemcpyDeviceToHost, s));
-  SV_HIP(hipStreamSynchronize(s));
-  const double* X = sv->bufs_stage[k].x[hs->cur];
-  SV_HIP(hipMemcpy2DAsync(r->D_host, r->n * sizeof(double), X, r->np * sizeof(double),
-                          r->n * sizeof(double), r->n, hipMemcpyDeviceToHost, s));
-  SV_HIP(hipStreamSynchronize(s));
-  fill_result(hs, res, nullptr, 0);
-  *status = hs->stop ? hs->status : SNF_ENOCONV;
-  res->status = *status;
+  const Buffers& b = sv->bufs_stage[k];
+  if (r->device_io) {
+    launch_copy_out(sv->states + k, sv->bufs + k, r->n, r->np, r->D_dev, r->n, s);
+  } else {
+    launch_copy_out(sv->states + k, sv->bufs + k, r->n, r->np, b.x[2], r->n, s);
+    SV_HIP(hipMemcpyAsync(r->D_pin, b.x[2], (size_t)r->n * r->n * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+  }
+  SV_HIP(hipMemcpyAsync(r->st_pin, sv->states + k, sizeof(SnfState), hipMemcpyDeviceToHost, s));
+  SV_HIP(hipEventRecord(r->ev, s));
+  SV_HIP(hipGetLastError());
   return SNF_OK;
+}
+
+static void finisher(snf_server* sv) {
+  (void)hipSetDevice(sv->device);
+  for (;;) {
+    ServeRequest* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      sv->fin_cv.wait(lk, [&] { return !sv->finishing.empty() || sv->sched_done; });
+      if (sv->finishing.empty()) return;
+      r = sv->finishing.front();
+      sv->finishing.pop_front();
+    }
+    int status = SNF_EDEVICE;
+    snf_result res;
+    memset(&res, 0, sizeof(res));
+    if (hipEventSynchronize(r->ev) == hipSuccess) {
+      if (!r->device_io) memcpy(r->D_host, r->D_pin, (size_t)r->n * r->n * sizeof(double));
+      fill_result(r->st_pin, &res, nullptr, 0);
+      status = r->st_pin->stop ? r->st_pin->status : SNF_ENOCONV;
+    }
+    res.status = status;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    r->result = res;
+    r->status = status;
+    r->t_done = Clock::now();
+    sv->pin_arena.release(r->pin_off, r->pin_bytes);
+    r->pinned = false;
+    sv->free_events.push_back(r->ev);
+    r->ev = nullptr;
+    sv->cv.notify_all();   // pinned staging freed: admission may proceed
+  }
 }
 
 static void scheduler(snf_server* sv) {
@@ -236,7 +320,9 @@ static void scheduler(snf_server* sv) {
       for (;;) {
         bool any_running = false;
         for (ServeRequest* r : sv->slot_req) any_running |= (r != nullptr);
-        while (!sv->pending.empty()) {
+        // FIFO on device memory; a request whose host staging is not available yet is
+        // passed over (requests holding staging must be able to run and release it)
+        for (size_t qi = 0; qi < sv->pending.size();) {
           int k = -1;
           for (int i = 0; i < sv->max_slots; ++i)
             if (!sv->slot_req[i]) {
@@ -244,10 +330,24 @@ static void scheduler(snf_server* sv) {
               break;
             }
           if (k < 0) break;
-          ServeRequest* r = sv->pending.front();
+          ServeRequest* r = sv->pending[qi];
+          if (!r->pinned && !take_pinned_locked(sv, r)) {
+            ++qi;
+            continue;
+          }
           size_t off = 0;
-          if (!sv->arena.alloc(r->bytes, &off)) break;   // FIFO: wait for memory
-          sv->pending.pop_front();
+          if (!sv->arena.alloc(r->bytes, &off)) break;
+          hipEvent_t ev = take_event_locked(sv);
+          if (!ev) {
+            sv->arena.release(off, r->bytes);
+            break;
+          }
+          sv->pending.erase(sv->pending.begin() + qi);
+          if (!r->F_pageable.empty()) {   // late pinned staging: move the host copy over
+            memcpy(r->F_pin, r->F_pageable.data(), r->F_pageable.size() * sizeof(double));
+            std::vector<double>().swap(r->F_pageable);
+          }
+          r->ev = ev;
           r->slot = k;
           r->off = off;
           r->t_admit = Clock::now();
@@ -256,7 +356,11 @@ static void scheduler(snf_server* sv) {
           any_running = true;
         }
         if (any_running) break;
-        if (sv->stopping && sv->pending.empty()) return;
+        if (sv->stopping && sv->pending.empty()) {
+          sv->sched_done = true;
+          sv->fin_cv.notify_all();
+          return;
+        }
         sv->cv.wait(lk);
       }
     }
@@ -266,16 +370,13 @@ static void scheduler(snf_server* sv) {
     // grouped step over every running request
     active.clear();
     int prec_mask = 1 << kPrecF64;
-    {
-      std::lock_guard<std::mutex> lk(sv->mu);
-      for (int i = 0; i < sv->max_slots; ++i)
-        if (sv->slot_req[i]) {
-          active.push_back(i);
-          const snf_precision p = sv->slot_req[i]->prec;
-          if (p == SNF_P_FP32 || p == SNF_P_FP32_REF64) prec_mask |= 1 << kPrecF32;
-          if (p == SNF_P_BF16_REF64) prec_mask |= 1 << kPrecBF16;
-        }
-    }
+    for (int i = 0; i < sv->max_slots; ++i)   // slot_req is written by this thread only
+      if (sv->slot_req[i]) {
+        active.push_back(i);
+        const snf_precision p = sv->slot_req[i]->prec;
+        if (p == SNF_P_FP32 || p == SNF_P_FP32_REF64) prec_mask |= 1 << kPrecF32;
+        if (p == SNF_P_BF16_REF64) prec_mask |= 1 << kPrecBF16;
+      }
     const int na = (int)active.size();
     if (rc == SNF_OK && na > 0) {
       int* idx = sv->index_stage;
@@ -301,29 +402,61 @@ static void scheduler(snf_server* sv) {
             hipStreamSynchronize(s) != hipSuccess)
           rc = SNF_EDEVICE;
       }
-      if (rc == SNF_OK) {
-        for (int a = 0; a < na && rc == SNF_OK; ++a) {
-          if (!sv->stop_stage[a]) continue;
-          ServeRequest* r = sv->slot_req[active[a]];
-          snf_result res;
-          int status = SNF_OK;
-          rc = finish_request(sv, r, &res, &status);
-          if (rc != SNF_OK) break;
-          std::lock_guard<std::mutex> lk(sv->mu);
-          r->result = res;
-          r->status = status;
-          r->t_done = Clock::now();
-          sv->arena.release(r->off, r->bytes);
-          sv->slot_req[r->slot] = nullptr;
-        }
+      for (int a = 0; a < na && rc == SNF_OK; ++a) {
+        if (!sv->stop_stage[a]) continue;
+        ServeRequest* r = sv->slot_req[active[a]];
+        rc = retire_request(sv, r);
+        if (rc != SNF_OK) break;
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->arena.release(r->off, r->bytes);
+        sv->slot_req[r->slot] = nullptr;
+        sv->finishing.push_back(r);
+        sv->fin_cv.notify_one();
       }
     }
     if (rc != SNF_OK) {
       std::lock_guard<std::mutex> lk(sv->mu);
       fail_all_locked(sv, rc);
-      if (sv->stopping) return;
+      if (sv->stopping) {
+        sv->sched_done = true;
+        sv->fin_cv.notify_all();
+        return;
+      }
     }
   }
+}
+
+static int submit_common(snf_server* sv, ServeRequest* r, uint64_t* ticket) {
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stopping || sv->sticky_error != SNF_OK) {
+      const int rc = sv->stopping ? SNF_EINVAL : sv->sticky_error;
+      if (r->pinned) sv->pin_arena.release(r->pin_off, r->pin_bytes);
+      delete r;
+      return rc;
+    }
+    r->ticket = sv->next_ticket++;
+    sv->by_ticket[r->ticket] = r;
+    sv->pending.push_back(r);
+    *ticket = r->ticket;
+  }
+  sv->cv.notify_one();
+  return SNF_OK;
+}
+
+static ServeRequest* new_request(snf_server* sv, int64_t n, const snf_params* params,
+                                 snf_scheme scheme, snf_precision precision) {
+  ServeRequest* r = new ServeRequest();
+  r->n = n;
+  r->np = (n + kTile - 1) / kTile * kTile;
+  r->params = *params;
+  r->scheme = scheme;
+  r->prec = precision;
+  r->bytes = request_layout(n, precision).total;
+  memset(&r->result, 0, sizeof(r->result));
+  r->result.status = SNF_PENDING;
+  r->t_submit = Clock::now();
+  return r;
 }
 
 }  // namespace snf
@@ -343,9 +476,14 @@ int snf_serve_create(size_t hbm_budget_bytes, int32_t max_slots, snf_server** ou
   sv->budget = hbm_budget_bytes;
   sv->max_slots = max_slots;
   sv->slot_req.assign(max_slots, nullptr);
+  size_t pin = hbm_budget_bytes / 4;
+  if (pin < ((size_t)64 << 20)) pin = (size_t)64 << 20;
+  if (pin > ((size_t)2 << 30)) pin = (size_t)2 << 30;
+  sv->pin_size = pin;
   bool ok = hipGetDevice(&sv->device) == hipSuccess &&
             hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) == hipSuccess;
   ok = ok && hipMalloc(&sv->arena_base, hbm_budget_bytes) == hipSuccess;
+  ok = ok && hipHostMalloc(&sv->pin_base, pin, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipMalloc(&sv->states, max_slots * sizeof(SnfState)) == hipSuccess &&
        hipMalloc(&sv->bufs, max_slots * sizeof(Buffers)) == hipSuccess &&
        hipMalloc(&sv->slots, max_slots * sizeof(SlotDesc)) == hipSuccess &&
@@ -366,11 +504,14 @@ int snf_serve_create(size_t hbm_budget_bytes, int32_t max_slots, snf_server** ou
   if (!ok) {
     (void)hipGetLastError();
     sv->stopping = true;
+    sv->sched_done = true;
     snf_serve_destroy(sv);
     return SNF_ENOMEM;
   }
   sv->arena.init(hbm_budget_bytes);
+  sv->pin_arena.init(pin);
   sv->thread = std::thread(scheduler, sv);
+  sv->finisher = std::thread(finisher, sv);
   *out = sv;
   return SNF_OK;
 }
@@ -381,37 +522,43 @@ int snf_serve_submit(snf_server* sv, const double* F_host, int64_t n, const snf_
   if (!sv || !F_host || !D_host_out || !ticket) return SNF_EINVAL;
   int rc = validate(n, params, scheme, precision);
   if (rc != SNF_OK) return rc;
-  const size_t bytes = request_layout(n, precision).total;
-  if (bytes > sv->budget) return SNF_ENOMEM;
-  ServeRequest* r = new ServeRequest();
-  r->n = n;
-  r->np = (n + kTile - 1) / kTile * kTile;
-  r->params = *params;
-  r->scheme = scheme;
-  r->prec = precision;
-  r->F.assign(F_host, F_host + (size_t)n * n);
+  ServeRequest* r = new_request(sv, n, params, scheme, precision);
   r->D_host = D_host_out;
-  r->bytes = bytes;
-  memset(&r->result, 0, sizeof(r->result));
-  r->result.status = SNF_PENDING;
-  r->t_submit = Clock::now();
+  if (r->bytes > sv->budget || pinned_bytes(r) > sv->pin_size) {
+    delete r;
+    return SNF_ENOMEM;
+  }
+  bool pinned;
   {
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (sv->stopping) {
-      delete r;
-      return SNF_EINVAL;
-    }
-    if (sv->sticky_error != SNF_OK) {
-      delete r;
-      return sv->sticky_error;
-    }
-    r->ticket = sv->next_ticket++;
-    sv->by_ticket[r->ticket] = r;
-    sv->pending.push_back(r);
-    *ticket = r->ticket;
+    pinned = take_pinned_locked(sv, r);
   }
-  sv->cv.notify_one();
-  return SNF_OK;
+  const size_t elems = (size_t)n * n;
+  if (pinned) memcpy(r->F_pin, F_host, elems * sizeof(double));
+  else r->F_pageable.assign(F_host, F_host + elems);
+  return submit_common(sv, r, ticket);
+}
+
+int snf_serve_submit_device(snf_server* sv, const double* F_dev, int64_t n,
+                            const snf_params* params, snf_scheme scheme,
+                            snf_precision precision, double* D_dev_out, uint64_t* ticket) {
+  if (!sv || !F_dev || !D_dev_out || !ticket || (const void*)F_dev == (const void*)D_dev_out)
+    return SNF_EINVAL;
+  int rc = validate(n, params, scheme, precision);
+  if (rc != SNF_OK) return rc;
+  ServeRequest* r = new_request(sv, n, params, scheme, precision);
+  r->device_io = true;
+  r->F_dev = F_dev;
+  r->D_dev = D_dev_out;
+  if (r->bytes > sv->budget) {
+    delete r;
+    return SNF_ENOMEM;
+  }
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    (void)take_pinned_locked(sv, r);   // else taken at admission
+  }
+  return submit_common(sv, r, ticket);
 }
 
 int snf_serve_poll(snf_server* sv, uint64_t ticket, snf_result* out) {
@@ -451,9 +598,17 @@ int snf_serve_destroy(snf_server* sv) {
   }
   sv->cv.notify_all();
   if (sv->thread.joinable()) sv->thread.join();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->sched_done = true;
+  }
+  sv->fin_cv.notify_all();
+  if (sv->finisher.joinable()) sv->finisher.join();
   if (sv->stream) (void)hipStreamSynchronize(sv->stream);
   for (auto& kv : sv->by_ticket) delete kv.second;
+  for (hipEvent_t e : sv->free_events) (void)hipEventDestroy(e);
   if (sv->arena_base) (void)hipFree(sv->arena_base);
+  if (sv->pin_base) (void)hipHostFree(sv->pin_base);
   if (sv->states) (void)hipFree(sv->states);
   if (sv->bufs) (void)hipFree(sv->bufs);
   if (sv->slots) (void)hipFree(sv->slots);
@@ -468,7 +623,7 @@ int snf_serve_destroy(snf_server* sv) {
   if (sv->stream) (void)hipStreamDestroy(sv->stream);
   const int rc = sv->sticky_error;
   delete sv;
-  return rc == SNF_OK ? SNF_OK : rc;
+  return rc;
 }
 
 }  // extern "C"

@@ -404,9 +404,11 @@ def request_hamiltonian(req: Request) -> Hamiltonian:
                                        name=f"req-n{n}")
 
 
-def request_hamiltonian_torch(req: Request, device: str = "cuda:0") -> Hamiltonian:
+def request_hamiltonian_torch(req: Request, device: str = "cuda:0",
+                              keep_on_device: bool = False) -> Hamiltonian:
     """As ``request_hamiltonian`` but with the Haar rotation drawn and applied on the GPU
-    (torch, seeded per request), for traces too large for host QR; F is returned on the host.
+    (torch, seeded per request), for traces too large for host QR.  F is returned on the
+    host, or as the device tensor with ``keep_on_device``.
     """
     import torch
 
@@ -425,6 +427,7 @@ def request_hamiltonian_torch(req: Request, device: str = "cuda:0") -> Hamiltoni
     q = q * d[None, :]
     f = (q * torch.tensor(lam, device=device)[None, :]) @ q.T
     f = 0.5 * (f + f.T)
-    return Hamiltonian(name=f"req-n{n}", F=f.cpu().numpy(), n_occ=k, lambda_min=-1.0,
+    return Hamiltonian(name=f"req-n{n}", F=f.contiguous() if keep_on_device else f.cpu().numpy(),
+                       n_occ=k, lambda_min=-1.0,
                        lambda_max=1.0, homo=float(homo), lumo=float(lumo),
                        mu=0.5 * (homo + lumo), xi=float(lumo - homo), eigvals=lam, Q=None)

@@ -103,6 +103,9 @@ def lib() -> ctypes.CDLL:
     L.snf_serve_submit.argtypes = [vp, vp, i64, ctypes.POINTER(Params), i32, i32, vp,
                                    ctypes.POINTER(ctypes.c_uint64)]
     L.snf_serve_submit.restype = ctypes.c_int
+    L.snf_serve_submit_device.argtypes = [vp, vp, i64, ctypes.POINTER(Params), i32, i32, vp,
+                                          ctypes.POINTER(ctypes.c_uint64)]
+    L.snf_serve_submit_device.restype = ctypes.c_int
     L.snf_serve_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Result)]
     L.snf_serve_poll.restype = ctypes.c_int
     L.snf_serve_timing.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
@@ -320,6 +323,28 @@ class Server:
         if rc != OK:
             raise RuntimeError(f"snf_serve_submit: {strerror(rc)} ({rc})")
         self._out[t.value] = D
+        return t.value
+
+    def submit_device(self, F, scheme: str = "snf_varmu", precision: str = "fp64",
+                      out=None, **params) -> int:
+        """Submit a float64 CUDA tensor F (kept alive until completion); D is written to
+        ``out`` (allocated if None), returned by poll/wait."""
+        import torch
+        _check_dense(F, "F")
+        if not F.is_contiguous():
+            raise ValueError("F must be contiguous")
+        n = F.shape[0]
+        D = out if out is not None else torch.empty_like(F)
+        p = make_params(**params)
+        t = ctypes.c_uint64(0)
+        rc = lib().snf_serve_submit_device(self._h, F.data_ptr(), n, ctypes.byref(p),
+                                           SCHEMES[scheme], PRECISIONS[precision],
+                                           D.data_ptr(), ctypes.byref(t))
+        if rc != OK:
+            raise RuntimeError(f"snf_serve_submit_device: {strerror(rc)} ({rc})")
+        self._out[t.value] = D
+        self._keep = getattr(self, "_keep", {})
+        self._keep[t.value] = F
         return t.value
 
     def poll(self, ticket: int):

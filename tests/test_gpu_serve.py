@@ -106,3 +106,26 @@ def test_unknown_ticket(snf):
     with snf.Server(GB // 4, max_slots=2) as sv:
         with pytest.raises(KeyError):
             sv.poll(12345)
+
+
+def test_device_submit_matches_host_submit(snf):
+    hs = [_req(n, n // 2 + 1, seed=7 * n, gap=0.05) for n in (96, 300, 700)]
+    with snf.Server(GB, max_slots=8) as sv:
+        th = [sv.submit(h.F, "snf_varmu", "fp32_ref64", **_kw(h)) for h in hs]
+        Fd = [torch.tensor(h.F, device="cuda:0") for h in hs]
+        td = [sv.submit_device(F, "snf_varmu", "fp32_ref64", **_kw(h)) for F, h in zip(Fd, hs)]
+        host = [sv.wait(t) for t in th]
+        devr = [sv.wait(t) for t in td]
+    torch.cuda.synchronize()
+    for (Dh, rh), (Dd, rd) in zip(host, devr):
+        assert rh["status"] == rd["status"] == "ok"
+        assert np.array_equal(Dh, Dd.cpu().numpy())
+
+
+def test_many_small_requests_pinned_staging_cycles(snf):
+    """More queued host requests than the pinned staging holds at once: all complete."""
+    hs = [_req(512, 250 + (i % 7), seed=500 + i, gap=0.1) for i in range(40)]
+    with snf.Server(64 << 20, max_slots=4) as sv:
+        ts = [sv.submit(h.F, "sp2", "fp64", **_kw(h, tol=1e-9)) for h in hs]
+        rs = [sv.wait(t) for t in ts]
+    assert all(r["status"] == "ok" for _, r in rs)
