@@ -150,14 +150,17 @@ def run_bsr(args):
         t0 = time.perf_counter()
         steps = max(1, args.steps)
         for _ in range(steps):
-            D, r = snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=1e-6, want_log=False, **kw)
+            D, r = snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=1e-6, want_log=True, **kw)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
         res[scheme] = dict(ms=round(ms, 1), products=r["products"], status=r["status"],
                            idem_err=r["idem_err"], trace_err=r["trace_err"],
                            blocks_D=r["blocks"], blocks_per_row=round(r["blocks"] / m.nb, 1),
                            product_ms=round(r["product_ms"], 1),
-                           useful_tflops=round(r["flops"] / (r["product_ms"] * 1e-3) / 1e12, 2))
+                           useful_tflops=round(r["flops"] / (r["product_ms"] * 1e-3) / 1e12, 2),
+                           blocks_per_row_by_iterate=[round(x["phase"] / m.nb, 1)
+                                                      for x in r["log"]],
+                           branches=r["branches"])
         del D
     s = res["snf_varmu"]
     line = _base_line("time-to-solution ms at the truncation floor (block-sparse), SnF vs SP2",

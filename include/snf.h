@@ -115,7 +115,8 @@ typedef struct {
   int32_t i;          /* iteration index: X_i was the input of this product                */
   int32_t branch;     /* SNF_BRANCH_* applied to X_i (-1 for the last, certifying record)  */
   int32_t precision;  /* 0 FP64, 1 FP32, 2 BF16 product for X_i^2                          */
-  int32_t reserved;
+  int32_t reserved;   /* dense: precision phase (0 FP64, 1 low precision, 2 refinement);
+                         block-sparse: stored blocks of X_i                                */
   double alpha;       /* scaling parameter of the step                                     */
   double beta;        /* image of the lumo bound in X_i                                     */
   double betabar;     /* image of the homo bound in X_i                                     */

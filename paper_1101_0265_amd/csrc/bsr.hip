@@ -180,6 +180,7 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
   __shared__ uint16_t klist[kChunkWords * 32];
   __shared__ uint32_t sw[kChunkWords];
   __shared__ int offs[kChunkWords + 1];
+  __shared__ uint32_t spres[2];
   __shared__ double red[12];
 
   const int packed = g.tiles[blockIdx.x];
@@ -199,11 +200,13 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
   // block row k = tid / 8, columns 4 (tid % 8) .. +3.
   const int lk = tid >> 3, lc = (tid & 7) * 4;
   u32x4 ra[kSup], rb[kSup];
+  uint32_t pres = 0;   // presence of the stage's blocks: bits 0-3 A panel, 4-7 B panel
   auto gload = [&](int K) {
     // the 4 panel columns of each side share one bitmap word of block row K
     const int rp = g.X.row_ptr[K];
     const uint32_t wa = g.X.bm[(size_t)K * W + (ci0 >> 5)];
     const uint32_t wb = g.X.bm[(size_t)K * W + (cj0 >> 5)];
+    pres = ((wa >> (ci0 & 31)) & 0xFu) | (((wb >> (cj0 & 31)) & 0xFu) << 4);
     const int pa0 = rp + g.X.pre[(size_t)K * W + (ci0 >> 5)];
     const int pb0 = rp + g.X.pre[(size_t)K * W + (cj0 >> 5)];
 #pragma unroll
@@ -223,6 +226,7 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
       *(u32x4*)(&sA[buf][lk][a * kB + lc]) = ra[a];
       *(u32x4*)(&sB[buf][lk][a * kB + lc]) = rb[a];
     }
+    if (tid == 0) spres[buf] = pres;
   };
 
   const int fr = lane & 15, fk = lane >> 4;
@@ -270,18 +274,35 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
       const int buf = s & 1;
       const bool more = s + 1 < nk;
       if (more) gload(klist[s + 1]);
+      // this wave's two A blocks (rows 2 wr, 2 wr + 1) and two B blocks; absent blocks are
+      // zero, so their MFMAs are skipped (the test is uniform across the wave)
+      const uint32_t pm = spres[buf];
+      const bool pa0 = (pm >> (2 * wr)) & 1u, pa1 = (pm >> (2 * wr + 1)) & 1u;
+      const bool pb0 = (pm >> (4 + 2 * wc)) & 1u, pb1 = (pm >> (4 + 2 * wc + 1)) & 1u;
+      if ((pa0 || pa1) && (pb0 || pb1)) {
 #pragma unroll
-      for (int kk = 0; kk < kB; kk += 4) {
-        float a[4], b[4];
+        for (int kk = 0; kk < kB; kk += 4) {
+          float a[4], b[4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) a[m] = sA[buf][kk + fk][wr * 64 + m * 16 + fr];
+          for (int m = 0; m < 4; ++m) a[m] = sA[buf][kk + fk][wr * 64 + m * 16 + fr];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) b[q] = sB[buf][kk + fk][wc * 64 + q * 16 + fr];
+          for (int q = 0; q < 4; ++q) b[q] = sB[buf][kk + fk][wc * 64 + q * 16 + fr];
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+          for (int bi = 0; bi < 2; ++bi) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], b[q], acc[m][q], 0, 0, 0);
+            for (int bj = 0; bj < 2; ++bj) {
+              if (!((bi ? pa1 : pa0) && (bj ? pb1 : pb0))) continue;
+#pragma unroll
+              for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+                for (int qq = 0; qq < 2; ++qq) {
+                  const int m = 2 * bi + mm, q = 2 * bj + qq;
+                  acc[m][q] =
+                      __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], b[q], acc[m][q], 0, 0, 0);
+                }
+            }
+          }
+        }
       }
       if (more) lstore(buf ^ 1);
       __syncthreads();
@@ -860,6 +881,8 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
   const bool timing = (p.flags & SNF_FLAG_TIME_PRODUCTS) != 0;
   double prod_ms = 0.0, flops = 0.0;
   int cur = 0;
+  std::vector<int64_t> blocks_of_iterate;   // stored blocks of X_i
+  blocks_of_iterate.push_back(w->X[0].nnzb);
   for (int it = 0; it <= p.max_iter; ++it) {
     int slots = 0;
     rc = bsr_step(w, cur, nb, W, tau2, &slots, timing ? w->ev[2] : nullptr,
@@ -877,6 +900,7 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
     flops += 2.0 * kB * kB * kB * (double)w->last_triples;
     if (sh->stop) break;
     cur = 1 - cur;
+    blocks_of_iterate.push_back(w->X[cur].nnzb);
     if ((rc = build_lookup(w->X[cur], nb, W, s))) return fail(rc);
   }
   // the result is the X whose idempotency was certified (the input of the last product)
@@ -899,7 +923,13 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
   const int nrec = sh->nlog < SNF_LOG_MAX ? sh->nlog : SNF_LOG_MAX;
   for (int i = 0; i < nrec; ++i)
     out->branch[i] = (uint8_t)(sh->log[i].branch < 0 ? 255 : sh->log[i].branch);
-  if (log && log_cap > 0) memcpy(log, sh->log, (size_t)std::min(nrec, (int)log_cap) * sizeof(snf_log_rec));
+  if (log && log_cap > 0) {
+    const int m = std::min(nrec, (int)log_cap);
+    memcpy(log, sh->log, (size_t)m * sizeof(snf_log_rec));
+    // block-sparse: the spare field of record i holds the stored blocks of X_i
+    for (int i = 0; i < m && i < (int)blocks_of_iterate.size(); ++i)
+      log[i].reserved = (int32_t)std::min<int64_t>(blocks_of_iterate[i], INT32_MAX);
+  }
   float ms = 0.f;
   BSR_HIP(hipEventElapsedTime(&ms, w->ev[0], w->ev[1]));
   out->device_ms = ms;
