@@ -346,6 +346,24 @@ def main():
     snf_ms, snf_rs = timed("snf_varmu")
     sp2_ms, sp2_rs = timed("sp2")
 
+    # FP32 products after the X-space gap reaches 0.5, FP64 refinement to the same tol
+    def solve_mixed():
+        _, r = snf.purify_dense(F, "snf_varmu", "fp32_ref64", out=D, want_log=False,
+                                gap_switch=0.5, **kw)
+        if r["status"] != "ok":
+            raise RuntimeError(f"fp32_ref64: {r['status']}")
+        return r
+    solve_mixed()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mixed_r = solve_mixed()
+    torch.cuda.synchronize()
+    mixed_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    D_mixed = D.clone()
+    solve("snf_varmu")
+    mixed_err = float(torch.linalg.norm(D_mixed - D))
+
     flops_per_product = float(n) * n * (n + 1)
     prod_ms = sum(r["product_ms"] for r in snf_rs + sp2_rs)
     prods = sum(r["products"] for r in snf_rs + sp2_rs)
@@ -382,6 +400,10 @@ def main():
         "products": {"snf_varmu": snf_rs[0]["products"], "sp2": sp2_rs[0]["products"]},
         "xx_tflops_fp64": round(achieved, 2),
         "xx_algorithmic_gbps": round(algo_bytes / (avg_launch_ms * 1e-3) / 1e9, 1),
+        "fp32_ref64": {"ms": round(mixed_ms, 3), "products_fp32": mixed_r["products_lowp"],
+                       "products_fp64": mixed_r["products_fp64"],
+                       "idem_err": mixed_r["idem_err"],
+                       "dist_to_fp64_D_frobenius": mixed_err},
         "idem_err": snf_rs[0]["idem_err"],
         "trace_err": snf_rs[0]["trace_err"],
         "roofline": roofline,

@@ -328,7 +328,7 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
     return rc;
   }
   const ProductGrid grid = make_product_grid(np, n, sym, w->num_cus, w->partials, w->split_buf,
-                                             kSplitCap);
+                                             kSplitCap, stage_depth_for(precision));
   // A workspace of larger order is used with this call's np: the kernels index rows with
   // np, so every buffer just needs np*np elements.
   init_state(w->state_host, n, params, scheme, precision);
@@ -430,7 +430,7 @@ int snf_step_dense(const double* A_dev, const double* B_dev, int64_t n, int64_t 
   int rc = ensure_workspace(w, np, lowp_bytes_for(precision), tiles + 16 * kSplitCap);
   if (rc != SNF_OK) return rc;
   const ProductGrid grid = make_product_grid(np, n, sym, w->num_cus, w->partials, w->split_buf,
-                                             kSplitCap);
+                                             kSplitCap, stage_depth_for(precision));
   const int lk = lowp_kind_for(precision);
   rc = upload_buffers(w, s);
   if (rc != SNF_OK) return rc;

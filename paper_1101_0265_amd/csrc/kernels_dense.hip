@@ -565,7 +565,7 @@ __global__ __launch_bounds__(256) void split_fixup_kernel(const SnfState* __rest
 }
 
 ProductGrid make_product_grid(int64_t np, int64_t n, int sym, int num_cus, double* partials,
-                              double* split_buf, int split_cap) {
+                              double* split_buf, int split_cap, int stage_depth) {
   ProductGrid g;
   g.np = np;
   g.n = n;
@@ -579,7 +579,9 @@ ProductGrid make_product_grid(int64_t np, int64_t n, int sym, int num_cus, doubl
   g.partial_count = tiles;
   if (num_cus <= 0 || !split_buf) return g;
   const int rem = tiles % num_cus;
-  const int kt_min = (int)(np / 64);     // k-stages of the deepest stage (bf16: 64 per stage)
+  // every slice needs at least one k-stage of the deepest stage that may run (f64 16,
+  // f32 32, bf16 64 values of k per stage)
+  const int kt_min = (int)(np / stage_depth);
   if (rem == 0 || rem > num_cus / 2) return g;
   int s = num_cus / rem;
   if (s > kt_min) s = kt_min;

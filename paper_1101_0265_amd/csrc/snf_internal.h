@@ -89,7 +89,11 @@ struct ProductGrid {
 // Split the last (tiles mod num_cus) tiles into k-slices when that tail would leave most
 // compute units idle; split_cap = slices the split buffer holds.
 ProductGrid make_product_grid(int64_t np, int64_t n, int sym, int num_cus, double* partials,
-                              double* split_buf, int split_cap);
+                              double* split_buf, int split_cap, int stage_depth);
+// k values per stage of the deepest product variant a precision mode may run
+inline int stage_depth_for(snf_precision p) {
+  return p == SNF_P_BF16_REF64 ? 64 : (p == SNF_P_FP32 || p == SNF_P_FP32_REF64) ? 32 : 16;
+}
 constexpr int kSplitCap = 512;   // slices held by the split buffer (64*256 doubles each)
 
 // Product of the pending step; each variant exits at once unless the state asks for its
