@@ -142,6 +142,24 @@ def run_bsr(args):
     va = torch.tensor(m.val, device="cuda:0")
     kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
               lumo=h.lumo, tol=1e-9, max_iter=80, flags=snf.FLAG_TIME_PRODUCTS)
+    if args.bsr_sweep:
+        D, _ = snf.purify_bsr(rp, ci, va, m.n, "snf_varmu", trunc_tau=1e-5, want_log=False, **kw)
+        del D
+        for scheme, tau in (("sp2", 1e-6), ("sp2", 3e-7), ("snf_varmu", 1e-6),
+                            ("snf_varmu", 2e-6), ("snf_varmu", 5e-6), ("snf_varmu", 1e-5),
+                            ("tc2", 1e-6)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            D, r = snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=tau, **kw)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            peak = max(x["phase"] for x in r["log"]) / m.nb
+            print(json.dumps(dict(scheme=scheme, tau=tau, ms=round(ms, 1),
+                                  products=r["products"], status=r["status"],
+                                  e=r["idem_err"], trace_err=r["trace_err"],
+                                  blocks_per_row=round(r["blocks"] / m.nb, 1),
+                                  peak_blocks_per_row=round(peak, 1))), flush=True)
+            del D
     res = {}
     for scheme in ("snf_varmu", "sp2"):
         for _ in range(args.warmup):
@@ -281,6 +299,9 @@ def main():
                     help="dense: n=4096 lattice (default line); small: n=256 gap-0.05 latency "
                          "of all five schemes; bsr: block-sparse 32^3-site lattice n=65536; "
                          "serve: 512-request continuous-batching trace")
+    ap.add_argument("--bsr-sweep", action="store_true",
+                    help="with --workload bsr: one solve per (scheme, truncation threshold) of "
+                         "the sweep, one JSON line each")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for hardware-counter runs: a plain 512 MiB device copy (counter "
                          "calibration), then three FP64 products of the workload's X_0")
