@@ -51,22 +51,29 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum three values over a 256-thread block; result valid in thread 0.
-__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* lds12) {
+// Sum three values over the block (up to 8 waves), in wave order; result valid in thread 0.
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* lds24) {
   a = wave_sum(a);
   b = wave_sum(b);
   c = wave_sum(c);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) {
-    lds12[w * 3 + 0] = a;
-    lds12[w * 3 + 1] = b;
-    lds12[w * 3 + 2] = c;
+    lds24[w * 3 + 0] = a;
+    lds24[w * 3 + 1] = b;
+    lds24[w * 3 + 2] = c;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    a = ((lds12[0] + lds12[3]) + lds12[6]) + lds12[9];
-    b = ((lds12[1] + lds12[4]) + lds12[7]) + lds12[10];
-    c = ((lds12[2] + lds12[5]) + lds12[8]) + lds12[11];
+    const int nw = blockDim.x >> 6;
+    double sa = lds24[0], sb = lds24[1], sc = lds24[2];
+    for (int i = 1; i < nw; ++i) {
+      sa += lds24[3 * i + 0];
+      sb += lds24[3 * i + 1];
+      sc += lds24[3 * i + 2];
+    }
+    a = sa;
+    b = sb;
+    c = sc;
   }
 }
 
@@ -79,7 +86,7 @@ __global__ __launch_bounds__(256) void f0_kernel(const double* __restrict__ F, i
                                                  const Buffers* __restrict__ bufs,
                                                  int lowp_kind, double* __restrict__ partials) {
   __shared__ double tile[32][33];
-  __shared__ double red[12];
+  __shared__ double red[24];
   const int alg1 = (st->scheme == SNF_MCWEENY || st->scheme == SNF_SNF_FIXMU);
   const double lmin = st->lambda_min, lmax = st->lambda_max, mu = st->mu, gamma = st->gamma;
   double* X = bufs->x[st->cur];
@@ -173,10 +180,7 @@ __device__ __forceinline__ void tile_coords(int t, int nt, int sym, int& bi, int
 }
 
 // ---------------------------------------------------------------------------------------
-// Product kernel, f64 / f32 MFMA 16x16x4.
-//   LDS tiles hold 'k-rows' of both operands: sA[k][i] = A[k0+k][i0+i] and
-//   sB[k][j] = B[k0+k][j0+j]; A[i][k] = A[k][i] because A is symmetric, so both panels are
-//   read with contiguous, coalesced rows.  MFMA operand of lane l: row/col (l % 16), k (l / 16).
+// MFMA wrappers, the shared epilogue, slices
 // ---------------------------------------------------------------------------------------
 template <typename T> struct Mfma;
 template <> struct Mfma<double> {
@@ -222,6 +226,47 @@ __device__ __forceinline__ EpiArgs epi_args(const SnfState* st, const Buffers* b
   return e;
 }
 
+// Epilogue of one product entry p at global (r, c): Y = c2 p + c1 X + c0 [r == c], the FP64
+// sums, the mirror write.  In symmetric mode a diagonal tile keeps its upper half and
+// mirrors it, so the result is exactly symmetric; every off-diagonal entry then stands for
+// two.
+__device__ __forceinline__ void epi_elem(double p, int64_t r, int64_t c, int sym, int diag,
+                                         int64_t n, int64_t np, const EpiArgs& ea, double& e2,
+                                         double& t1, double& t2) {
+  if (diag && sym && r > c) return;
+  const bool mirror = sym && r != c;
+  const double w = mirror ? 2.0 : 1.0;
+  const double x = ea.Xt[r * np + c];
+  if (ea.want_e) {
+    const double d = p - x;
+    e2 += w * (d * d);
+  }
+  double y = ea.c2 * p + ea.c1 * x + (r == c ? ea.c0 : 0.0);
+  if (r >= n || c >= n) y = 0.0;
+  if (r == c) t1 += y;
+  t2 += w * (y * y);
+  ea.Y[r * np + c] = y;
+  if (mirror) ea.Y[c * np + r] = y;
+  if (ea.lowp_kind == kPrecF32) {
+    const float yf = (float)y;
+    ((float*)ea.LPY)[r * np + c] = yf;
+    if (mirror) ((float*)ea.LPY)[c * np + r] = yf;
+  } else if (ea.lowp_kind == kPrecBF16) {
+    const unsigned short yb = f32_to_bf16_rne((float)y);
+    ((unsigned short*)ea.LPY)[r * np + c] = yb;
+    if (mirror) ((unsigned short*)ea.LPY)[c * np + r] = yb;
+  }
+}
+
+// Row of accumulator register v of lane l inside its 16x16 MFMA block:
+//   4 (l / 16) + v   for the f32 and bf16 MFMAs (ROWS_INTERLEAVED = false),
+//   (l / 16) + 4 v   for the f64 MFMA          (ROWS_INTERLEAVED = true);
+// the column is l % 16 for all three.
+template <bool ROWS_INTERLEAVED>
+__device__ __forceinline__ int acc_row(int lane, int v) {
+  return ROWS_INTERLEAVED ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+}
+
 // One 16x16 MFMA block (m, q) of the wave tile: acc4 holds its four values of this lane.
 template <bool ROWS_INTERLEAVED, typename Acc4>
 __device__ __forceinline__ void epilogue_block(const Acc4& acc4, int m, int q, int gi0, int gj0,
@@ -229,56 +274,29 @@ __device__ __forceinline__ void epilogue_block(const Acc4& acc4, int m, int q, i
                                                const EpiArgs& ea, double& e2, double& t1,
                                                double& t2) {
   const int lane = threadIdx.x & 63;
-  const int rsub = ROWS_INTERLEAVED ? (lane >> 4) : 4 * (lane >> 4), csub = lane & 15;
-  const int rstep = ROWS_INTERLEAVED ? 4 : 1;
-  const int64_t c = gj0 + q * 16 + csub;
+  const int64_t c = gj0 + q * 16 + (lane & 15);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int64_t r = gi0 + m * 16 + rsub + v * rstep;
-    // In symmetric mode a diagonal tile keeps its upper half and mirrors it, so the
-    // result is exactly symmetric; every off-diagonal entry then stands for two.
-    if (diag && sym && r > c) continue;
-    const bool mirror = sym && r != c;
-    const double w = mirror ? 2.0 : 1.0;
-    const double p = (double)acc4[v];
-    const double x = ea.Xt[r * np + c];
-    if (ea.want_e) {
-      const double d = p - x;
-      e2 += w * (d * d);
-    }
-    double y = ea.c2 * p + ea.c1 * x + (r == c ? ea.c0 : 0.0);
-    if (r >= n || c >= n) y = 0.0;
-    if (r == c) t1 += y;
-    t2 += w * (y * y);
-    ea.Y[r * np + c] = y;
-    if (mirror) ea.Y[c * np + r] = y;
-    if (ea.lowp_kind == kPrecF32) {
-      const float yf = (float)y;
-      ((float*)ea.LPY)[r * np + c] = yf;
-      if (mirror) ((float*)ea.LPY)[c * np + r] = yf;
-    } else if (ea.lowp_kind == kPrecBF16) {
-      const unsigned short yb = f32_to_bf16_rne((float)y);
-      ((unsigned short*)ea.LPY)[r * np + c] = yb;
-      if (mirror) ((unsigned short*)ea.LPY)[c * np + r] = yb;
-    }
+    const int64_t r = gi0 + m * 16 + acc_row<ROWS_INTERLEAVED>(lane, v);
+    epi_elem((double)acc4[v], r, c, sym, diag, n, np, ea, e2, t1, t2);
   }
 }
 
-template <bool ROWS_INTERLEAVED, typename AccT>
-__device__ __forceinline__ void epilogue(const AccT (&acc)[4][4], int gi0, int gj0, int sym,
+template <bool ROWS_INTERLEAVED, int MT, int QT, typename AccT>
+__device__ __forceinline__ void epilogue(const AccT (&acc)[MT][QT], int gi0, int gj0, int sym,
                                          int diag, int64_t n, int64_t np, const EpiArgs& ea,
                                          double& e2, double& t1, double& t2) {
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < MT; ++m)
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < QT; ++q)
       epilogue_block<ROWS_INTERLEAVED>(acc[m][q], m, q, gi0, gj0, sym, diag, n, np, ea, e2, t1,
                                        t2);
 }
 
 __device__ __forceinline__ void write_partials(double e2, double t1, double t2,
                                                double* partials, int tile) {
-  __shared__ double red[12];
+  __shared__ double red[24];
   block_sum3(e2, t1, t2, red);
   if (threadIdx.x == 0) {
     partials[tile * 4 + 0] = e2;
@@ -317,16 +335,23 @@ __device__ __forceinline__ WorkItem work_item(const ProductGrid& g, int KT) {
   return it;
 }
 
-// Raw accumulators of a k-slice: split[piece][idx][tid], idx = (m*4 + q)*4 + v.
-template <typename AccT>
-__device__ __forceinline__ void store_slice(const AccT (&acc)[4][4], double* split, int piece) {
-  double* base = split + (size_t)piece * 64 * kThreads + threadIdx.x;
+// Raw accumulators of a k-slice in tile order: split[piece][r][c], r, c < 128, whatever the
+// thread layout of the kernel that produced them.
+template <bool ROWS_INTERLEAVED, int MT, int QT, typename AccT>
+__device__ __forceinline__ void store_slice(const AccT (&acc)[MT][QT], int wr0, int wc0,
+                                            double* split, int piece) {
+  const int lane = threadIdx.x & 63;
+  double* base = split + (size_t)piece * kTile * kTile;
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < MT; ++m)
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < QT; ++q)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) base[((m * 4 + q) * 4 + v) * kThreads] = (double)acc[m][q][v];
+      for (int v = 0; v < 4; ++v) {
+        const int r = wr0 + m * 16 + acc_row<ROWS_INTERLEAVED>(lane, v);
+        const int c = wc0 + q * 16 + (lane & 15);
+        base[r * kTile + c] = (double)acc[m][q][v];
+      }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -335,15 +360,27 @@ __device__ __forceinline__ void store_slice(const AccT (&acc)[4][4], double* spl
 //   sB[k][j] = B[k0+k][j0+j]; A[i][k] = A[k][i] because A is symmetric, so both panels are
 //   read with contiguous, coalesced rows.  MFMA operand of lane l: row/col (l % 16), k (l / 16).
 // ---------------------------------------------------------------------------------------
+// Thread layout: NT threads = (NT/64) waves in WR x WC, each wave a (128/WR) x (128/WC)
+// piece of the tile made of MT x QT MFMA 16x16 blocks.
+template <typename T> struct Layout;
+template <> struct Layout<double> {   // 8 waves of 64x32: 64 accumulator registers per lane,
+  static constexpr int NT = 512, WC = 4;   // so 4 waves fit on each SIMD
+};
+template <> struct Layout<float> {    // 4 waves of 64x64
+  static constexpr int NT = 256, WC = 2;
+};
+
 template <typename T, int PREC>
 __device__ __forceinline__ void product_body(const SnfState* __restrict__ st,
                                              const Buffers* __restrict__ bufs,
                                              const ProductGrid& g, const WorkItem& wi) {
   typedef Mfma<T> M;
+  constexpr int NT = Layout<T>::NT, WC = Layout<T>::WC, WR = NT / 64 / WC;
+  constexpr int TR = kTile / WR, TC = kTile / WC, MT = TR / 16, QT = TC / 16;
   constexpr int BK = M::kBK, LDS_W = kTile + M::kPad;
   constexpr int VE = 16 / sizeof(T);          // elements per 16-byte vector
   constexpr int VPR = kTile / VE;             // vectors per LDS row
-  constexpr int RPP = kThreads / VPR;         // rows per load pass
+  constexpr int RPP = NT / VPR;               // rows per load pass
   constexpr int PASSES = BK / RPP;
   __shared__ __attribute__((aligned(16))) T sA[2][BK][LDS_W];
   __shared__ __attribute__((aligned(16))) T sB[2][BK][LDS_W];
@@ -357,14 +394,14 @@ __device__ __forceinline__ void product_body(const SnfState* __restrict__ st,
   const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
+  const int wr = wid / WC, wc = wid % WC;
   const int lrow = tid / VPR, lvec = tid % VPR;
 
-  typename M::acc_t acc[4][4];
+  typename M::acc_t acc[MT][QT];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < MT; ++m)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[m][q] = typename M::acc_t{0, 0, 0, 0};
+    for (int q = 0; q < QT; ++q) acc[m][q] = typename M::acc_t{0, 0, 0, 0};
 
   u32x4 ra[PASSES], rb[PASSES];
   auto gload = [&](int64_t k0) {
@@ -393,27 +430,27 @@ __device__ __forceinline__ void product_body(const SnfState* __restrict__ st,
     if (more) gload((int64_t)(kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      T a[4], b[4];
+      T a[MT], b[QT];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) a[m] = sA[buf][kk + fk][wr * 64 + m * 16 + fr];
+      for (int m = 0; m < MT; ++m) a[m] = sA[buf][kk + fk][wr * TR + m * 16 + fr];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) b[q] = sB[buf][kk + fk][wc * 64 + q * 16 + fr];
+      for (int q = 0; q < QT; ++q) b[q] = sB[buf][kk + fk][wc * TC + q * 16 + fr];
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[m][q] = M::mma(a[m], b[q], acc[m][q]);
+        for (int q = 0; q < QT; ++q) acc[m][q] = M::mma(a[m], b[q], acc[m][q]);
     }
     if (more) lstore(buf ^ 1);
     __syncthreads();
   }
 
   if (wi.piece >= 0) {
-    store_slice(acc, g.split_buf, wi.piece);
+    store_slice<PREC == kPrecF64>(acc, wr * TR, wc * TC, g.split_buf, wi.piece);
     return;
   }
   const EpiArgs ea = epi_args(st, bufs);
   double e2 = 0.0, t1 = 0.0, t2 = 0.0;
-  epilogue<PREC == kPrecF64>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), g.sym, bi == bj,
+  epilogue<PREC == kPrecF64>(acc, (int)(i0 + wr * TR), (int)(j0 + wc * TC), g.sym, bi == bj,
                              g.n, np, ea, e2, t1, t2);
   write_partials(e2, t1, t2, g.partials, wi.tile);
 }
@@ -499,7 +536,7 @@ __device__ __forceinline__ void product_bf16_body(const SnfState* __restrict__ s
   }
 
   if (wi.piece >= 0) {
-    store_slice(acc, g.split_buf, wi.piece);
+    store_slice<false>(acc, wr * 64, wc * 64, g.split_buf, wi.piece);
     return;
   }
   const EpiArgs ea = epi_args(st, bufs);
@@ -509,12 +546,18 @@ __device__ __forceinline__ void product_bf16_body(const SnfState* __restrict__ s
   write_partials(e2, t1, t2, g.partials, wi.tile);
 }
 
-template <typename T, int PREC>
-__global__ __launch_bounds__(256, 2) void product_kernel(const SnfState* __restrict__ st,
-                                                         const Buffers* __restrict__ bufs,
-                                                         ProductGrid g) {
-  if (st->stop || st->prec != PREC) return;
-  product_body<T, PREC>(st, bufs, g, work_item(g, (int)(g.np / Mfma<T>::kBK)));
+__global__ __launch_bounds__(512, 2) void product_f64_kernel(const SnfState* __restrict__ st,
+                                                             const Buffers* __restrict__ bufs,
+                                                             ProductGrid g) {
+  if (st->stop || st->prec != kPrecF64) return;
+  product_body<double, kPrecF64>(st, bufs, g, work_item(g, (int)(g.np / Mfma<double>::kBK)));
+}
+
+__global__ __launch_bounds__(256, 2) void product_f32_kernel(const SnfState* __restrict__ st,
+                                                             const Buffers* __restrict__ bufs,
+                                                             ProductGrid g) {
+  if (st->stop || st->prec != kPrecF32) return;
+  product_body<float, kPrecF32>(st, bufs, g, work_item(g, (int)(g.np / Mfma<float>::kBK)));
 }
 
 __global__ __launch_bounds__(256, 2) void product_bf16_kernel(const SnfState* __restrict__ st,
@@ -524,43 +567,42 @@ __global__ __launch_bounds__(256, 2) void product_bf16_kernel(const SnfState* __
   product_bf16_body(st, bufs, g, work_item(g, (int)(g.np / 64)));
 }
 
-// Fix-up of the split tail tiles: workgroup (t, b) handles MFMA block b = (m, q) of every
-// wave of tail tile t; it adds the k-slices in slice order (all loads in flight at once),
-// then runs the epilogue of that block and stores its sums in its own partials slot.
+// Fix-up of the split tail tiles: workgroup (t, b) handles rows 8b .. 8b + 7 of tail tile t
+// (256 threads, 4 consecutive columns each); it adds the k-slices in slice order (the loads
+// of four slices in flight at a time), runs the epilogue of those entries and stores its
+// sums in its own partials slot.
 constexpr int kMaxSplit = 16;
 __global__ __launch_bounds__(256) void split_fixup_kernel(const SnfState* __restrict__ st,
                                                           const Buffers* __restrict__ bufs,
                                                           ProductGrid g) {
   if (st->stop) return;
-  const int t = blockIdx.x >> 4, b = blockIdx.x & 15, m = b >> 2, q = b & 3;
+  const int t = blockIdx.x >> 4, b = blockIdx.x & 15;
   const int tile = g.dp_tiles + t;
   int bi, bj;
   tile_coords(tile, (int)(g.np / kTile), g.sym, bi, bj);
-  const int64_t i0 = (int64_t)bi * kTile, j0 = (int64_t)bj * kTile;
-  const int wid = threadIdx.x >> 6, wr = wid >> 1, wc = wid & 1;
-  const double* base =
-      g.split_buf + (size_t)t * g.split_s * 64 * kThreads + (size_t)(b * 4) * kThreads + threadIdx.x;
-  double part[kMaxSplit][4];
+  const int r = 8 * b + (threadIdx.x >> 5), c0 = (threadIdx.x & 31) * 4;
+  const double* base = g.split_buf + (size_t)t * g.split_s * kTile * kTile + r * kTile + c0;
+  double sum[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int p0 = 0; p0 < g.split_s; p0 += 4) {
+    double part[4][4];
 #pragma unroll
-  for (int p = 0; p < kMaxSplit; ++p)
+    for (int pp = 0; pp < 4; ++pp)
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      part[p][v] = (p < g.split_s) ? base[((size_t)p * 64 + v) * kThreads] : 0.0;
-  dbl4 acc4;
+      for (int v = 0; v < 4; ++v)
+        part[pp][v] = (p0 + pp < g.split_s) ? base[(size_t)(p0 + pp) * kTile * kTile + v] : 0.0;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    double s = 0.0;
+    for (int pp = 0; pp < 4; ++pp)
 #pragma unroll
-    for (int p = 0; p < kMaxSplit; ++p) s += part[p][v];
-    acc4[v] = s;
+      for (int v = 0; v < 4; ++v)
+        if (p0 + pp < g.split_s) sum[v] += part[pp][v];
   }
   const EpiArgs ea = epi_args(st, bufs);
   double e2 = 0.0, t1 = 0.0, t2 = 0.0;
-  const int gi0 = (int)(i0 + wr * 64), gj0 = (int)(j0 + wc * 64);
-  if (st->prec == kPrecF64)
-    epilogue_block<true>(acc4, m, q, gi0, gj0, g.sym, bi == bj, g.n, g.np, ea, e2, t1, t2);
-  else
-    epilogue_block<false>(acc4, m, q, gi0, gj0, g.sym, bi == bj, g.n, g.np, ea, e2, t1, t2);
+  const int64_t gr = (int64_t)bi * kTile + r;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    epi_elem(sum[v], gr, (int64_t)bj * kTile + c0 + v, g.sym, bi == bj, g.n, g.np, ea, e2, t1,
+             t2);
   write_partials(e2, t1, t2, g.partials, g.dp_tiles + blockIdx.x);
 }
 
@@ -598,11 +640,11 @@ void launch_product(int prec, SnfState* st, const Buffers* bufs_dev, const Produ
                     hipStream_t s) {
   const int grid = g.dp_tiles + g.tail_tiles * g.split_s;
   if (prec == kPrecF64) {
-    hipLaunchKernelGGL((product_kernel<double, kPrecF64>), dim3(grid), dim3(kThreads), 0, s,
-                       st, bufs_dev, g);
+    hipLaunchKernelGGL(product_f64_kernel, dim3(grid), dim3(Layout<double>::NT), 0, s, st,
+                       bufs_dev, g);
   } else if (prec == kPrecF32) {
-    hipLaunchKernelGGL((product_kernel<float, kPrecF32>), dim3(grid), dim3(kThreads), 0, s,
-                       st, bufs_dev, g);
+    hipLaunchKernelGGL(product_f32_kernel, dim3(grid), dim3(Layout<float>::NT), 0, s, st,
+                       bufs_dev, g);
   } else {
     hipLaunchKernelGGL(product_bf16_kernel, dim3(grid), dim3(kThreads), 0, s, st, bufs_dev, g);
   }
@@ -695,7 +737,7 @@ __device__ void finish(SnfState* s, int status) {
 
 __device__ void schedule_body(SnfState* __restrict__ s, const double* __restrict__ partials,
                               int count, int init) {
-  __shared__ double red[12];
+  __shared__ double red[24];
   double e2 = 0.0, t1 = 0.0, t2 = 0.0;
   for (int i = threadIdx.x; i < count; i += kReduceThreads) {
     e2 += partials[i * 4 + 0];
@@ -847,7 +889,7 @@ void launch_unpad_copy(const double* src, int64_t np, int64_t n, double* dst, in
 
 __global__ void sum_partials_kernel(const double* __restrict__ partials, int count,
                                     double* __restrict__ out3) {
-  __shared__ double red[12];
+  __shared__ double red[24];
   double a = 0.0, b = 0.0, c = 0.0;
   for (int i = threadIdx.x; i < count; i += kReduceThreads) {
     a += partials[i * 4 + 0];
@@ -898,7 +940,7 @@ __device__ __forceinline__ ProductGrid slot_grid(const SlotDesc& sd) {
 }
 
 template <typename T, int PREC>
-__global__ __launch_bounds__(256, 2) void grouped_product_kernel(const SlotDesc* __restrict__ slots,
+__global__ __launch_bounds__(Layout<T>::NT, 2) void grouped_product_kernel(const SlotDesc* __restrict__ slots,
                                                                  const int* __restrict__ active,
                                                                  const int* __restrict__ offs,
                                                                  int nactive) {
@@ -949,10 +991,10 @@ void launch_grouped_step(int prec_mask, const SlotDesc* slots, const int* active
   if (nactive <= 0) return;
   if (prec_mask & (1 << kPrecF64))
     hipLaunchKernelGGL((grouped_product_kernel<double, kPrecF64>), dim3(total_tiles),
-                       dim3(kThreads), 0, s, slots, active, offs, nactive);
+                       dim3(Layout<double>::NT), 0, s, slots, active, offs, nactive);
   if (prec_mask & (1 << kPrecF32))
     hipLaunchKernelGGL((grouped_product_kernel<float, kPrecF32>), dim3(total_tiles),
-                       dim3(kThreads), 0, s, slots, active, offs, nactive);
+                       dim3(Layout<float>::NT), 0, s, slots, active, offs, nactive);
   if (prec_mask & (1 << kPrecBF16))
     hipLaunchKernelGGL(grouped_product_bf16_kernel, dim3(total_tiles), dim3(kThreads), 0, s,
                        slots, active, offs, nactive);
