@@ -128,6 +128,58 @@ def run_small(args):
     return line
 
 
+def run_precision(args):
+    """n = 8192, spectrum in [-1, 1] with a 1e-3 gap at mu = 0.1 (N_occ = 4506), Haar Q:
+    FP64 against FP32 / BF16 products with FP64 refinement, each solve's distance to the
+    exact projector Q_occ Q_occ^T."""
+    import numpy as np
+    import torch
+    from paper_1101_0265_amd import hamiltonians as H
+    from paper_1101_0265_amd import snf
+    n, n_occ = 8192, 4506
+    lam = H.two_interval_spectrum(n_occ, n - n_occ, -1.0, 0.0995, 0.1005, 1.0,
+                                  np.random.default_rng(4))
+    F, Q = H.rotated_spectrum_torch(lam, seed=4)
+    qo = Q[:, :n_occ].contiguous()
+    D_exact = qo @ qo.T
+    del Q, qo
+    D = torch.empty_like(F)
+    kw = dict(lambda_min=-1.0, lambda_max=1.0, n_occ=n_occ, homo=0.0995, lumo=0.1005, mu=0.1,
+              xi=1e-3, tol=1e-8, max_iter=200)
+    runs = [("snf_varmu", "fp64", 0.0), ("sp2", "fp64", 0.0), ("snf_fixmu", "fp64", 0.0),
+            ("snf_varmu", "fp32_ref64", 0.0), ("snf_varmu", "fp32_ref64", 0.5),
+            ("snf_varmu", "fp32_ref64", 0.9), ("snf_varmu", "bf16_ref64", 0.5),
+            ("snf_varmu", "bf16_ref64", 0.9), ("snf_varmu", "fp32", 0.0)]
+    out = {}
+    for scheme, prec, gsw in runs:
+        snf.purify_dense(F, scheme, prec, out=D, want_log=False, gap_switch=gsw, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = max(1, args.steps)
+        for _ in range(steps):
+            _, r = snf.purify_dense(F, scheme, prec, out=D, want_log=False, gap_switch=gsw, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        err = float(torch.linalg.norm(D - D_exact))
+        comm = float(torch.linalg.norm(F @ D - D @ F))
+        out[f"{scheme}/{prec}/gsw{gsw}"] = dict(
+            ms=round(ms, 2), status=r["status"], products=r["products"],
+            products_fp64=r["products_fp64"], products_lowp=r["products_lowp"],
+            idem_err=r["idem_err"], trace_err=r["trace_err"], dist_to_exact_D=err,
+            commutator=comm)
+    base = out["snf_varmu/fp64/gsw0.0"]
+    line = _base_line("time-to-solution ms at ‖X²−X‖≤1e-8 by precision mode (n=8192)",
+                      base["ms"], "ms", args, False, "f64",
+                      {"workload": "dense n=8192, Haar Q, spectrum uniform in [-1,1] with a 1e-3 "
+                                   "gap at mu=0.1, N_occ=4506, tol 1e-8; FP64 vs FP32/BF16 "
+                                   "products + FP64 refinement"})
+    line["ms_per_step"] = base["ms"]
+    line["runs"] = out
+    line["speedup_vs_sp2"] = round(out["sp2/fp64/gsw0.0"]["ms"] / base["ms"], 3)
+    line["cpu_baseline"] = None
+    return line
+
+
 def run_bsr(args):
     """Block-sparse lattice 32x32x32 sites (n = 65536, 32x32 FP32 blocks, tau = 1e-6):
     time to the truncation floor, SnF varying-mu vs the trace scheme."""
@@ -295,7 +347,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="dense",
-                    choices=["dense", "small", "bsr", "serve"],
+                    choices=["dense", "small", "bsr", "serve", "precision"],
                     help="dense: n=4096 lattice (default line); small: n=256 gap-0.05 latency "
                          "of all five schemes; bsr: block-sparse 32^3-site lattice n=65536; "
                          "serve: 512-request continuous-batching trace")
@@ -322,7 +374,8 @@ def main():
     snf.lib()
     dev = torch.device("cuda:0")
     if args.workload != "dense":
-        line = {"small": run_small, "bsr": run_bsr, "serve": run_serve}[args.workload](args)
+        line = {"small": run_small, "bsr": run_bsr, "serve": run_serve,
+                "precision": run_precision}[args.workload](args)
         print(json.dumps(line), flush=True)
         return
     h = H.lattice_hamiltonian(LATTICE, seed=2)
@@ -393,7 +446,7 @@ def main():
     traffic = load_traffic()
     roofline = dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_FP64_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / PEAK_FP64_TFLOPS, 4),
-                    traffic=traffic, kernel="product_kernel<double> (f64 MFMA, 128x128 tiles)",
+                    traffic=traffic, kernel="product_f64_kernel (f64 MFMA, 128x128 tiles)",
                     avg_launch_ms=round(avg_launch_ms, 4),
                     flops_per_launch=flops_per_product)
     # HBM bytes an ideal product must move: read X (operand) once, write X_new, read the

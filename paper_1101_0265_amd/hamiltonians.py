@@ -431,3 +431,20 @@ def request_hamiltonian_torch(req: Request, device: str = "cuda:0",
                        n_occ=k, lambda_min=-1.0,
                        lambda_max=1.0, homo=float(homo), lumo=float(lumo),
                        mu=0.5 * (homo + lumo), xi=float(lumo - homo), eigvals=lam, Q=None)
+
+
+def rotated_spectrum_torch(eigvals: np.ndarray, seed: int, device: str = "cuda:0") -> tuple:
+    """(F, Q) as device tensors: F = Q diag(eigvals) Q^T symmetrised, Q Haar-orthogonal drawn
+    on the GPU (QR of a seeded Gaussian, sign-fixed).  For orders where host QR is slow."""
+    import torch
+
+    n = eigvals.size
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    z = torch.randn(n, n, generator=g, device=device, dtype=torch.float64)
+    q, r = torch.linalg.qr(z)
+    d = torch.sign(torch.diagonal(r))
+    d[d == 0] = 1.0
+    q = q * d[None, :]
+    f = (q * torch.tensor(eigvals, device=device)[None, :]) @ q.T
+    return (0.5 * (f + f.T)).contiguous(), q
