@@ -23,4 +23,5 @@ Everything here is plain FP64 NumPy/Python written from the paper:
 Parity status of each function is stated in its module header.
 """
 
-SCHEMES = ("sp2", "tc2", "snf_varmu", "mcweeny", "snf_fixmu")
+SCHEMES = ("sp2", "tc2", "snf_varmu", "mcweeny", "snf_fixmu",
+           "snf_fixmu3", "snf_fixmu5", "pmm3", "pmm5")

@@ -9,6 +9,9 @@ Follows the paper's steps on n x n matrices with ``numpy.matmul``:
   |tr(X^2) - N| < |2 tr X - tr(X^2) - N|.
 * Algorithm 1 (fixed-mu scale-and-fold) and its alpha = 1 form (McWeeny):
   X_0 = (mu I - F)/gamma + 0.5 I; X_s = a (X - 0.5 I) + 0.5 I; X <- 3 X_s^2 - 2 X_s^3.
+* The same with P_{3,3} or P_{5,5} in place of P_{1,1} (Eq. 2 for odd m): X <- P_{m,m}(X_s),
+  evaluated by Horner's rule in X_s on the exact coefficients; the count reported is the
+  scheme's m + 1 products per iteration, not the oracle's own.
 
 Stopping rule (reading of the open loop length): X_{i-1}^2 is formed, and if
 ||X_{i-1}^2 - X_{i-1}||_F <= tol the result is D = X_{i-1}.  The scheme's product count
@@ -27,6 +30,7 @@ import math
 
 import numpy as np
 
+from . import polynomials as poly
 from . import schedule as sch
 
 
@@ -49,9 +53,16 @@ def step(X: np.ndarray, branch: str, alpha: float) -> np.ndarray:
     if branch == sch.FOLD:
         return 2.0 * (1.0 + alpha) * X - (1.0 + alpha) ** 2 * (X @ X)
     Xs = alpha * (X - 0.5 * I) + 0.5 * I
-    Xs2 = Xs @ Xs
-    Xs3 = Xs2 @ Xs
-    return 3.0 * Xs2 - 2.0 * Xs3
+    if branch == sch.MCW:
+        Xs2 = Xs @ Xs
+        Xs3 = Xs2 @ Xs
+        return 3.0 * Xs2 - 2.0 * Xs3
+    m = 3 if branch == sch.PMM[3] else 5
+    c = [float(v) for v in poly.p_ij_exact(m, m)]
+    Y = c[-1] * I
+    for k in range(len(c) - 2, -1, -1):
+        Y = Y @ Xs + c[k] * I
+    return Y
 
 
 def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
@@ -71,7 +82,7 @@ def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
     X = f0(np.asarray(F, dtype=np.float64), scheme, lambda_min, lambda_max, mu)
     if mask is not None:
         X = mask(X)
-    per_it = 2 if scheme in ("mcweeny", "snf_fixmu") else 1
+    per_it = sch.products_per_iteration(scheme)
     log, branches = [], []
     products = 0
     status = "noconv"

@@ -7,9 +7,15 @@ the Hermite interpolation system; the closed forms used by the algorithms (P_{1,
 P_{0,1} = 2x - x^2, P_{1,1} = 3x^2 - 2x^3, Algorithm 1's update) are written separately and
 the tests pin one against the other.
 
-Parity: pinned (closed forms == definition; fixed points and derivative conditions).
+The higher-order fixed-mu schemes need P_{m,m} for odd m exactly: ``p_ij_exact`` solves the
+same Hermite system in rational arithmetic, so its coefficients carry no rounding.
+
+Parity: pinned (closed forms == definition; fixed points and derivative conditions; the exact
+coefficients against the binomial form of P_{i,j} and the derivative x^m (1-x)^m).
 """
 from __future__ import annotations
+
+from fractions import Fraction
 
 import numpy as np
 
@@ -63,3 +69,41 @@ def p01(x):
 def p11(x):
     """P_{1,1}(x) = 3x^2 - 2x^3 (McWeeny); odd in both ends, folds both sides."""
     return 3.0 * x * x - 2.0 * x * x * x
+
+
+def p_ij_exact(i: int, j: int) -> list:
+    """Monomial coefficients (ascending, ``Fraction``) of P_{i,j} from the same defining
+    conditions as ``p_ij_coefficients``, solved by exact Gaussian elimination."""
+    d = 1 + i + j
+
+    def deriv_row(x: int, k: int) -> list:
+        r = [Fraction(0)] * (d + 1)
+        for m in range(k, d + 1):
+            fac = 1
+            for t in range(k):
+                fac *= (m - t)
+            r[m] = Fraction(fac * (x ** (m - k)))
+        return r
+
+    rows = [deriv_row(0, k) + [Fraction(0)] for k in range(0, i + 1)]
+    rows.append(deriv_row(1, 0) + [Fraction(1)])
+    rows += [deriv_row(1, k) + [Fraction(0)] for k in range(1, j + 1)]
+    size = d + 1
+    for c in range(size):                       # exact elimination with row pivoting
+        piv = next(r for r in range(c, size) if rows[r][c] != 0)
+        rows[c], rows[piv] = rows[piv], rows[c]
+        for r in range(size):
+            if r != c and rows[r][c] != 0:
+                f = rows[r][c] / rows[c][c]
+                rows[r] = [a - f * b for a, b in zip(rows[r], rows[c])]
+    return [rows[k][size] / rows[k][k] for k in range(size)]
+
+
+def pmm(m: int, x):
+    """P_{m,m}(x) in FP64, Horner on the exact coefficients rounded once to FP64."""
+    c = [float(v) for v in p_ij_exact(m, m)]
+    x = np.asarray(x, dtype=np.float64) if not np.isscalar(x) else float(x)
+    y = c[-1]
+    for k in range(len(c) - 2, -1, -1):
+        y = y * x + c[k]
+    return y

@@ -14,6 +14,10 @@ evaluates the same expressions in the same order.
   trace-correcting scheme with the eigenvalue-based choice.
 * Trace rule (the original trace-correcting choice, paragraph after Eqs. 4-5): square iff
   |tr(X^2) - N| < |2 tr X - tr(X^2) - N|; a tie folds.
+* Higher-order fixed-mu scale-and-fold (the generalisation of Algorithm 1 to P_{m,m}, m odd,
+  stated with Eqs. 2 and 3): f_i(X) = P_{m,m}(alpha (X - 0.5 I) + 0.5 I), alpha >= 1 the root
+  of Eq. 3, beta <- P_{m,m}(alpha (beta - 0.5) + 0.5).  Eq. 3 has no closed form for m > 1; it
+  is solved here by bisection.  alpha = 1 gives the unscaled grand-canonical P_{m,m} scheme.
 
 Parity: pinned (Eq. 3 residual, closed-form images of the interval ends, alpha = 0 / 1
 reductions, exact-rational decisions).
@@ -22,9 +26,17 @@ from __future__ import annotations
 
 import math
 
+from . import polynomials as poly
+
 SQUARE = "S"   # P_{1,0} branch: X <- ((1+a) X - a I)^2
 FOLD = "F"     # P_{0,1} branch: X <- 2 (1+a) X - (1+a)^2 X^2
 MCW = "M"      # P_{1,1} branch: X <- 3 Xs^2 - 2 Xs^3, Xs = a (X - I/2) + I/2
+PMM = {3: "3", 5: "5"}   # P_{m,m} branch: X <- P_{m,m}(Xs)
+
+# scheme name -> (m, scaled) of the higher-order fixed-mu schemes
+HIGHER_ORDER = {"snf_fixmu3": (3, True), "snf_fixmu5": (5, True),
+                "pmm3": (3, False), "pmm5": (5, False)}
+FIXED_MU = ("mcweeny", "snf_fixmu") + tuple(HIGHER_ORDER)
 
 
 # ---- Algorithm 1 -----------------------------------------------------------------------
@@ -53,6 +65,39 @@ def alg1_beta_next(beta: float, alpha: float) -> float:
     """beta_s = alpha (beta - 0.5) + 0.5; beta <- 3 beta_s^2 - 2 beta_s^3."""
     bs = alpha * (beta - 0.5) + 0.5
     return 3.0 * bs * bs - 2.0 * bs * bs * bs
+
+
+# ---- Eq. 3 for P_{m,m} -------------------------------------------------------------------
+
+def pmm_alpha(m: int, beta: float) -> float:
+    """The root alpha >= 1 of Eq. 3, P(alpha (beta - 0.5) + 0.5) = P(0.5 (1 - alpha)), for
+    P = P_{m,m} (m odd) and 0 < beta < 0.5.
+
+    G(alpha) = P(0.5 (1 - alpha)) - P(alpha (beta - 0.5) + 0.5) is -P(beta) < 0 at alpha = 1
+    and P(0.5 (1 - alpha)) > 0 where the scaled gap edge reaches 0, alpha = 1 / (1 - 2 beta);
+    P decreases on x < 0 and increases on [0, 1], so G increases in between and the root is
+    unique.  Plain bisection until the bracket stops shrinking.
+    """
+    if not 0.0 < beta < 0.5:
+        raise ValueError("beta must lie in (0, 0.5)")
+
+    def G(a):
+        return poly.pmm(m, 0.5 * (1.0 - a)) - poly.pmm(m, a * (beta - 0.5) + 0.5)
+
+    lo, hi = 1.0, 1.0 / (1.0 - 2.0 * beta)
+    while True:
+        mid = 0.5 * (lo + hi)
+        if mid <= lo or mid >= hi:
+            return lo
+        if G(mid) < 0.0:
+            lo = mid
+        else:
+            hi = mid
+
+
+def pmm_beta_next(m: int, beta: float, alpha: float) -> float:
+    """beta <- P_{m,m}(alpha (beta - 0.5) + 0.5)."""
+    return float(poly.pmm(m, alpha * (beta - 0.5) + 0.5))
 
 
 # ---- Algorithm 2 -----------------------------------------------------------------------
@@ -98,6 +143,15 @@ def trace_margin(tr_x: float, tr_x2: float, n_occ: int) -> float:
     return abs(tr_x2 - n_occ) - abs(2.0 * tr_x - tr_x2 - n_occ)
 
 
+def products_per_iteration(scheme: str) -> int:
+    """Matrix products one f_i costs.  Algorithm 1: X_s^2 and X_s^3.  P_{m,m} (m odd): the
+    polynomial is point-symmetric about (1/2, 1/2), P(1/2 + v) = 1/2 + v r(v^2) with r of
+    degree m, so v^2, then r by Horner (m - 1 products), then v r: m + 1 products."""
+    if scheme in HIGHER_ORDER:
+        return HIGHER_ORDER[scheme][0] + 1
+    return 2 if scheme in ("mcweeny", "snf_fixmu") else 1
+
+
 # ---- one step of the scalar state (used by the spectral and dense drivers) --------------
 
 class SchemeState:
@@ -105,8 +159,9 @@ class SchemeState:
 
     scheme: "sp2" (trace rule, no scaling), "tc2" (Algorithm 2, alpha = 0),
     "snf_varmu" (Algorithm 2), "mcweeny" (Algorithm 1, alpha = 1), "snf_fixmu"
-    (Algorithm 1).  For "sp2" the tracked beta / beta-bar follow the branches actually taken
-    (they are reported only; the choice uses traces).
+    (Algorithm 1), "snf_fixmu3" / "snf_fixmu5" (scaled P_{3,3} / P_{5,5}), "pmm3" / "pmm5"
+    (the same with alpha = 1).  For "sp2" the tracked beta / beta-bar follow the branches
+    actually taken (they are reported only; the choice uses traces).
     """
 
     def __init__(self, scheme: str, lambda_min: float, lambda_max: float, *,
@@ -118,7 +173,7 @@ class SchemeState:
             self.betabar = (alg2_f0_scalar(homo, lambda_min, lambda_max)
                             if homo is not None else 1.0)
             self.gamma = None
-        elif scheme in ("mcweeny", "snf_fixmu"):
+        elif scheme in FIXED_MU:
             self.gamma = alg1_gamma(lambda_min, lambda_max, mu)
             self.beta = alg1_beta0(xi, self.gamma)
             self.betabar = 1.0 - self.beta
@@ -134,6 +189,9 @@ class SchemeState:
             if alg2_choose_square(self.beta, self.betabar):
                 return SQUARE, (alg2_square_alpha(self.beta) if s == "snf_varmu" else 0.0)
             return FOLD, (alg2_fold_alpha(self.betabar) if s == "snf_varmu" else 0.0)
+        if s in HIGHER_ORDER:
+            m, scaled = HIGHER_ORDER[s]
+            return PMM[m], (pmm_alpha(m, self.beta) if scaled and self.beta > 0.0 else 1.0)
         return MCW, (alg1_alpha(self.beta) if s == "snf_fixmu" else 1.0)
 
     def advance(self, branch: str, alpha: float) -> None:
@@ -143,8 +201,12 @@ class SchemeState:
         elif branch == FOLD:
             self.beta = alg2_fold_scalar(self.beta, alpha)
             self.betabar = alg2_fold_scalar(self.betabar, alpha)
-        else:
+        elif branch == MCW:
             self.beta = alg1_beta_next(self.beta, alpha)
+            self.betabar = 1.0 - self.beta
+        else:
+            m = 3 if branch == PMM[3] else 5
+            self.beta = pmm_beta_next(m, self.beta, alpha)
             self.betabar = 1.0 - self.beta
 
     def bound(self) -> float:

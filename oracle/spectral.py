@@ -20,6 +20,7 @@ import math
 
 import numpy as np
 
+from . import polynomials as poly
 from . import schedule as sch
 
 
@@ -41,12 +42,13 @@ def apply_branch(p: np.ndarray, branch: str, alpha: float) -> np.ndarray:
     if branch == sch.FOLD:                   # P_{0,1}((1+a) x), Eq. 5
         z = (1.0 + alpha) * p
         return 2.0 * z - z * z
-    xs = alpha * (p - 0.5) + 0.5             # P_{1,1}(a (x - 1/2) + 1/2), Eq. 2 with m = 1
-    return 3.0 * xs * xs - 2.0 * xs * xs * xs
+    xs = alpha * (p - 0.5) + 0.5             # P_{m,m}(a (x - 1/2) + 1/2), Eq. 2
+    if branch == sch.MCW:
+        return 3.0 * xs * xs - 2.0 * xs * xs * xs
+    return poly.pmm(3 if branch == sch.PMM[3] else 5, xs)
 
 
-def products_per_iteration(scheme: str) -> int:
-    return 2 if scheme in ("mcweeny", "snf_fixmu") else 1
+products_per_iteration = sch.products_per_iteration
 
 
 def purify_spectrum(eigvals: np.ndarray, scheme: str, *, lambda_min: float,
