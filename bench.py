@@ -99,7 +99,8 @@ def run_small(args):
     kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
               lumo=h.lumo, mu=h.mu, xi=h.xi, tol=1e-10, max_iter=100)
     out = {}
-    for scheme in ("snf_varmu", "snf_fixmu", "sp2", "tc2", "mcweeny"):
+    for scheme in ("snf_varmu", "snf_fixmu", "sp2", "tc2", "mcweeny", "snf_fixmu3",
+                   "snf_fixmu5", "pmm3", "pmm5"):
         for _ in range(args.warmup):
             snf.purify_dense(F, scheme, out=D, want_log=False, **kw)
         torch.cuda.synchronize()
@@ -147,6 +148,7 @@ def run_precision(args):
     kw = dict(lambda_min=-1.0, lambda_max=1.0, n_occ=n_occ, homo=0.0995, lumo=0.1005, mu=0.1,
               xi=1e-3, tol=1e-8, max_iter=200)
     runs = [("snf_varmu", "fp64", 0.0), ("sp2", "fp64", 0.0), ("snf_fixmu", "fp64", 0.0),
+            ("snf_fixmu3", "fp64", 0.0), ("snf_fixmu5", "fp64", 0.0), ("mcweeny", "fp64", 0.0),
             ("snf_varmu", "fp32_ref64", 0.0), ("snf_varmu", "fp32_ref64", 0.5),
             ("snf_varmu", "fp32_ref64", 0.9), ("snf_varmu", "bf16_ref64", 0.5),
             ("snf_varmu", "bf16_ref64", 0.9), ("snf_varmu", "fp32", 0.0)]

@@ -6,7 +6,7 @@
  * arXiv:1101.0265) by recursive purification, Eq. 1:
  *     X_0 = f_0(F),   X_i = f_i(X_{i-1}),  i = 1, 2, ...
  * where f_0 is linear and every f_i costs one matrix-matrix product X.X (two for
- * Algorithm 1).  Five schemes are offered:
+ * Algorithm 1, m + 1 for the P_{m,m} schemes).  Nine schemes are offered:
  *
  *   SNF_SP2_TRACE   second-order trace-correcting purification, x^2 / 2x - x^2 chosen from
  *                   the trace of X (the unscaled scheme the paper compares against).
@@ -15,6 +15,14 @@
  *   SNF_SNF_VARMU   Algorithm 2: varying-mu scale-and-fold, Eqs. 4 and 5.
  *   SNF_MCWEENY     Algorithm 1 with alpha = 1: regular grand-canonical McWeeny.
  *   SNF_SNF_FIXMU   Algorithm 1: McWeeny-based fixed-mu scale-and-fold, Eqs. 2 and 3.
+ *   SNF_SNF_FIXMU3  fixed-mu scale-and-fold with P_{3,3} (Eq. 2 for m = 3): alpha >= 1 is
+ *                   the root of Eq. 3, found on the device by bisection; 4 products per f_i.
+ *   SNF_SNF_FIXMU5  the same with P_{5,5}; 6 products per f_i.
+ *   SNF_PMM3        SNF_SNF_FIXMU3 with alpha = 1 (unscaled grand-canonical P_{3,3}).
+ *   SNF_PMM5        SNF_SNF_FIXMU5 with alpha = 1.
+ *   The P_{m,m} schemes evaluate P_{m,m}(1/2 + v) = 1/2 + v r(v^2) (the polynomial is
+ *   point-symmetric about (1/2, 1/2); r has degree m): v^2, r by Horner's rule, then v r.
+ *   They take the inputs of Algorithm 1 and run in SNF_P_FP64 only.
  *
  * Conventions shared by every entry point:
  *  - Matrices are row-major FP64.  Only the upper triangle of F (j >= i) is read; the
@@ -57,7 +65,11 @@ typedef enum {
   SNF_TC2_BETA = 1,
   SNF_SNF_VARMU = 2,
   SNF_MCWEENY = 3,
-  SNF_SNF_FIXMU = 4
+  SNF_SNF_FIXMU = 4,
+  SNF_SNF_FIXMU3 = 5,
+  SNF_SNF_FIXMU5 = 6,
+  SNF_PMM3 = 7,
+  SNF_PMM5 = 8
 } snf_scheme;
 
 typedef enum {
@@ -71,13 +83,16 @@ typedef enum {
 #define SNF_BRANCH_SQUARE 0   /* P_{1,0}: X <- ((1+a) X - a I)^2           (Eq. 4)          */
 #define SNF_BRANCH_FOLD   1   /* P_{0,1}: X <- 2 (1+a) X - (1+a)^2 X^2      (Eq. 5)          */
 #define SNF_BRANCH_P11    2   /* P_{1,1}: X <- 3 Xs^2 - 2 Xs^3, Xs = a (X - I/2) + I/2 (Eq. 2) */
+#define SNF_BRANCH_P33    3   /* P_{3,3}(Xs)                                                 */
+#define SNF_BRANCH_P55    4   /* P_{5,5}(Xs)                                                 */
 
 /* Flags (snf_params.flags). */
 #define SNF_FLAG_TIME_PRODUCTS 1  /* bracket every product kernel with HIP events and report
                                      their summed duration in snf_result.product_ms         */
 
 /*
- * Inputs of a purification (Algorithm 1 needs lambda_min, lambda_max, mu, xi; Algorithm 2
+ * Inputs of a purification (Algorithm 1 and the P_{m,m} schemes need lambda_min, lambda_max,
+ * mu, xi; Algorithm 2
  * and its alpha = 0 form need lambda_min, lambda_max, homo, lumo; the trace scheme needs
  * lambda_min, lambda_max, n_occ).
  *  lambda_min/lambda_max: bounds of the whole spectrum of F (lambda_min <= eig <= lambda_max).
@@ -194,7 +209,7 @@ typedef struct {
 
 /*
  * snf_purify_bsr -- purify a block-sparse symmetric F (schemes SNF_SP2_TRACE, SNF_TC2_BETA,
- * SNF_SNF_VARMU: one product per iteration; the Algorithm 1 schemes return SNF_EINVAL).
+ * SNF_SNF_VARMU: one product per iteration; the fixed-mu schemes return SNF_EINVAL).
  *   F:      caller-owned, device arrays; the pattern must be symmetric with every diagonal
  *           block present; only blocks (I,J) with I <= J (and the upper triangle of diagonal
  *           blocks) are read, the rest is taken as their transpose.
@@ -249,7 +264,8 @@ size_t snf_serve_request_bytes(int64_t n, snf_precision precision);
  * call returns, so the caller may reuse it).  D_host_out (n x n FP64, row-major) receives D
  * and must stay valid until snf_serve_poll reports completion.  Never waits for the GPU.
  * Returns SNF_OK and a ticket; SNF_EINVAL for bad arguments (checked as for
- * snf_purify_dense); SNF_ENOMEM if the request alone exceeds the budget. */
+ * snf_purify_dense; the P_{m,m} schemes are not served); SNF_ENOMEM if the request alone
+ * exceeds the budget. */
 int snf_serve_submit(snf_server* server, const double* F_host, int64_t n,
                      const snf_params* params, snf_scheme scheme, snf_precision precision,
                      double* D_host_out, uint64_t* ticket);
@@ -274,7 +290,8 @@ int snf_serve_timing(snf_server* server, uint64_t ticket, double* ms);
 /* Finish every queued and running request, stop the scheduler, release the arena. */
 int snf_serve_destroy(snf_server* server);
 
-/* Bytes of device workspace snf_purify_dense needs for order n (allocated on demand). */
+/* Bytes of device workspace snf_purify_dense needs for order n (allocated on demand); the
+   P_{m,m} schemes take one more n_pad x n_pad FP64 buffer (n_pad = n rounded up to 128). */
 size_t snf_workspace_bytes(int64_t n, snf_precision precision);
 
 /* Release the calling device's cached workspace (it is re-created on the next call). */

@@ -40,8 +40,8 @@ static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 struct Workspace {
   int64_t np = 0;          // padded order the buffers hold
   int lp_bytes = 0;        // bytes per element of the low-precision copies (0, 2, 4)
-  double* x[3] = {nullptr, nullptr, nullptr};
-  void* lp[3] = {nullptr, nullptr, nullptr};
+  double* x[4] = {nullptr, nullptr, nullptr, nullptr};
+  void* lp[4] = {nullptr, nullptr, nullptr, nullptr};
   double* partials = nullptr;
   int partial_cap = 0;
   double* split_buf = nullptr;       // kSplitCap slices of 64*256 doubles
@@ -70,7 +70,7 @@ static Workspace* workspace_for_current_device(int* dev_out) {
 }
 
 static void free_buffers(Workspace* w) {
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 4; ++i) {
     if (w->x[i]) (void)hipFree(w->x[i]);
     if (w->lp[i]) (void)hipFree(w->lp[i]);
     w->x[i] = nullptr;
@@ -80,7 +80,9 @@ static void free_buffers(Workspace* w) {
   w->lp_bytes = 0;
 }
 
-static int ensure_workspace(Workspace* w, int64_t np, int lp_bytes, int partial_need) {
+// nbuf: FP64 n_pad x n_pad buffers the call needs (3, or 4 for the P_{m,m} schemes).
+static int ensure_workspace(Workspace* w, int64_t np, int lp_bytes, int partial_need,
+                            int nbuf = 3) {
   if (!w->state) {
     SNF_HIP(hipMalloc(&w->state, sizeof(SnfState)));
     SNF_HIP(hipMalloc(&w->bufs_dev, sizeof(Buffers)));
@@ -127,6 +129,14 @@ static int ensure_workspace(Workspace* w, int64_t np, int lp_bytes, int partial_
     w->np = np;
     w->lp_bytes = lp_bytes;
   }
+  if (nbuf > 3 && !w->x[3]) {
+    const size_t elems = (size_t)w->np * (size_t)w->np;
+    if (hipMalloc(&w->x[3], elems * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      w->x[3] = nullptr;
+      return SNF_ENOMEM;
+    }
+  }
   return SNF_OK;
 }
 
@@ -153,7 +163,7 @@ int lowp_kind_for(snf_precision p) {
 // so a buffer of order w->np serves any np <= w->np.
 static int upload_buffers(Workspace* w, hipStream_t s) {
   Buffers b;
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 4; ++i) {
     b.x[i] = w->x[i];
     b.lp[i] = w->lp[i];
   }
@@ -166,7 +176,7 @@ static bool finite(double v) { return isfinite(v) != 0; }
 
 int validate(int64_t n, const snf_params* p, snf_scheme scheme, snf_precision prec) {
   if (!p || n <= 0) return SNF_EINVAL;
-  if ((int)scheme < SNF_SP2_TRACE || (int)scheme > SNF_SNF_FIXMU) return SNF_EINVAL;
+  if ((int)scheme < SNF_SP2_TRACE || (int)scheme > SNF_PMM5) return SNF_EINVAL;
   if ((int)prec < SNF_P_FP64 || (int)prec > SNF_P_BF16_REF64) return SNF_EINVAL;
   if (!finite(p->lambda_min) || !finite(p->lambda_max) || !(p->lambda_min < p->lambda_max))
     return SNF_EINVAL;
@@ -184,6 +194,12 @@ int validate(int64_t n, const snf_params* p, snf_scheme scheme, snf_precision pr
     case SNF_SNF_VARMU:
       if (!gap_edges) return SNF_EINVAL;
       break;
+    case SNF_SNF_FIXMU3:
+    case SNF_SNF_FIXMU5:
+    case SNF_PMM3:
+    case SNF_PMM5:
+      if (prec != SNF_P_FP64) return SNF_EINVAL;
+      [[fallthrough]];
     case SNF_MCWEENY:
     case SNF_SNF_FIXMU:
       if (!finite(p->mu) || !finite(p->xi) || !(p->mu > p->lambda_min) ||
@@ -217,7 +233,8 @@ void init_state(SnfState* s, int64_t n, const snf_params* p, snf_scheme scheme,
   s->lumo = p->lumo;
   s->gap_switch = p->gap_switch;
   s->lowp_floor = p->lowp_floor > 0.0 ? p->lowp_floor : (prec == SNF_P_BF16_REF64 ? 1e-2 : 1e-4);
-  if (scheme == SNF_MCWEENY || scheme == SNF_SNF_FIXMU) {
+  s->pmm_m = scheme_pmm_m(scheme);
+  if (scheme == SNF_MCWEENY || scheme == SNF_SNF_FIXMU || s->pmm_m) {
     s->gamma = sched::alg1_gamma(p->lambda_min, p->lambda_max, p->mu);
     s->beta = sched::alg1_beta0(p->xi, s->gamma);
     s->betabar = 1.0 - s->beta;
@@ -322,7 +339,8 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
   const int64_t np = round_up(n, kTile);
   const int sym = 1;
   const int tiles = num_product_tiles(np, sym);
-  rc = ensure_workspace(w, np, lowp_bytes_for(precision), tiles + 16 * kSplitCap);
+  rc = ensure_workspace(w, np, lowp_bytes_for(precision), tiles + 16 * kSplitCap,
+                        scheme_pmm_m(scheme) ? 4 : 3);
   if (rc != SNF_OK) {
     out->status = rc;
     return rc;
@@ -333,8 +351,8 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
   // np, so every buffer just needs np*np elements.
   init_state(w->state_host, n, params, scheme, precision);
   const bool time_products = (params->flags & SNF_FLAG_TIME_PRODUCTS) != 0;
-  const int per_it = (scheme == SNF_MCWEENY || scheme == SNF_SNF_FIXMU) ? 2 : 1;
-  const int max_steps = (params->max_iter + 1) * (per_it > 1 ? 2 : 1) + 1;
+  const int per_it = products_per_iteration(scheme);
+  const int max_steps = (params->max_iter + 1) * per_it + 1;
   if (time_products && (int)w->prod_ev.size() < 2 * max_steps) {
     const size_t old = w->prod_ev.size();
     w->prod_ev.resize(2 * max_steps);

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void f0_kernel(const double* __restrict__ F, i
                                                  int lowp_kind, double* __restrict__ partials) {
   __shared__ double tile[32][33];
   __shared__ double red[24];
-  const int alg1 = (st->scheme == SNF_MCWEENY || st->scheme == SNF_SNF_FIXMU);
+  const int alg1 = (st->scheme == SNF_MCWEENY || st->scheme == SNF_SNF_FIXMU || st->pmm_m);
   const double lmin = st->lambda_min, lmax = st->lambda_max, mu = st->mu, gamma = st->gamma;
   double* X = bufs->x[st->cur];
   void* LP = bufs->lp[st->cur];
@@ -686,13 +686,23 @@ __device__ void decide(SnfState* s) {
     br = sq ? SNF_BRANCH_SQUARE : SNF_BRANCH_FOLD;
     if (scheme == SNF_SNF_VARMU)
       a = sq ? sched::alg2_square_alpha(s->beta) : sched::alg2_fold_alpha(s->betabar);
+  } else if (scheme_pmm_m(scheme)) {
+    br = s->pmm_m == 3 ? SNF_BRANCH_P33 : SNF_BRANCH_P55;
+    a = (scheme == SNF_SNF_FIXMU3 || scheme == SNF_SNF_FIXMU5) ? sched::pmm_alpha(s->pmm_m, s->beta)
+                                                               : 1.0;
   } else {
     br = SNF_BRANCH_P11;
     a = (scheme == SNF_SNF_FIXMU) ? sched::alg1_alpha(s->beta) : 1.0;
   }
   s->branch = br;
   s->alpha = a;
-  if (br == SNF_BRANCH_SQUARE) {          // ((1+a) X - a I)^2 = (1+a)^2 P - 2a(1+a) X + a^2 I
+  if (br == SNF_BRANCH_P33 || br == SNF_BRANCH_P55) {
+    // W = (a (X - I/2))^2 = a^2 P - a^2 X + (a^2 / 4) I
+    const double a2 = a * a;
+    s->c2 = a2;
+    s->c1 = -a2;
+    s->c0 = 0.25 * a2;
+  } else if (br == SNF_BRANCH_SQUARE) {          // ((1+a) X - a I)^2 = (1+a)^2 P - 2a(1+a) X + a^2 I
     s->c2 = (1.0 + a) * (1.0 + a);
     s->c1 = -2.0 * a * (1.0 + a);
     s->c0 = a * a;
@@ -709,7 +719,13 @@ __device__ void decide(SnfState* s) {
   s->kind = kKindSquare;
   s->want_e = 1;
   s->ia = s->ib = s->ix = s->cur;
-  s->io = (br == SNF_BRANCH_P11) ? 2 : 1 - s->cur;
+  if (br == SNF_BRANCH_P33 || br == SNF_BRANCH_P55) {
+    s->bw = (s->cur + 1) & 3;
+    s->io = s->bw;
+    s->horner_left = s->pmm_m - 1;
+  } else {
+    s->io = (br == SNF_BRANCH_P11) ? 2 : 1 - s->cur;
+  }
 }
 
 __device__ void advance_beta(SnfState* s, int br, double a) {
@@ -720,10 +736,53 @@ __device__ void advance_beta(SnfState* s, int br, double a) {
   } else if (br == SNF_BRANCH_FOLD) {
     s->beta = sched::alg2_fold_map(s->beta, a);
     s->betabar = sched::alg2_fold_map(s->betabar, a);
-  } else {
+  } else if (br == SNF_BRANCH_P11) {
     s->beta = sched::alg1_beta_next(s->beta, a);
     s->betabar = 1.0 - s->beta;
+  } else {
+    s->beta = sched::pmm_beta_next(s->pmm_m, s->beta, a);
+    s->betabar = 1.0 - s->beta;
   }
+}
+
+// Set up the next product of a P_{m,m} iteration once the previous one finished:
+// P(1/2 + v) = 1/2 + v r(v^2), v = a (X - I/2), W = v^2.  After W: T = r_m W^2 + r_{m-1} W
+// + r_{m-2} I from W.W; then T <- W.T + r_k I down to k = 0; then X_new = 1/2 I + v T.
+__device__ void pmm_next(SnfState* s) {
+#pragma clang fp contract(off)
+  const int m = s->pmm_m;
+  double r[sched::kPmmMaxM + 1];
+  sched::pmm_coeffs(m, r);
+  const int ta = (s->cur + 2) & 3, tb = (s->cur + 3) & 3;
+  s->want_e = 0;
+  if (s->kind == kKindSquare) {             // W done: first Horner level from W.W
+    s->kind = kKindHorner;
+    s->ia = s->ib = s->ix = s->bw;
+    s->io = s->bt = ta;
+    s->c2 = r[m];
+    s->c1 = r[m - 1];
+    s->c0 = r[m - 2];
+    return;
+  }
+  if (s->kind == kKindHorner && s->horner_left > 0) {   // T <- W.T + r_k I
+    const int k = s->horner_left - 1;
+    s->ia = s->bw;
+    s->ib = s->ix = s->bt;
+    s->io = (s->bt == ta) ? tb : ta;
+    s->bt = s->io;
+    s->c2 = 1.0;
+    s->c1 = 0.0;
+    s->c0 = r[k];
+    return;
+  }
+  // T = r(W) done: X_new = a X.T - (a / 2) T + I / 2, written over W
+  s->kind = kKindFinal;
+  s->ia = s->cur;
+  s->ib = s->ix = s->bt;
+  s->io = s->bw;
+  s->c2 = s->alpha;
+  s->c1 = -0.5 * s->alpha;
+  s->c0 = 0.5;
 }
 
 __device__ void finish(SnfState* s, int status) {
@@ -753,10 +812,10 @@ __device__ void schedule_body(SnfState* __restrict__ s, const double* __restrict
     decide(s);
     return;
   }
+  s->products += 1;
+  if (s->prec == kPrecF64) s->products_f64 += 1; else s->products_lowp += 1;
   if (s->kind == kKindSquare) {
     const double e = sqrt(e2);
-    s->products += 1;
-    if (s->prec == kPrecF64) s->products_f64 += 1; else s->products_lowp += 1;
     s->e_last = e;
     const int it = s->iter;
     snf_log_rec* rec = &s->log[it < SNF_LOG_MAX ? it : SNF_LOG_MAX - 1];
@@ -787,6 +846,10 @@ __device__ void schedule_body(SnfState* __restrict__ s, const double* __restrict
       }
     }
     if (it >= s->max_iter) { rec->branch = -1; finish(s, SNF_ENOCONV); return; }
+    if (s->pmm_m) {
+      pmm_next(s);
+      return;
+    }
     if (s->branch == SNF_BRANCH_P11) {
       // second product of Algorithm 1: R = S2.X; X_new = (3 - 2c) S2 - 2 a R
       const double a = s->alpha, c = 0.5 * (1.0 - a);
@@ -807,10 +870,11 @@ __device__ void schedule_body(SnfState* __restrict__ s, const double* __restrict
     s->t1 = t1;
     s->t2 = t2;
     decide(s);
-  } else {
-    s->products += 1;
-    if (s->prec == kPrecF64) s->products_f64 += 1; else s->products_lowp += 1;
-    advance_beta(s, SNF_BRANCH_P11, s->alpha);
+  } else if (s->kind == kKindHorner) {
+    s->horner_left -= 1;
+    pmm_next(s);
+  } else {                                  // kKindCube or kKindFinal: X_new is complete
+    advance_beta(s, s->branch, s->alpha);
     s->iter += 1;
     s->cur = s->io;
     s->t1 = t1;

@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdint.h>
 
 namespace snf {
 namespace sched {
@@ -36,6 +37,77 @@ __host__ __device__ inline double alg1_beta_next(double beta, double alpha) {
 #pragma clang fp contract(off)
   const double bs = alpha * (beta - 0.5) + 0.5;
   return 3.0 * bs * bs - 2.0 * bs * bs * bs;
+}
+
+// ---- P_{m,m}, m odd: the higher-order fixed-mu schemes (Eqs. 2 and 3) ------------------
+//
+// P_{m,m} is point-symmetric about (1/2, 1/2) and P'(x) = c_m x^m (1 - x)^m with
+// c_m = (2m+1)! / (m!)^2.  With x = 1/2 + v, P'(x) = c_m (1/4 - v^2)^m; integrating term by
+// term from v = 0 gives P(1/2 + v) = 1/2 + v r(v^2) with
+//   r_k = c_m C(m, k) (-1)^k 4^(k-m) / (2k + 1),   k = 0..m.
+// For m = 1, 3, 5 each c_m C(m, k) is divisible by 2k + 1, so every r_k is an integer times a
+// power of two: exact in FP64.
+constexpr int kPmmMaxM = 5;
+
+__host__ __device__ inline double pmm_r(int m, int k) {
+  int64_t fact = 1;
+  for (int t = 2; t <= 2 * m + 1; ++t) fact *= t;
+  int64_t fm = 1;
+  for (int t = 2; t <= m; ++t) fm *= t;
+  const int64_t cm = fact / (fm * fm);
+  int64_t binom = 1;
+  for (int t = 0; t < k; ++t) binom = binom * (m - t) / (t + 1);
+  const int64_t q = cm * binom / (2 * k + 1);
+  double p4 = 1.0;
+  for (int t = k; t < m; ++t) p4 *= 0.25;
+  return (double)((k & 1) ? -q : q) * p4;
+}
+
+// r_0..r_m of pmm_r into r[] (the coefficients of the matrix evaluation)
+__host__ __device__ inline void pmm_coeffs(int m, double* r) {
+  for (int k = 0; k <= m; ++k) r[k] = pmm_r(m, k);
+}
+
+// P_{m,m}(x) = x^(m+1) sum_{k=0..m} C(m+k, k) (1-x)^k (the incomplete-beta form of P_{i,j}),
+// accurate relative to its value near x = 0, where the scalar schedule evaluates it: the
+// centred form 1/2 + v r(v^2) cancels there.  Horner's rule in y = 1 - x.
+__host__ __device__ inline double pmm_eval(int m, double x) {
+#pragma clang fp contract(off)
+  const double y = 1.0 - x;
+  double binom = 1.0;                        // C(m+k, k) for k = m, built upwards first
+  for (int t = 1; t <= m; ++t) binom = binom * (double)(m + t) / (double)t;
+  double acc = binom;
+  for (int k = m - 1; k >= 0; --k) {
+    binom = binom * (double)(k + 1) / (double)(m + k + 1);   // C(m+k, k) from C(m+k+1, k+1)
+    acc = acc * y + binom;
+  }
+  double xp = x;
+  for (int t = 0; t < m; ++t) xp = xp * x;
+  return xp * acc;
+}
+
+// The root alpha >= 1 of Eq. 3, P(alpha (beta - 1/2) + 1/2) = P((1 - alpha) / 2), for
+// 0 < beta < 1/2: G(alpha) = P((1 - alpha) / 2) - P(alpha (beta - 1/2) + 1/2) is -P(beta) < 0
+// at alpha = 1 and positive at alpha = 1 / (1 - 2 beta) (the scaled gap edge reaches 0); P
+// falls on x < 0 and rises on [0, 1], so G increases in between and bisection converges to
+// the unique root.  Outside (0, 1/2), alpha = 1.
+__host__ __device__ inline double pmm_alpha(int m, double beta) {
+#pragma clang fp contract(off)
+  if (!(beta > 0.0 && beta < 0.5)) return 1.0;
+  double lo = 1.0, hi = 1.0 / (1.0 - 2.0 * beta);
+  for (int it = 0; it < 2200; ++it) {     // a bracket of doubles stops shrinking long before
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    const double g = pmm_eval(m, 0.5 * (1.0 - mid)) - pmm_eval(m, mid * (beta - 0.5) + 0.5);
+    if (g < 0.0) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// beta <- P_{m,m}(alpha (beta - 1/2) + 1/2)
+__host__ __device__ inline double pmm_beta_next(int m, double beta, double alpha) {
+#pragma clang fp contract(off)
+  return pmm_eval(m, alpha * (beta - 0.5) + 0.5);
 }
 
 // ---- Algorithm 2 (P_{0,1} & P_{1,0} varying-mu purification) ---------------------------

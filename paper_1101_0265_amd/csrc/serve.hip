@@ -233,6 +233,8 @@ static int start_request(snf_server* sv, ServeRequest* r) {
     b.x[i] = (double*)(base + L.x[i]);
     b.lp[i] = lowp_bytes_for(r->prec) ? (void*)(base + L.lp[i]) : nullptr;
   }
+  b.x[3] = nullptr;      // the fourth buffer serves only the P_{m,m} schemes, not served
+  b.lp[3] = nullptr;
   SlotDesc& d = sv->desc_stage[k];
   d.st = sv->states + k;
   d.bufs = sv->bufs + k;
@@ -521,6 +523,7 @@ int snf_serve_submit(snf_server* sv, const double* F_host, int64_t n, const snf_
                      uint64_t* ticket) {
   if (!sv || !F_host || !D_host_out || !ticket) return SNF_EINVAL;
   int rc = validate(n, params, scheme, precision);
+  if (rc == SNF_OK && scheme_pmm_m(scheme)) rc = SNF_EINVAL;   // three buffers per request
   if (rc != SNF_OK) return rc;
   ServeRequest* r = new_request(sv, n, params, scheme, precision);
   r->D_host = D_host_out;
@@ -545,6 +548,7 @@ int snf_serve_submit_device(snf_server* sv, const double* F_dev, int64_t n,
   if (!sv || !F_dev || !D_dev_out || !ticket || (const void*)F_dev == (const void*)D_dev_out)
     return SNF_EINVAL;
   int rc = validate(n, params, scheme, precision);
+  if (rc == SNF_OK && scheme_pmm_m(scheme)) rc = SNF_EINVAL;   // three buffers per request
   if (rc != SNF_OK) return rc;
   ServeRequest* r = new_request(sv, n, params, scheme, precision);
   r->device_io = true;

@@ -24,8 +24,23 @@ enum : int32_t { kPhaseHigh = 0, kPhaseLow = 1, kPhaseRefine = 2 };
 // Kind of the pending product.
 enum : int32_t {
   kKindSquare = 0,   // P = X.X, epilogue Y = c2 P + c1 X + c0 I, idempotency of X checked
-  kKindCube = 1      // Algorithm 1 second product: R = S2.X, Y = c2 R + c1 S2
+  kKindCube = 1,     // Algorithm 1 second product: R = S2.X, Y = c2 R + c1 S2
+  kKindHorner = 2,   // P_{m,m} schemes: T <- W.T + r_k I (or the first level from W.W)
+  kKindFinal = 3     // P_{m,m} schemes: X_new = a X.T0 - (a/2) T0 + I/2
 };
+
+// m of a P_{m,m} scheme (3 or 5), 0 for the other schemes.
+inline __host__ __device__ int scheme_pmm_m(int scheme) {
+  return (scheme == SNF_SNF_FIXMU3 || scheme == SNF_PMM3) ? 3
+       : (scheme == SNF_SNF_FIXMU5 || scheme == SNF_PMM5) ? 5 : 0;
+}
+
+// Matrix products one f_i costs.
+inline int products_per_iteration(int scheme) {
+  const int m = scheme_pmm_m(scheme);
+  if (m) return m + 1;
+  return (scheme == SNF_MCWEENY || scheme == SNF_SNF_FIXMU) ? 2 : 1;
+}
 
 // Scalar state of one purification, resident in device memory.  Written by the host
 // once (configuration), then only by the schedule kernel (one thread).
@@ -56,17 +71,21 @@ struct SnfState {
   int32_t status;         // final snf status code once stop != 0
   int32_t cur;            // buffer index holding X_cur
   int32_t ia, ib, ix, io; // operand / linear-term / output buffer indices of the pending product
+  int32_t pmm_m;          // m of a P_{m,m} scheme, else 0
+  int32_t horner_left;    // P_{m,m}: Horner products still to run in this iteration
+  int32_t bw, bt;         // P_{m,m}: buffers holding W = (a (X - I/2))^2 and the last T
   int32_t want_e;         // pending product checks idempotency of its A operand
   int32_t write_lowp;     // epilogue also writes the low-precision operand copy
   int32_t nlog;
   snf_log_rec log[SNF_LOG_MAX];
 };
 
-// Buffers of one purification: three FP64 n_pad x n_pad matrices and, for precision modes,
-// their low-precision operand copies (FP32 or BF16, same indices).
+// Buffers of one purification: three FP64 n_pad x n_pad matrices (four for the P_{m,m}
+// schemes) and, for precision modes, their low-precision operand copies (FP32 or BF16, same
+// indices).
 struct Buffers {
-  double* x[3];
-  void* lp[3];
+  double* x[4];
+  void* lp[4];
 };
 
 // ---- kernels launched by the host drivers (defined in kernels_dense.hip) ----------------

@@ -21,9 +21,10 @@ STATUS_NAMES = {OK: "ok", PENDING: "pending", OK_FLOOR: "ok_floor", EINVAL: "ein
                 ENOMEM: "enomem", ENOCONV: "noconv", ENONFINITE: "nonfinite", EMIXED: "mixed",
                 EDEVICE: "edevice"}
 
-SCHEMES = {"sp2": 0, "tc2": 1, "snf_varmu": 2, "mcweeny": 3, "snf_fixmu": 4}
+SCHEMES = {"sp2": 0, "tc2": 1, "snf_varmu": 2, "mcweeny": 3, "snf_fixmu": 4,
+           "snf_fixmu3": 5, "snf_fixmu5": 6, "pmm3": 7, "pmm5": 8}
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_ref64": 2, "bf16_ref64": 3}
-BRANCH_LETTERS = {0: "S", 1: "F", 2: "M"}
+BRANCH_LETTERS = {0: "S", 1: "F", 2: "M", 3: "3", 4: "5"}
 LOG_MAX = 256
 FLAG_TIME_PRODUCTS = 1
 
