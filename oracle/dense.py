@@ -20,7 +20,9 @@ itself spends extra products (it forms X^2 for the check separately from the ste
 slow on purpose and the count it reports is the scheme's, not its own.
 
 ``mask`` (optional): a callable applied to each new X, used by the block-truncation oracle
-(drop blocks below a threshold after every step, the BSR reading).
+(drop blocks below a threshold after every step, the BSR reading).  A mask with
+``needs_gap = True`` is called as ``mask(X, gap)`` with the X-space gap beta-bar - beta of
+the new iterate (the error-controlled rule) and is not applied to X_0.
 
 Parity: pinned against the exact projector, its invariants and the spectral oracle.
 """
@@ -80,7 +82,8 @@ def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
         raise ValueError("F must be square")
     st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi)
     X = f0(np.asarray(F, dtype=np.float64), scheme, lambda_min, lambda_max, mu)
-    if mask is not None:
+    gap_mask = mask is not None and getattr(mask, "needs_gap", False)
+    if mask is not None and not gap_mask:
         X = mask(X)
     per_it = sch.products_per_iteration(scheme)
     log, branches = [], []
@@ -112,9 +115,11 @@ def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
         log.append(rec)
         branches.append(branch)
         X = step(X, branch, alpha)
-        if mask is not None:
-            X = mask(X)
         st.advance(branch, alpha)
+        if gap_mask:
+            X = mask(X, st.betabar - st.beta)
+        elif mask is not None:
+            X = mask(X)
         products += per_it - 1
     if n_occ is not None and status == "ok" and abs(float(np.trace(X)) - n_occ) >= 0.5:
         status = "mixed"
@@ -140,3 +145,91 @@ def block_truncation_mask(b: int, tau: float):
         return (blocks * keep[:, None, :, None]).reshape(n, n)
 
     return apply
+
+
+# ---- error-controlled block truncation ------------------------------------------------
+#
+# The paper expects the schemes, being of the form of Eq. 1, to combine with forward-error
+# control of the truncation, and fewer iterations to allow more aggressive truncation each
+# (sparsity paragraph after the bounds paragraph).  The rule used here (a reading; the paper
+# gives none): a symmetric perturbation E of an iterate whose X-space gap is g turns its
+# occupied subspace by at most ~||E||_F / g (Davis-Kahan), and later iterations keep that
+# subspace, so the error of D is bounded to first order by sum_i sqrt(2) ||E_i||_F / g_i.
+# With N iterations predicted by the scalar recurrence and a budget eps for ||D~ - D||_F,
+# iteration i may drop blocks of total Frobenius norm eps_i = eps g_i / (sqrt(2) N).
+# Dropped blocks are chosen on a quarter-octave grid of block norms (half-octaves of the
+# squared norm s): bin(s) = floor(2 log2 s), decided exactly from the binary exponent and
+# the mantissa against fl(sqrt 2), clamped to [BIN_MIN, BIN_MAX]; each bin is charged
+# count * 2^((j+1)/2) (its upper edge), mirror blocks included; the lowest bins are dropped
+# while their charge stays within eps_i^2.  Diagonal blocks are never dropped.
+
+BIN_MIN, BIN_MAX = -160, 40
+SQRT2 = math.sqrt(2.0)
+
+
+def half_octave_bin(s: np.ndarray) -> np.ndarray:
+    """floor(2 log2 s) for s > 0 (exact), clamped to [BIN_MIN, BIN_MAX]; s = 0 -> BIN_MIN."""
+    s = np.asarray(s, dtype=np.float64)
+    m, e = np.frexp(s)                 # s = m 2^e, m in [0.5, 1)
+    m2, e2 = 2.0 * m, e - 1            # s = m2 2^e2, m2 in [1, 2)
+    j = 2 * e2 + (m2 >= SQRT2).astype(np.int64)
+    j = np.where(s > 0.0, j, BIN_MIN)
+    return np.clip(j, BIN_MIN, BIN_MAX)
+
+
+def drop_bin_limit(bins: np.ndarray, weights: np.ndarray, eps_i: float) -> int:
+    """Largest k such that the blocks with bin < k may be dropped: sum over bins j < k of
+    weight * 2^((j+1)/2) <= eps_i^2.  Returns BIN_MIN if not even the lowest bin fits."""
+    budget = eps_i * eps_i
+    charge = 0.0
+    k = BIN_MIN
+    for j in range(BIN_MIN, BIN_MAX + 1):
+        w = float(np.sum(weights[bins == j]))
+        if w == 0.0:
+            k = j + 1
+            continue
+        c = w * 2.0 ** ((j + 1) / 2.0)
+        if charge + c > budget:
+            return j
+        charge += c
+        k = j + 1
+    return k
+
+
+def predicted_iterations(scheme: str, *, lambda_min: float, lambda_max: float, homo: float,
+                         lumo: float, eps: float, max_iter: int = 200) -> int:
+    """Iterations the scalar recurrence takes until max(beta, 1 - beta-bar) <= eps (the trace
+    scheme, whose choice needs the matrix, is predicted by its alpha = 0 recurrence)."""
+    sch_name = "tc2" if scheme == "sp2" else scheme
+    st = sch.SchemeState(sch_name, lambda_min, lambda_max, homo=homo, lumo=lumo)
+    for it in range(max_iter):
+        if st.bound() <= eps:
+            return max(it, 1)
+        branch, alpha = st.choose()
+        st.advance(branch, alpha)
+    return max_iter
+
+
+class ErrorControlledTruncation:
+    """Mask for the error-controlled block truncation (rule above); call as mask(X, gap)."""
+
+    needs_gap = True
+
+    def __init__(self, b: int, eps: float, n_iter: int):
+        self.b, self.eps, self.n_iter = b, eps, max(int(n_iter), 1)
+        self.history = []              # (eps_i, k, dropped Frobenius^2) per call
+
+    def __call__(self, X: np.ndarray, gap: float) -> np.ndarray:
+        n, b = X.shape[0], self.b
+        nb = n // b
+        blocks = X.reshape(nb, b, nb, b)
+        s = np.einsum("ibjc,ibjc->ij", blocks, blocks)
+        present = np.any(blocks != 0.0, axis=(1, 3))
+        upper = np.triu(present, 1)
+        eps_i = self.eps * gap / (SQRT2 * self.n_iter)
+        bins = half_octave_bin(s)
+        k = drop_bin_limit(bins[upper], np.full(int(upper.sum()), 2.0), eps_i)
+        drop = upper & (bins < k)
+        drop = drop | drop.T
+        self.history.append((eps_i, k, float(np.sum(s[drop]))))
+        return (blocks * (~drop)[:, None, :, None]).reshape(n, n)

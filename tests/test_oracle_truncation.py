@@ -1,0 +1,96 @@
+"""Pins of the error-controlled block truncation rule of the CPU oracle (no GPU).
+
+The rule (a reading; the sparsity paragraph of the paper asks for forward-error control but
+gives no rule): iteration i may drop blocks of total Frobenius norm eps g_i / (sqrt(2) N),
+chosen on a half-octave grid of squared block norms with each bin charged at its upper edge.
+Pinned against: exact rational binning, brute-force maximality of the dropped set, and the
+property the rule is built for -- the final D stays within eps of the exact projector.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import dense, exact
+from paper_1101_0265_amd import hamiltonians as H
+
+
+def _pow2(j: int) -> Fraction:
+    return Fraction(2 ** j) if j >= 0 else Fraction(1, 2 ** (-j))
+
+
+def _exact_bin(s: float) -> int:
+    """floor(2 log2 s) = max j with 2^j <= s^2, in rational arithmetic."""
+    q = Fraction(s) ** 2
+    j = q.numerator.bit_length() - q.denominator.bit_length()
+    while _pow2(j) > q:
+        j -= 1
+    while _pow2(j + 1) <= q:
+        j += 1
+    return j
+
+
+def test_half_octave_bin_is_exact():
+    rng = np.random.default_rng(0)
+    s = np.exp(rng.uniform(-150, 20, 3000))
+    edges = np.array([2.0 ** (k / 2) for k in range(-200, 40)])        # boundaries themselves
+    near = np.concatenate([np.nextafter(edges, 0), edges, np.nextafter(edges, np.inf)])
+    s = np.concatenate([s, near[(near > 2.0 ** -80) & (near < 2.0 ** 20)]])
+    got = dense.half_octave_bin(s)
+    want = np.clip([_exact_bin(float(v)) for v in s], dense.BIN_MIN, dense.BIN_MAX)
+    assert np.array_equal(got, want)
+    assert dense.half_octave_bin(np.array([0.0]))[0] == dense.BIN_MIN
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_drop_limit_is_maximal_within_budget(seed):
+    rng = np.random.default_rng(seed)
+    bins = rng.integers(-60, 5, 400)
+    w = np.full(400, 2.0)
+    eps_i = 10.0 ** rng.uniform(-12, -1)
+
+    def charge(k):
+        return sum(float(np.sum(w[bins == j])) * 2.0 ** ((j + 1) / 2.0)
+                   for j in range(dense.BIN_MIN, k))
+
+    k = dense.drop_bin_limit(bins, w, eps_i)
+    assert charge(k) <= eps_i ** 2
+    nxt = [j for j in np.unique(bins) if j >= k]
+    if nxt:                                     # one more occupied bin would exceed
+        assert charge(int(nxt[0]) + 1) > eps_i ** 2
+
+
+@pytest.mark.parametrize("scheme", ["tc2", "snf_varmu"])
+@pytest.mark.parametrize("eps", [1e-2, 1e-3])
+def test_error_budget_holds_on_lattice(scheme, eps):
+    """16x8x8 sites (n = 2048, 64 block rows): the truncated iteration's result stays within
+    eps of the exact projector, and every step stays within its own share of the budget."""
+    m, h = H.lattice_bsr((16, 8, 8), seed=3, dtype=np.float64)
+    Fd = m.to_dense()
+    D_ref = exact.projector(F=Fd, n_occ=h.n_occ)
+    kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, homo=h.homo, lumo=h.lumo)
+    N = dense.predicted_iterations(scheme, eps=eps, **kw)
+    mk = dense.ErrorControlledTruncation(32, eps, N)
+    o = dense.purify(Fd, scheme, n_occ=h.n_occ, tol=1e-12, max_iter=N + 6, mask=mk, **kw)
+    assert np.linalg.norm(o["D"] - D_ref) <= eps
+    assert any(d > 0.0 for _, _, d in mk.history)          # the rule did drop blocks
+    for eps_i, _, dropped2 in mk.history:
+        assert dropped2 <= eps_i ** 2
+    assert abs(o["trace"] - h.n_occ) < 0.5
+
+
+def test_predicted_iterations_reach_the_bound():
+    from oracle import schedule as sch
+    kw = dict(lambda_min=-1.4, lambda_max=1.4, homo=-0.18, lumo=0.18)
+    for scheme in ("tc2", "snf_varmu"):
+        for eps in (1e-2, 1e-6):
+            N = dense.predicted_iterations(scheme, eps=eps, **kw)
+            st = sch.SchemeState(scheme, kw["lambda_min"], kw["lambda_max"], homo=kw["homo"],
+                                 lumo=kw["lumo"])
+            bounds = []
+            for _ in range(N):
+                bounds.append(st.bound())
+                st.advance(*st.choose())
+            assert st.bound() <= eps < bounds[-1]
+    assert dense.predicted_iterations("sp2", eps=1e-6, **kw) == \
+        dense.predicted_iterations("tc2", eps=1e-6, **kw)
