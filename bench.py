@@ -182,6 +182,34 @@ def run_precision(args):
     return line
 
 
+def _bsr_mm(rp, ci, va, Z):
+    """Y = M Z for a BSR matrix M (32x32 blocks, device tensors) and a dense (n, p) float64
+    block of vectors, by batched block products (measurement helper)."""
+    import torch
+    nb = rp.numel() - 1
+    p = Z.shape[1]
+    rows = torch.repeat_interleave(torch.arange(nb, device=Z.device), rp[1:] - rp[:-1])
+    Zb = Z.reshape(nb, 32, p)
+    out = torch.zeros(nb, 32, p, dtype=torch.float64, device=Z.device)
+    step = 65536
+    for c0 in range(0, ci.numel(), step):
+        c1 = min(c0 + step, ci.numel())
+        G = Zb[ci[c0:c1].long()].contiguous()
+        V = va[c0:c1].double().contiguous()
+        out.index_add_(0, rows[c0:c1], torch.bmm(V, G))
+    return out.reshape(nb * 32, p)
+
+
+def _bsr_commutator(Fm, Dm, n, probes=4, seed=0):
+    """Hutchinson estimate of ||F D - D F||_F: E ||[F, D] z||^2 over Gaussian z."""
+    import torch
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(seed)
+    Z = torch.randn(n, probes, generator=g, device="cuda:0", dtype=torch.float64)
+    C = _bsr_mm(*Fm, _bsr_mm(*Dm, Z)) - _bsr_mm(*Dm, _bsr_mm(*Fm, Z))
+    return float(torch.sqrt((C * C).sum() / probes))
+
+
 def run_bsr(args):
     """Block-sparse lattice 32x32x32 sites (n = 65536, 32x32 FP32 blocks, tau = 1e-6):
     time to the truncation floor, SnF varying-mu vs the trace scheme."""
@@ -211,6 +239,29 @@ def run_bsr(args):
             print(json.dumps(dict(scheme=scheme, tau=tau, ms=round(ms, 1),
                                   products=r["products"], status=r["status"],
                                   e=r["idem_err"], trace_err=r["trace_err"],
+                                  blocks_per_row=round(r["blocks"] / m.nb, 1),
+                                  peak_blocks_per_row=round(peak, 1))), flush=True)
+            del D
+    if args.bsr_ec:
+        # fixed threshold against error-controlled truncation at several budgets; accuracy
+        # from ||[F, D]||_F (no exact D at this size)
+        D, _ = snf.purify_bsr(rp, ci, va, m.n, "tc2", trunc_tau=1e-2, want_log=False,
+                              **dict(kw, flags=kw["flags"] | snf.FLAG_TRUNC_ERROR_CONTROL))
+        del D
+        runs = [(sc, "tau", 1e-6) for sc in ("tc2", "snf_varmu")]
+        runs += [(sc, "eps", e) for sc in ("tc2", "snf_varmu") for e in (1e-1, 3e-2, 1e-2, 3e-3)]
+        for scheme, kind, val in runs:
+            fl = kw["flags"] | (snf.FLAG_TRUNC_ERROR_CONTROL if kind == "eps" else 0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            D, r = snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=val, **dict(kw, flags=fl))
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            comm = _bsr_commutator((rp, ci, va), D, m.n)
+            peak = max(x["phase"] for x in r["log"]) / m.nb
+            print(json.dumps(dict(scheme=scheme, rule=kind, value=val, ms=round(ms, 1),
+                                  products=r["products"], status=r["status"],
+                                  e=r["idem_err"], trace_err=r["trace_err"], commutator=comm,
                                   blocks_per_row=round(r["blocks"] / m.nb, 1),
                                   peak_blocks_per_row=round(peak, 1))), flush=True)
             del D
@@ -356,6 +407,9 @@ def main():
     ap.add_argument("--bsr-sweep", action="store_true",
                     help="with --workload bsr: one solve per (scheme, truncation threshold) of "
                          "the sweep, one JSON line each")
+    ap.add_argument("--bsr-ec", action="store_true",
+                    help="block-sparse workload: also run fixed-threshold and error-controlled "
+                         "truncation at several budgets, with ||[F, D]||_F estimates")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for hardware-counter runs: a plain 512 MiB device copy (counter "
                          "calibration), then three FP64 products of the workload's X_0")

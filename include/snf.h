@@ -89,6 +89,8 @@ typedef enum {
 /* Flags (snf_params.flags). */
 #define SNF_FLAG_TIME_PRODUCTS 1  /* bracket every product kernel with HIP events and report
                                      their summed duration in snf_result.product_ms         */
+#define SNF_FLAG_TRUNC_ERROR_CONTROL 2  /* snf_purify_bsr: trunc_tau is an error budget for
+                                     ||D - D_exact||_F, not a per-block threshold (below)   */
 
 /*
  * Inputs of a purification (Algorithm 1 and the P_{m,m} schemes need lambda_min, lambda_max,
@@ -214,6 +216,16 @@ typedef struct {
  *           block present; only blocks (I,J) with I <= J (and the upper triangle of diagonal
  *           blocks) are read, the rest is taken as their transpose.
  *   trunc_tau: block truncation threshold (Frobenius norm), >= 0 (0 = no truncation).
+ *           With SNF_FLAG_TRUNC_ERROR_CONTROL in params->flags, trunc_tau > 0 is instead a
+ *           budget eps for ||D - D_exact||_F (forward-error control, which the sparsity
+ *           paragraph expects the schemes to combine with): the step producing X_i drops
+ *           off-diagonal block pairs of total Frobenius norm at most eps g_i / (sqrt 2 N), with
+ *           g_i = beta-bar_i - beta_i the X-space gap of X_i (a perturbation E of X_i turns its
+ *           occupied subspace by about ||E|| / g_i) and N the iterations the scalar recurrence
+ *           predicts until max(beta, 1 - beta-bar) <= eps.  The blocks dropped are those in the
+ *           lowest bins of a half-octave grid of squared block norms, floor(2 log2 ||B||_F^2)
+ *           clamped to [-160, 40], while the bins' charge, 2 count_j 2^((j+1)/2) (each bin at
+ *           its upper edge, mirror blocks included), stays within the step's budget squared.
  *   D_out:  receives a library-allocated snf_bsr (host struct, device arrays) holding D;
  *           release it with snf_bsr_free.  NULL on error.
  *   Stops with SNF_OK at ||X^2 - X||_F <= tol, or SNF_OK_FLOOR once the a-priori error

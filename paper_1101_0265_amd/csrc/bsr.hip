@@ -411,6 +411,66 @@ __global__ __launch_bounds__(64) void bsr_truncate_kernel(const int32_t* __restr
   partials[(slot0 + I) * 4 + 3] = 0.0;
 }
 
+// ---- 5a. error-controlled truncation: histogram of block norms ------------------------
+// Half-octave bins of the squared block norm s: bin(s) = floor(2 log2 s), exact from the
+// binary exponent and the mantissa against fl(sqrt 2) (no double lies between sqrt 2 and
+// fl(sqrt 2), so the comparison is exact), clamped to [kBinMin, kBinMax]; s = 0 -> kBinMin.
+constexpr int kBinMin = -160, kBinMax = 40, kNumBins = kBinMax - kBinMin + 1;
+constexpr double kSqrt2 = 1.4142135623730951;
+
+__device__ __forceinline__ int half_octave_bin(double s) {
+  if (!(s > 0.0)) return kBinMin;
+  int e = 0;
+  const double m = frexp(s, &e);                 // s = m 2^e, m in [0.5, 1)
+  const int j = 2 * (e - 1) + (2.0 * m >= kSqrt2 ? 1 : 0);
+  return j < kBinMin ? kBinMin : (j > kBinMax ? kBinMax : j);
+}
+
+// Counts of the candidate blocks (I, J), J > I, per bin (each stands for a mirror pair).
+// Integer atomics: the counts do not depend on the order of arrival.
+__global__ __launch_bounds__(64) void bsr_norm_hist_kernel(const int32_t* __restrict__ row_ptrP,
+                                                           const int32_t* __restrict__ colP,
+                                                           const double* __restrict__ normP,
+                                                           uint32_t* __restrict__ counts) {
+  __shared__ uint32_t h[kNumBins];
+  for (int b = threadIdx.x; b < kNumBins; b += 64) h[b] = 0u;
+  __syncthreads();
+  const int I = blockIdx.x;
+  for (int p = row_ptrP[I] + (int)threadIdx.x; p < row_ptrP[I + 1]; p += 64)
+    if (colP[p] > I) atomicAdd(&h[half_octave_bin(normP[p]) - kBinMin], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kNumBins; b += 64)
+    if (h[b]) atomicAdd(&counts[b], h[b]);
+}
+
+// Squared-norm threshold of the error-controlled rule from the bin counts: the lowest bins
+// are dropped while their charge, 2 count_j 2^((j+1)/2) summed (each bin at its upper edge,
+// mirror blocks included), stays within eps_i^2.  Returns tau2 such that a block is kept iff
+// its squared norm >= tau2 (0: keep all; +inf: drop every off-diagonal block).
+static double error_control_tau2(const uint32_t* counts, double eps_i) {
+  const double budget = eps_i * eps_i;
+  double charge = 0.0;
+  int k = kBinMin;
+  for (int j = kBinMin; j <= kBinMax; ++j) {
+    const double wj = 2.0 * (double)counts[j - kBinMin];
+    if (wj == 0.0) {
+      k = j + 1;
+      continue;
+    }
+    const double c = wj * pow(2.0, (j + 1) / 2.0);
+    if (charge + c > budget) {
+      k = j;
+      break;
+    }
+    charge += c;
+    k = j + 1;
+  }
+  if (k <= kBinMin) return 0.0;
+  if (k > kBinMax) return INFINITY;
+  // bin(s) >= k  <=>  s >= 2^(k/2) (k even), s >= fl(sqrt 2) 2^((k-1)/2) (k odd)
+  return (k % 2 == 0) ? ldexp(1.0, k / 2) : ldexp(kSqrt2, (k - 1) / 2);
+}
+
 // ---- 6. compaction ----------------------------------------------------------------------
 __global__ __launch_bounds__(256) void bsr_compact_kernel(const int32_t* __restrict__ row_ptrP,
                                                           const int32_t* __restrict__ colP,
@@ -553,6 +613,9 @@ struct BsrWorkspace {
   SnfState* state_host = nullptr;
   int32_t* pinned = nullptr;    // scratch for small read-backs
   size_t pinned_cap = 0;
+  DevArr<uint32_t> hist;        // error-controlled truncation: bin counts (device)
+  double last_tau2 = 0.0;       // squared-norm threshold the last step used
+  uint32_t* hist_host = nullptr;   // pinned copy
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::mutex mu;
 };
@@ -648,8 +711,10 @@ static int scan_counts(BsrWorkspace* w, const int32_t* cnt_dev, int nb, DevArr<i
 // One step on w->X[cur] (lookup tables built): candidate pattern, numeric product (reads
 // the coefficients in the state), truncation, compaction into w->X[1 - cur].  Partial sums
 // land in slots [0, tiles) (product) and [tiles, tiles + nb) (kept norms); *slots = total.
+// eps_i >= 0 selects the error-controlled rule (tau2 is then derived from the block-norm
+// histogram of this product); eps_i < 0 keeps the fixed threshold tau2.
 static int bsr_step(BsrWorkspace* w, int cur, int nb, int W, double tau2, int* slots,
-                    hipEvent_t ev_a, hipEvent_t ev_b, hipStream_t s) {
+                    hipEvent_t ev_a, hipEvent_t ev_b, hipStream_t s, double eps_i = -1.0) {
   BsrBuf& X = w->X[cur];
   BsrBuf& N = w->X[1 - cur];
   BsrBuf& P = w->P;
@@ -712,7 +777,19 @@ static int bsr_step(BsrWorkspace* w, int cur, int nb, int W, double tau2, int* s
     hipLaunchKernelGGL(bsr_product_kernel, dim3(ntiles), dim3(256), 0, s, w->state, args);
   if (ev_b) BSR_HIP(hipEventRecord(ev_b, s));
   BSR_HIP(hipGetLastError());
-  // 5. truncation
+  // 5. truncation (threshold from the norm histogram under error control)
+  if (eps_i >= 0.0) {
+    if ((rc = w->hist.reserve(kNumBins))) return rc;
+    BSR_HIP(hipMemsetAsync(w->hist.p, 0, kNumBins * sizeof(uint32_t), s));
+    hipLaunchKernelGGL(bsr_norm_hist_kernel, dim3(nb), dim3(64), 0, s, P.row_ptr.p, P.col.p,
+                       w->normP.p, w->hist.p);
+    BSR_HIP(hipGetLastError());
+    BSR_HIP(hipMemcpyAsync(w->hist_host, w->hist.p, kNumBins * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
+    BSR_HIP(hipStreamSynchronize(s));
+    tau2 = error_control_tau2(w->hist_host, eps_i);
+    w->last_tau2 = tau2;
+  }
   hipLaunchKernelGGL(bsr_truncate_kernel, dim3(nb), dim3(64), 0, s, P.row_ptr.p, P.col.p,
                      w->normP.p, tau2, w->rank.p, w->cnt.p, w->partials.p, ntiles);
   BSR_HIP(hipGetLastError());
@@ -764,6 +841,7 @@ static int ensure_state(BsrWorkspace* w) {
     BSR_HIP(hipMalloc(&w->state, sizeof(SnfState)));
     BSR_HIP(hipHostMalloc(&w->state_host, sizeof(SnfState), hipHostMallocDefault));
     for (int i = 0; i < 4; ++i) BSR_HIP(hipEventCreate(&w->ev[i]));
+    BSR_HIP(hipHostMalloc(&w->hist_host, kNumBins * sizeof(uint32_t), hipHostMallocDefault));
   }
   return SNF_OK;
 }
@@ -819,6 +897,45 @@ void snf_bsr_free(snf_bsr* m) {
   free(m);
 }
 
+namespace snf {
+// Iterations the scalar recurrence of Algorithm 2 (alpha = 0 for the unscaled schemes; the
+// trace scheme is predicted by that recurrence) takes until max(beta, 1 - beta-bar) <= eps.
+static int predicted_iterations(snf_scheme scheme, double beta, double betabar, double eps) {
+#pragma clang fp contract(off)
+  for (int it = 0; it < 200; ++it) {
+    const double bound = beta > 1.0 - betabar ? beta : 1.0 - betabar;
+    if (bound <= eps) return it > 1 ? it : 1;
+    const bool sq = sched::alg2_square(beta, betabar);
+    double a = 0.0;
+    if (scheme == SNF_SNF_VARMU)
+      a = sq ? sched::alg2_square_alpha(beta) : sched::alg2_fold_alpha(betabar);
+    if (sq) {
+      beta = sched::alg2_square_map(beta, a);
+      betabar = sched::alg2_square_map(betabar, a);
+    } else {
+      beta = sched::alg2_fold_map(beta, a);
+      betabar = sched::alg2_fold_map(betabar, a);
+    }
+  }
+  return 200;
+}
+
+// Truncation budget of the pending step: eps g / (sqrt 2 N), g the X-space gap of the iterate
+// the step produces (beta, beta-bar advanced by the step's branch and alpha).
+static double error_control_eps(const SnfState* sh, double eps, int n_pred) {
+#pragma clang fp contract(off)
+  double b = sh->beta, bb = sh->betabar;
+  if (sh->branch == SNF_BRANCH_SQUARE) {
+    b = sched::alg2_square_map(b, sh->alpha);
+    bb = sched::alg2_square_map(bb, sh->alpha);
+  } else {
+    b = sched::alg2_fold_map(b, sh->alpha);
+    bb = sched::alg2_fold_map(bb, sh->alpha);
+  }
+  return eps * (bb - b) / (kSqrt2 * (double)n_pred);
+}
+}  // namespace snf
+
 int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme,
                    double trunc_tau, snf_bsr** D_out, snf_result* out, snf_log_rec* log,
                    int32_t log_cap, void* stream) {
@@ -830,6 +947,7 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
     return rc;
   };
   if (!F || !params || !D_out || !(trunc_tau >= 0.0) || !isfinite(trunc_tau)) return fail(SNF_EINVAL);
+  if ((params->flags & SNF_FLAG_TRUNC_ERROR_CONTROL) && !(trunc_tau > 0.0)) return fail(SNF_EINVAL);
   if (scheme != SNF_SP2_TRACE && scheme != SNF_TC2_BETA && scheme != SNF_SNF_VARMU)
     return fail(SNF_EINVAL);
   const snf_params& p = *params;
@@ -877,7 +995,13 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
   launch_schedule(w->state, w->partials.p, kF0Blocks, 1, s);
   BSR_HIP(hipGetLastError());
 
-  const double tau2 = trunc_tau * trunc_tau;
+  const bool ec = (p.flags & SNF_FLAG_TRUNC_ERROR_CONTROL) != 0;
+  const double tau2 = ec ? 0.0 : trunc_tau * trunc_tau;
+  const int n_pred = ec ? predicted_iterations(scheme, sh->beta, sh->betabar, trunc_tau) : 1;
+  if (ec) {   // the pending step's branch and alpha, for its truncation budget
+    BSR_HIP(hipMemcpyAsync(sh, w->state, sizeof(SnfState), hipMemcpyDeviceToHost, s));
+    BSR_HIP(hipStreamSynchronize(s));
+  }
   const bool timing = (p.flags & SNF_FLAG_TIME_PRODUCTS) != 0;
   double prod_ms = 0.0, flops = 0.0;
   int cur = 0;
@@ -885,8 +1009,9 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
   blocks_of_iterate.push_back(w->X[0].nnzb);
   for (int it = 0; it <= p.max_iter; ++it) {
     int slots = 0;
+    const double eps_i = ec ? error_control_eps(sh, trunc_tau, n_pred) : -1.0;
     rc = bsr_step(w, cur, nb, W, tau2, &slots, timing ? w->ev[2] : nullptr,
-                  timing ? w->ev[3] : nullptr, s);
+                  timing ? w->ev[3] : nullptr, s, eps_i);
     if (rc) return fail(rc);
     launch_schedule(w->state, w->partials.p, slots, 0, s);
     BSR_HIP(hipGetLastError());

@@ -27,6 +27,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_ref64": 2, "bf16_ref64": 3}
 BRANCH_LETTERS = {0: "S", 1: "F", 2: "M", 3: "3", 4: "5"}
 LOG_MAX = 256
 FLAG_TIME_PRODUCTS = 1
+FLAG_TRUNC_ERROR_CONTROL = 2
 
 
 class Params(ctypes.Structure):

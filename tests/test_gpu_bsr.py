@@ -17,7 +17,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle import dense  # noqa: E402
+from oracle import dense, exact  # noqa: E402
 from paper_1101_0265_amd import hamiltonians as H  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -162,3 +162,54 @@ def test_bsr_full_lattice_65536(snf):
     print(f"\nBSR 32^3: {r['status']} products {r['products']} e={r['idem_err']:.2e} "
           f"tr err {r['trace_err']:.2e} blocks {r['nnzb']} ({r['nnzb'] / (n // 32):.0f} per row) "
           f"device {r['device_ms']:.0f} ms")
+
+
+@pytest.mark.parametrize("scheme", ["tc2", "snf_varmu", "sp2"])
+@pytest.mark.parametrize("eps", [1e-2, 1e-3])
+def test_error_controlled_truncation(snf, scheme, eps):
+    """Error-controlled truncation (budget eps for ||D - D_exact||_F) on the 16x8x8-site
+    lattice (n = 2048).  Bars: decisions equal the oracle's; ||D_gpu - D_exact||_F within eps
+    plus the FP32 floor of the same solve without truncation; stored blocks of D within 5% of
+    the oracle's (FP32 block norms near a bin edge may fall on the other side)."""
+    m, h = H.lattice_bsr((16, 8, 8), seed=3)
+    n = m.n
+    m64, _ = H.lattice_bsr((16, 8, 8), seed=3, dtype=np.float64)
+    Fd = m64.to_dense()
+    D_ref = exact.projector(F=Fd, n_occ=h.n_occ)
+    kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
+              lumo=h.lumo, tol=1e-9, max_iter=60)
+    (rp, ci, va), r = snf.purify_bsr(*_dev_bsr(m), n, scheme, trunc_tau=eps,
+                                      flags=snf.FLAG_TRUNC_ERROR_CONTROL, **kw)
+    assert r["status"] in ("ok", "ok_floor"), r["status"]
+    (rp0, ci0, va0), r0 = snf.purify_bsr(*_dev_bsr(m), n, scheme, trunc_tau=0.0, **kw)
+    floor = float(np.linalg.norm(_to_dense(rp0, ci0, va0, n) - D_ref))
+    Dg = _to_dense(rp, ci, va, n)
+    err = float(np.linalg.norm(Dg - D_ref))
+    N = dense.predicted_iterations(scheme, eps=eps, lambda_min=h.lambda_min,
+                                   lambda_max=h.lambda_max, homo=h.homo, lumo=h.lumo)
+    mk = dense.ErrorControlledTruncation(32, eps, N)
+    okw = dict(kw)
+    okw.update(tol=0.0, max_iter=r["iterations"])
+    o = dense.purify(Fd, scheme, mask=mk, **okw)
+    if scheme != "sp2":
+        assert r["branches"] == o["branches"]
+    nb = n // 32
+    blocks_o = int((np.abs(o["D"]).reshape(nb, 32, nb, 32).sum(axis=(1, 3)) > 0).sum())
+    print(f"\nEC {scheme} eps={eps:g}: {r['status']} products {r['products']} "
+          f"|D-D_exact|={err:.2e} (no-truncation floor {floor:.2e}, oracle "
+          f"{np.linalg.norm(o['D'] - D_ref):.2e}) blocks {r['nnzb']} / oracle {blocks_o} "
+          f"/ untruncated {r0['nnzb']}")
+    assert err <= eps + floor
+    assert abs(r["nnzb"] - blocks_o) <= 0.05 * blocks_o
+    # blocks stored over the iterates (the log's spare field): fewer than without truncation
+    assert sum(x["phase"] for x in r["log"]) < sum(x["phase"] for x in r0["log"])
+    assert np.array_equal(Dg, Dg.T)
+
+
+def test_error_control_rejects_zero_budget(snf):
+    m, h = H.lattice_bsr((8, 8, 4), seed=1)
+    kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
+              lumo=h.lumo, tol=1e-6, max_iter=40)
+    with pytest.raises(RuntimeError):
+        snf.purify_bsr(*_dev_bsr(m), m.n, "snf_varmu", trunc_tau=0.0,
+                       flags=snf.FLAG_TRUNC_ERROR_CONTROL, **kw)
