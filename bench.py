@@ -182,6 +182,67 @@ def run_precision(args):
     return line
 
 
+def run_bounds(args):
+    """n = 4096 lattice: bounds estimated on the device (Lanczos, 40 steps) instead of given.
+    The trace scheme with estimated extremal bounds, gap bounds from its D, then scale-and-fold
+    with them; against the solve with exact bounds."""
+    import numpy as np
+    import torch
+    from paper_1101_0265_amd import hamiltonians as H
+    from paper_1101_0265_amd import snf
+    h = H.lattice_hamiltonian((16, 16, 8), seed=2)
+    F = torch.tensor(h.F, device="cuda:0")
+    D1, D2 = torch.empty_like(F), torch.empty_like(F)
+    steps = 40
+    exact_kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ,
+                    homo=h.homo, lumo=h.lumo, tol=1e-8, max_iter=100)
+
+    def pipeline():
+        lo, hi, glo, ghi = snf.spectral_bounds(F, steps)
+        _, r1 = snf.purify_dense(F, "sp2", out=D1, want_log=False, lambda_min=lo,
+                                 lambda_max=hi, n_occ=h.n_occ, tol=1e-8, max_iter=100)
+        homo, lumo = snf.gap_bounds(F, D1, lo, hi, steps)
+        _, r2 = snf.purify_dense(F, "snf_varmu", out=D2, want_log=False, lambda_min=lo,
+                                 lambda_max=hi, homo=homo, lumo=lumo, n_occ=h.n_occ,
+                                 tol=1e-8, max_iter=100)
+        return (lo, hi, glo, ghi, homo, lumo), r1, r2
+
+    for _ in range(max(1, args.warmup)):
+        pipeline()
+    torch.cuda.synchronize()
+    t = {}
+    t0 = time.perf_counter()
+    snf.spectral_bounds(F, steps)
+    torch.cuda.synchronize()
+    t["spectral_bounds_ms"] = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    snf.gap_bounds(F, D1, h.lambda_min, h.lambda_max, steps)
+    torch.cuda.synchronize()
+    t["gap_bounds_ms"] = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    b, r1, r2 = pipeline()
+    torch.cuda.synchronize()
+    t["pipeline_ms"] = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    _, rx = snf.purify_dense(F, "snf_varmu", out=D2, want_log=False, **exact_kw)
+    torch.cuda.synchronize()
+    t["snf_exact_bounds_ms"] = (time.perf_counter() - t0) * 1e3
+    w = np.linalg.eigvalsh(h.F)
+    line = _base_line("time ms: bounds estimated on the device, then SP2 and SnF (n=4096)",
+                      round(t["pipeline_ms"], 2), "ms", args, False, "f64",
+                      {"workload": "dense FP64 two-orbital lattice 16x16x8 sites, n=4096; "
+                                   f"Lanczos {steps} steps for extremal and gap bounds"})
+    line["ms_per_step"] = line["value"]
+    line["timings_ms"] = {k: round(v, 2) for k, v in t.items()}
+    line["bounds"] = dict(lambda_min=b[0], lambda_max=b[1], gershgorin=[b[2], b[3]],
+                          homo=b[4], lumo=b[5], exact=[float(w[0]), float(w[-1]), h.homo,
+                                                        h.lumo])
+    line["products"] = dict(sp2_estimated=r1["products"], snf_estimated=r2["products"],
+                            snf_exact=rx["products"])
+    line["cpu_baseline"] = None
+    return line
+
+
 def _bsr_mm(rp, ci, va, Z):
     """Y = M Z for a BSR matrix M (32x32 blocks, device tensors) and a dense (n, p) float64
     block of vectors, by batched block products (measurement helper)."""
@@ -400,7 +461,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="dense",
-                    choices=["dense", "small", "bsr", "serve", "precision"],
+                    choices=["dense", "small", "bsr", "serve", "precision", "bounds"],
                     help="dense: n=4096 lattice (default line); small: n=256 gap-0.05 latency "
                          "of all five schemes; bsr: block-sparse 32^3-site lattice n=65536; "
                          "serve: 512-request continuous-batching trace")
@@ -431,7 +492,7 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload != "dense":
         line = {"small": run_small, "bsr": run_bsr, "serve": run_serve,
-                "precision": run_precision}[args.workload](args)
+                "precision": run_precision, "bounds": run_bounds}[args.workload](args)
         print(json.dumps(line), flush=True)
         return
     h = H.lattice_hamiltonian(LATTICE, seed=2)

@@ -302,6 +302,41 @@ int snf_serve_timing(snf_server* server, uint64_t ticket, double* ms);
 /* Finish every queued and running request, stop the scheduler, release the arena. */
 int snf_serve_destroy(snf_server* server);
 
+/* ---- bounds of the inputs --------------------------------------------------------------
+ * Both algorithms take bounds as inputs: the extremal eigenvalues of F or bounds of them, and
+ * for the scaled varying-mu scheme a lower bound of the highest occupied (homo) and an upper
+ * bound of the lowest unoccupied (lumo) eigenvalue (the bounds paragraph after Fig. 3, which
+ * points to methods for interior eigenvalues).  Both estimators run `steps` Lanczos steps with
+ * full reorthogonalisation (classical Gram-Schmidt applied twice) on the device, from
+ * start_dev (n FP64 values, device; NULL = a fixed pseudo-random vector, u_i in [-1, 1) from
+ * SplitMix64 of i), and diagonalise the tridiagonal on the host.  The tridiagonal is cut at
+ * the first beta_j <= 1e-12 max |alpha_0..j| (an invariant subspace).  Matrices are dense
+ * row-major FP64 with row stride ld, upper triangle read.  1 <= steps <= 512.  The
+ * workspace (steps + 1 vectors per Lanczos chain) is kept per device.  Synchronous on
+ * `stream`.
+ */
+
+/* snf_spectral_bounds -- out[0] = theta_min - r_min - pad, out[1] = theta_max + r_max + pad,
+ * theta the extreme Ritz values, r their residual norms beta_k |s_k| (an eigenvalue lies
+ * within r of theta), pad = 1e-13 max |theta| for rounding: outer bounds once the extreme Ritz
+ * pairs belong to the extreme eigenvalues, which a small r shows.  out[2], out[3] = the
+ * Gershgorin enclosure (rigorous, looser).  out: host array of 4 doubles. */
+int snf_spectral_bounds(const double* F_dev, int64_t n, int64_t ld, int32_t steps,
+                        const double* start_dev, double* out, void* stream);
+
+/* snf_gap_bounds -- from D_dev, a projector onto the occupied subspace of F (the result of a
+ * trace-scheme purification needs no gap bounds): the largest eigenvalue of
+ * D (F - lambda_min I) D is HOMO - lambda_min and that of (I - D)(lambda_max I - F)(I - D) is
+ * lambda_max - LUMO; Ritz values never exceed the largest eigenvalue, so
+ * out[0] = lambda_min + theta_1 - pad <= HOMO and out[1] = lambda_max - theta_2 + pad >= LUMO
+ * at any number of steps (pad = 1e-13 (lambda_max - lambda_min)); loose after few steps,
+ * never inside the gap, up to a shift of second order in the subspace error of D.
+ * lambda_min < lambda_max: bounds of the spectrum (for example from snf_spectral_bounds).
+ * out: host array of 2 doubles. */
+int snf_gap_bounds(const double* F_dev, const double* D_dev, int64_t n, int64_t ld,
+                   double lambda_min, double lambda_max, int32_t steps,
+                   const double* start_dev, double* out, void* stream);
+
 /* Bytes of device workspace snf_purify_dense needs for order n (allocated on demand); the
    P_{m,m} schemes take one more n_pad x n_pad FP64 buffer (n_pad = n rounded up to 128). */
 size_t snf_workspace_bytes(int64_t n, snf_precision precision);

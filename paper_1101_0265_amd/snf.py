@@ -118,6 +118,10 @@ def lib() -> ctypes.CDLL:
     L.snf_workspace_bytes.restype = ctypes.c_size_t
     L.snf_release_workspace.argtypes = []
     L.snf_release_workspace.restype = ctypes.c_int
+    L.snf_spectral_bounds.argtypes = [vp, i64, i64, i32, vp, ctypes.POINTER(dbl), vp]
+    L.snf_spectral_bounds.restype = ctypes.c_int
+    L.snf_gap_bounds.argtypes = [vp, vp, i64, i64, dbl, dbl, i32, vp, ctypes.POINTER(dbl), vp]
+    L.snf_gap_bounds.restype = ctypes.c_int
     L.snf_strerror.argtypes = [ctypes.c_int]
     L.snf_strerror.restype = ctypes.c_char_p
     L.snf_version.argtypes = []
@@ -258,6 +262,49 @@ def _take_bsr(ptr, stream) -> tuple:
     if rc != OK:
         raise RuntimeError(f"snf_bsr_copy_out: {strerror(rc)}")
     return rp, ci[:m.nnzb], va[:m.nnzb]
+
+
+def spectral_bounds(F, steps: int = 40, start=None, stream=None) -> tuple:
+    """(lambda_min, lambda_max, gershgorin_min, gershgorin_max) of the symmetric float64 CUDA
+    tensor F (see snf_spectral_bounds)."""
+    _check_dense(F, "F")
+    n = F.shape[0]
+    if start is not None:
+        _check_vec(start, n)
+    out = (ctypes.c_double * 4)()
+    rc = lib().snf_spectral_bounds(F.data_ptr(), n, F.stride(0), int(steps),
+                                   start.data_ptr() if start is not None else None, out,
+                                   _stream_handle(stream))
+    if rc != OK:
+        raise RuntimeError(f"snf_spectral_bounds: {strerror(rc)} ({rc})")
+    return tuple(out)
+
+
+def gap_bounds(F, D, lambda_min: float, lambda_max: float, steps: int = 40, start=None,
+               stream=None) -> tuple:
+    """(homo, lumo) bounds of the gap edges from a projector D (see snf_gap_bounds)."""
+    _check_dense(F, "F")
+    _check_dense(D, "D")
+    n = F.shape[0]
+    if D.shape != F.shape or D.stride(0) != F.stride(0):
+        raise ValueError("D must match F in shape and row stride")
+    if start is not None:
+        _check_vec(start, n)
+    out = (ctypes.c_double * 2)()
+    rc = lib().snf_gap_bounds(F.data_ptr(), D.data_ptr(), n, F.stride(0), float(lambda_min),
+                              float(lambda_max), int(steps),
+                              start.data_ptr() if start is not None else None, out,
+                              _stream_handle(stream))
+    if rc != OK:
+        raise RuntimeError(f"snf_gap_bounds: {strerror(rc)} ({rc})")
+    return tuple(out)
+
+
+def _check_vec(v, n):
+    import torch
+    if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64 and
+            v.dim() == 1 and v.numel() == n and v.is_contiguous()):
+        raise ValueError(f"start must be a contiguous float64 CUDA vector of length {n}")
 
 
 def purify_bsr(row_ptr, col_idx, val, n: int, scheme: str = "snf_varmu", *, trunc_tau=1e-6,
