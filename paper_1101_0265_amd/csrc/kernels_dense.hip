@@ -366,8 +366,8 @@ template <typename T> struct Layout;
 template <> struct Layout<double> {   // 8 waves of 64x32: 64 accumulator registers per lane,
   static constexpr int NT = 512, WC = 4;   // so 4 waves fit on each SIMD
 };
-template <> struct Layout<float> {    // 4 waves of 64x64
-  static constexpr int NT = 256, WC = 2;
+template <> struct Layout<float> {    // 8 waves of 32x64: 32 accumulator registers per lane,
+  static constexpr int NT = 512, WC = 2;   // 4 waves per SIMD
 };
 
 template <typename T, int PREC>
@@ -553,7 +553,7 @@ __global__ __launch_bounds__(512, 2) void product_f64_kernel(const SnfState* __r
   product_body<double, kPrecF64>(st, bufs, g, work_item(g, (int)(g.np / Mfma<double>::kBK)));
 }
 
-__global__ __launch_bounds__(256, 2) void product_f32_kernel(const SnfState* __restrict__ st,
+__global__ __launch_bounds__(512, 2) void product_f32_kernel(const SnfState* __restrict__ st,
                                                              const Buffers* __restrict__ bufs,
                                                              ProductGrid g) {
   if (st->stop || st->prec != kPrecF32) return;

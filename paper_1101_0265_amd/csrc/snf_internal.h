@@ -11,7 +11,7 @@ namespace snf {
 // Output tile of one workgroup of the dense product kernels, and the padding unit of
 // every internal n x n buffer (so the product main loop needs no bounds checks).
 constexpr int kTile = 128;
-constexpr int kThreads = 256;        // 4 waves of 64, arranged 2 x 2 over the tile
+constexpr int kThreads = 256;        // threads of the bf16 product and split fix-up kernels
 constexpr int kF0Blocks = 1024;      // fixed grid of the f0 / conversion kernels
 constexpr int kReduceThreads = 256;
 
