@@ -170,7 +170,7 @@ struct BsrProductArgs {
 };
 
 constexpr int kBsrLdsW = 128 + 16;   // LDS row stride (floats), as the dense f32 kernel
-constexpr int kChunkWords = 64;     // bitmap words per k-stage list chunk (2048 columns)
+constexpr int kChunkWords = 8;      // bitmap words per k-stage list chunk (256 columns)
 
 __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __restrict__ st,
                                                              BsrProductArgs g) {
@@ -178,6 +178,10 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
   __shared__ __attribute__((aligned(16))) float sA[2][kB][kBsrLdsW];
   __shared__ __attribute__((aligned(16))) float sB[2][kB][kBsrLdsW];
   __shared__ uint16_t klist[kChunkWords * 32];
+  // per k-stage of the chunk: bitmap words of block row K at the A and B panel columns and
+  // the value index of the first block of each panel (block row K's offset included)
+  __shared__ uint32_t kwa[kChunkWords * 32], kwb[kChunkWords * 32];
+  __shared__ int32_t kpa[kChunkWords * 32], kpb[kChunkWords * 32];
   __shared__ uint32_t sw[kChunkWords];
   __shared__ int offs[kChunkWords + 1];
   __shared__ uint32_t spres[2];
@@ -201,14 +205,11 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
   const int lk = tid >> 3, lc = (tid & 7) * 4;
   u32x4 ra[kSup], rb[kSup];
   uint32_t pres = 0;   // presence of the stage's blocks: bits 0-3 A panel, 4-7 B panel
-  auto gload = [&](int K) {
+  auto gload = [&](int s) {
     // the 4 panel columns of each side share one bitmap word of block row K
-    const int rp = g.X.row_ptr[K];
-    const uint32_t wa = g.X.bm[(size_t)K * W + (ci0 >> 5)];
-    const uint32_t wb = g.X.bm[(size_t)K * W + (cj0 >> 5)];
+    const uint32_t wa = kwa[s], wb = kwb[s];
     pres = ((wa >> (ci0 & 31)) & 0xFu) | (((wb >> (cj0 & 31)) & 0xFu) << 4);
-    const int pa0 = rp + g.X.pre[(size_t)K * W + (ci0 >> 5)];
-    const int pb0 = rp + g.X.pre[(size_t)K * W + (cj0 >> 5)];
+    const int pa0 = kpa[s], pb0 = kpb[s];
 #pragma unroll
     for (int a = 0; a < kSup; ++a) {
       const uint32_t bia = 1u << ((ci0 + a) & 31), bib = 1u << ((cj0 + a) & 31);
@@ -266,14 +267,23 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
     }
     __syncthreads();
     const int nk = offs[kChunkWords];
+    for (int t = tid; t < nk; t += 256) {
+      const int K = klist[t];
+      const int rp = g.X.row_ptr[K];
+      kwa[t] = g.X.bm[(size_t)K * W + (ci0 >> 5)];
+      kwb[t] = g.X.bm[(size_t)K * W + (cj0 >> 5)];
+      kpa[t] = rp + g.X.pre[(size_t)K * W + (ci0 >> 5)];
+      kpb[t] = rp + g.X.pre[(size_t)K * W + (cj0 >> 5)];
+    }
+    __syncthreads();
     if (nk == 0) continue;
-    gload(klist[0]);
+    gload(0);
     lstore(0);
     __syncthreads();
     for (int s = 0; s < nk; ++s) {
       const int buf = s & 1;
       const bool more = s + 1 < nk;
-      if (more) gload(klist[s + 1]);
+      if (more) gload(s + 1);
       // this wave's two A blocks (rows 2 wr, 2 wr + 1) and two B blocks; absent blocks are
       // zero, so their MFMAs are skipped (the test is uniform across the wave)
       const uint32_t pm = spres[buf];
