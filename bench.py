@@ -179,6 +179,23 @@ def run_precision(args):
     line["runs"] = out
     line["speedup_vs_sp2"] = round(out["sp2/fp64/gsw0.0"]["ms"] / base["ms"], 3)
     line["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        # the oracle on the same F for its first two iterations, scaled per iteration to the
+        # solve's iteration count (its per-iteration cost is the same at every iteration)
+        from oracle import dense
+        Fh = F.cpu().numpy()
+        okw = {k: v for k, v in kw.items() if k in ("lambda_min", "lambda_max", "n_occ", "homo",
+                                                     "lumo", "mu", "xi")}
+        t0 = time.perf_counter()
+        dense.purify(Fh, "snf_varmu", tol=1e-300, max_iter=2, **okw)
+        dt = time.perf_counter() - t0
+        its = base["products"] - 1
+        line["cpu_baseline"] = dict(
+            value=round(dt * 1e3 * (2 * its + 1) / 5, 1), unit="ms", cores=int(_blas_threads()),
+            kind="oracle",
+            sample=f"the first 2 iterations of the FP64 oracle on the same n=8192 F (5 dense "
+                   f"products: 3 checks, 2 steps; {dt:.1f} s), scaled to the solve's "
+                   f"{2 * its + 1} ({its} iterations of check + step, one certifying check)")
     return line
 
 
@@ -240,6 +257,21 @@ def run_bounds(args):
     line["products"] = dict(sp2_estimated=r1["products"], snf_estimated=r2["products"],
                             snf_exact=rx["products"])
     line["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        from oracle import bounds as obounds, dense
+        v0 = np.random.default_rng(0).standard_normal(h.n)
+        t0 = time.perf_counter()
+        lo, hi = obounds.spectral_bounds(h.F, v0, steps)
+        o1 = dense.purify(h.F, "sp2", lambda_min=lo, lambda_max=hi, n_occ=h.n_occ, tol=1e-8,
+                          max_iter=100)
+        homo, lumo = obounds.gap_bounds(h.F, o1["D"], lo, hi, v0, steps)
+        dense.purify(h.F, "snf_varmu", lambda_min=lo, lambda_max=hi, homo=homo, lumo=lumo,
+                     n_occ=h.n_occ, tol=1e-8, max_iter=100)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = dict(value=round(dt * 1e3, 1), unit="ms",
+                                    cores=int(_blas_threads()), kind="oracle",
+                                    sample="the whole pipeline once on the same input "
+                                           "(numpy Lanczos, FP64 oracle solves)")
     return line
 
 
@@ -361,6 +393,25 @@ def run_bsr(args):
                             note="achieved = 2*32^3 flops per stored-block triple (I,K,J), "
                                  "I<=J, over the summed numeric-kernel time")
     line["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        # the dense block-masked FP64 oracle cannot hold n = 65536 (34 GB per matrix, hours
+        # per product): timed on the same lattice recipe at 16x16x8 sites (n = 4096) for the
+        # same number of iterations, scaled by the n^3 of its dense products
+        from oracle import dense
+        ms, hs = H.lattice_bsr((16, 16, 8), seed=3, dtype=np.float64)
+        Fs = ms.to_dense()
+        t0 = time.perf_counter()
+        dense.purify(Fs, "snf_varmu", lambda_min=hs.lambda_min, lambda_max=hs.lambda_max,
+                     n_occ=hs.n_occ, homo=hs.homo, lumo=hs.lumo, tol=0.0,
+                     max_iter=s["products"] - 1, mask=dense.block_truncation_mask(32, 1e-6))
+        dt = time.perf_counter() - t0
+        scale = (m.n / ms.n) ** 3
+        line["cpu_baseline"] = dict(
+            value=round(dt * 1e3 * scale, 0), unit="ms", cores=int(_blas_threads()),
+            kind="oracle",
+            sample=f"dense block-masked FP64 oracle, same lattice recipe at 16x16x8 sites "
+                   f"(n={ms.n}), {s['products'] - 1} iterations: {dt:.1f} s, scaled by "
+                   f"(65536/{ms.n})^3 = {scale:.0f}")
     return line
 
 
