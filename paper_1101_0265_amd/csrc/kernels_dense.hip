@@ -1051,17 +1051,27 @@ __global__ void grouped_stop_kernel(const SlotDesc* __restrict__ slots, const in
 
 void launch_grouped_step(int prec_mask, const SlotDesc* slots, const int* active,
                          const int* offs, int nactive, int total_tiles, int32_t* stop_out,
-                         hipStream_t s) {
+                         hipStream_t s, hipStream_t s2, hipEvent_t fork, hipEvent_t join) {
   if (nactive <= 0) return;
+  const bool lowp = (prec_mask & ((1 << kPrecF32) | (1 << kPrecBF16))) != 0;
+  // the low-precision launch goes to s2 after everything on s so far, and s waits for it
+  // before the schedule: the two product grids (different requests) share the GPU
+  const bool split = lowp && s2 && fork && join &&
+                     hipEventRecord(fork, s) == hipSuccess &&
+                     hipStreamWaitEvent(s2, fork, 0) == hipSuccess;
+  hipStream_t sl = split ? s2 : s;
+  if (prec_mask & (1 << kPrecF32))
+    hipLaunchKernelGGL((grouped_product_kernel<float, kPrecF32>), dim3(total_tiles),
+                       dim3(Layout<float>::NT), 0, sl, slots, active, offs, nactive);
+  if (prec_mask & (1 << kPrecBF16))
+    hipLaunchKernelGGL(grouped_product_bf16_kernel, dim3(total_tiles), dim3(kThreads), 0, sl,
+                       slots, active, offs, nactive);
   if (prec_mask & (1 << kPrecF64))
     hipLaunchKernelGGL((grouped_product_kernel<double, kPrecF64>), dim3(total_tiles),
                        dim3(Layout<double>::NT), 0, s, slots, active, offs, nactive);
-  if (prec_mask & (1 << kPrecF32))
-    hipLaunchKernelGGL((grouped_product_kernel<float, kPrecF32>), dim3(total_tiles),
-                       dim3(Layout<float>::NT), 0, s, slots, active, offs, nactive);
-  if (prec_mask & (1 << kPrecBF16))
-    hipLaunchKernelGGL(grouped_product_bf16_kernel, dim3(total_tiles), dim3(kThreads), 0, s,
-                       slots, active, offs, nactive);
+  if (split && (hipEventRecord(join, s2) != hipSuccess ||
+                hipStreamWaitEvent(s, join, 0) != hipSuccess))
+    (void)hipStreamSynchronize(s2);    // the schedule must not start before that product
   hipLaunchKernelGGL(grouped_schedule_kernel, dim3(nactive), dim3(kReduceThreads), 0, s, slots,
                      active);
   hipLaunchKernelGGL(grouped_stop_kernel, dim3((nactive + 255) / 256), dim3(256), 0, s, slots,

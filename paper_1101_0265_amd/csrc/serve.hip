@@ -16,6 +16,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -136,6 +137,10 @@ using namespace snf;
 struct snf_server {
   int device = 0;
   hipStream_t stream = nullptr;
+  // second stream of a step: the FP32 product launch runs beside the FP64 one (different
+  // requests), joined by events before the schedule
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t budget = 0;
   int max_slots = 0;
   char* arena_base = nullptr;     // device arena (the HBM budget)
@@ -379,6 +384,12 @@ static void scheduler(snf_server* sv) {
         if (p == SNF_P_FP32 || p == SNF_P_FP32_REF64) prec_mask |= 1 << kPrecF32;
         if (p == SNF_P_BF16_REF64) prec_mask |= 1 << kPrecBF16;
       }
+    // largest orders first: their tiles run the longest k-loops, so dispatching them first
+    // lets the short tiles of small requests fill the end of the step (dispatch order only;
+    // every request keeps its own tiles and reduction order)
+    std::stable_sort(active.begin(), active.end(), [&](int x, int y) {
+      return sv->desc_stage[x].np > sv->desc_stage[y].np;
+    });
     const int na = (int)active.size();
     if (rc == SNF_OK && na > 0) {
       int* idx = sv->index_stage;
@@ -397,7 +408,7 @@ static void scheduler(snf_server* sv) {
         rc = SNF_EDEVICE;
       if (rc == SNF_OK) {
         launch_grouped_step(prec_mask, sv->slots, sv->active_dev, sv->offs_dev, na, total,
-                            sv->stop_dev, s);
+                            sv->stop_dev, s, sv->stream2, sv->ev_fork, sv->ev_join);
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(sv->stop_stage, sv->stop_dev, na * sizeof(int32_t),
                            hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -483,7 +494,10 @@ int snf_serve_create(size_t hbm_budget_bytes, int32_t max_slots, snf_server** ou
   if (pin > ((size_t)2 << 30)) pin = (size_t)2 << 30;
   sv->pin_size = pin;
   bool ok = hipGetDevice(&sv->device) == hipSuccess &&
-            hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) == hipSuccess;
+            hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&sv->stream2, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&sv->ev_fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&sv->ev_join, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipMalloc(&sv->arena_base, hbm_budget_bytes) == hipSuccess;
   ok = ok && hipHostMalloc(&sv->pin_base, pin, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipMalloc(&sv->states, max_slots * sizeof(SnfState)) == hipSuccess &&
@@ -624,6 +638,10 @@ int snf_serve_destroy(snf_server* sv) {
   if (sv->desc_stage) (void)hipHostFree(sv->desc_stage);
   if (sv->index_stage) (void)hipHostFree(sv->index_stage);
   if (sv->stop_stage) (void)hipHostFree(sv->stop_stage);
+  if (sv->stream2) (void)hipStreamSynchronize(sv->stream2);
+  if (sv->ev_fork) (void)hipEventDestroy(sv->ev_fork);
+  if (sv->ev_join) (void)hipEventDestroy(sv->ev_join);
+  if (sv->stream2) (void)hipStreamDestroy(sv->stream2);
   if (sv->stream) (void)hipStreamDestroy(sv->stream);
   const int rc = sv->sticky_error;
   delete sv;
