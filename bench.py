@@ -436,7 +436,7 @@ def run_serve(args):
 
     budget = 24 << 30
     flops = 0.0
-    with snf.Server(budget, max_slots=64) as sv:
+    with snf.Server(budget, max_slots=args.serve_slots) as sv:
         # warm-up on a few requests
         for h, o in list(zip(mats, outs))[:args.warmup * 4]:
             sv.wait(sv.submit_device(h.F, "snf_varmu", "fp32_ref64", out=o, **kw(h)))
@@ -450,7 +450,7 @@ def run_serve(args):
     closed_rate = count / closed_s
     # the same closed-loop pass through host buffers (PCIe-inclusive, for context)
     host_F = [h.F.cpu().numpy() for h in mats[:128]]
-    with snf.Server(budget, max_slots=64) as sv:
+    with snf.Server(budget, max_slots=args.serve_slots) as sv:
         t0 = time.perf_counter()
         tickets = [sv.submit(F, "snf_varmu", "fp32_ref64", **kw(h))
                    for F, h in zip(host_F, mats[:128])]
@@ -462,7 +462,7 @@ def run_serve(args):
     gaps = np.random.default_rng(55).exponential(1.0 / rate, size=count)
     arrivals = np.cumsum(gaps)
     lat, statuses = [], []
-    with snf.Server(budget, max_slots=64) as sv:
+    with snf.Server(budget, max_slots=args.serve_slots) as sv:
         tickets = []
         t0 = time.perf_counter()
         for h, o, ta in zip(mats, outs, arrivals):
@@ -482,7 +482,7 @@ def run_serve(args):
                                    "request, SnF varying-mu, fp32_ref64; matrices resident "
                                    "in HBM (device submit)",
                        "arrival_rate_per_s": round(rate, 2), "hbm_budget_gb": budget >> 30,
-                       "max_slots": 64})
+                       "max_slots": args.serve_slots})
     line["latency_ms"] = dict(p50=round(float(np.percentile(lat, 50)), 2),
                               p99=round(float(np.percentile(lat, 99)), 2),
                               mean=round(float(lat.mean()), 2))
@@ -519,6 +519,8 @@ def main():
     ap.add_argument("--bsr-sweep", action="store_true",
                     help="with --workload bsr: one solve per (scheme, truncation threshold) of "
                          "the sweep, one JSON line each")
+    ap.add_argument("--serve-slots", type=int, default=256,
+                    help="serving workload: requests in flight at most")
     ap.add_argument("--bsr-ec", action="store_true",
                     help="block-sparse workload: also run fixed-threshold and error-controlled "
                          "truncation at several budgets, with ||[F, D]||_F estimates")
