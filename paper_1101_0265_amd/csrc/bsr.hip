@@ -172,7 +172,7 @@ struct BsrProductArgs {
 constexpr int kBsrLdsW = 128 + 16;   // LDS row stride (floats), as the dense f32 kernel
 constexpr int kChunkWords = 8;      // bitmap words per k-stage list chunk (256 columns)
 
-__global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __restrict__ st,
+__global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __restrict__ st,
                                                              BsrProductArgs g) {
   if (st->stop) return;
   __shared__ __attribute__((aligned(16))) float sA[2][kB][kBsrLdsW];
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
   __shared__ uint32_t sw[kChunkWords];
   __shared__ int offs[kChunkWords + 1];
   __shared__ uint32_t spres[2];
-  __shared__ double red[12];
+  __shared__ double red[24];
 
   const int packed = g.tiles[blockIdx.x];
   const int TI = packed >> 16, TJ = packed & 0xFFFF;
@@ -194,39 +194,36 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
   const int wr = wid >> 1, wc = wid & 1;
   const int ci0 = kSup * TI, cj0 = kSup * TJ;   // first block column of the A / B panels
 
-  flt4 acc[4][4];
+  // 8 waves: wave (wr, wc) holds A block row wr (32 rows) against B blocks 2 wc, 2 wc + 1
+  flt4 acc[2][4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < 2; ++m)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[m][q] = flt4{0.f, 0.f, 0.f, 0.f};
 
-  // Each thread moves one 16-byte piece of each of the 8 blocks of a stage:
-  // block row k = tid / 8, columns 4 (tid % 8) .. +3.
-  const int lk = tid >> 3, lc = (tid & 7) * 4;
-  u32x4 ra[kSup], rb[kSup];
+  // Threads 0-255 move the A panel, 256-511 the B panel: one 16-byte piece of each of the 4
+  // blocks of their side, block row k = t / 8, columns 4 (t % 8) .. +3 (t = tid mod 256).
+  const int side = tid >> 8, lk = (tid & 255) >> 3, lc = (tid & 7) * 4;
+  u32x4 rv[kSup];
   uint32_t pres = 0;   // presence of the stage's blocks: bits 0-3 A panel, 4-7 B panel
   auto gload = [&](int s) {
     // the 4 panel columns of each side share one bitmap word of block row K
     const uint32_t wa = kwa[s], wb = kwb[s];
     pres = ((wa >> (ci0 & 31)) & 0xFu) | (((wb >> (cj0 & 31)) & 0xFu) << 4);
-    const int pa0 = kpa[s], pb0 = kpb[s];
+    const uint32_t wv = side ? wb : wa;
+    const int c0v = side ? cj0 : ci0, p0 = side ? kpb[s] : kpa[s];
 #pragma unroll
     for (int a = 0; a < kSup; ++a) {
-      const uint32_t bia = 1u << ((ci0 + a) & 31), bib = 1u << ((cj0 + a) & 31);
-      ra[a] = (wa & bia) ? bsr_gload16(g.X.val + (size_t)(pa0 + __popc(wa & (bia - 1u))) * kBB +
-                                       lk * kB + lc)
-                         : u32x4{0, 0, 0, 0};
-      rb[a] = (wb & bib) ? bsr_gload16(g.X.val + (size_t)(pb0 + __popc(wb & (bib - 1u))) * kBB +
+      const uint32_t bit = 1u << ((c0v + a) & 31);
+      rv[a] = (wv & bit) ? bsr_gload16(g.X.val + (size_t)(p0 + __popc(wv & (bit - 1u))) * kBB +
                                        lk * kB + lc)
                          : u32x4{0, 0, 0, 0};
     }
   };
   auto lstore = [&](int buf) {
+    float(*dst)[kBsrLdsW] = side ? sB[buf] : sA[buf];
 #pragma unroll
-    for (int a = 0; a < kSup; ++a) {
-      *(u32x4*)(&sA[buf][lk][a * kB + lc]) = ra[a];
-      *(u32x4*)(&sB[buf][lk][a * kB + lc]) = rb[a];
-    }
+    for (int a = 0; a < kSup; ++a) *(u32x4*)(&dst[lk][a * kB + lc]) = rv[a];
     if (tid == 0) spres[buf] = pres;
   };
 
@@ -267,7 +264,7 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
     }
     __syncthreads();
     const int nk = offs[kChunkWords];
-    for (int t = tid; t < nk; t += 256) {
+    for (int t = tid; t < nk; t += 512) {
       const int K = klist[t];
       const int rp = g.X.row_ptr[K];
       kwa[t] = g.X.bm[(size_t)K * W + (ci0 >> 5)];
@@ -284,33 +281,29 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
       const int buf = s & 1;
       const bool more = s + 1 < nk;
       if (more) gload(s + 1);
-      // this wave's two A blocks (rows 2 wr, 2 wr + 1) and two B blocks; absent blocks are
-      // zero, so their MFMAs are skipped (the test is uniform across the wave)
+      // this wave's A block (row wr) and two B blocks; absent blocks are zero, so their
+      // MFMAs are skipped (the test is uniform across the wave)
       const uint32_t pm = spres[buf];
-      const bool pa0 = (pm >> (2 * wr)) & 1u, pa1 = (pm >> (2 * wr + 1)) & 1u;
+      const bool pa = (pm >> wr) & 1u;
       const bool pb0 = (pm >> (4 + 2 * wc)) & 1u, pb1 = (pm >> (4 + 2 * wc + 1)) & 1u;
-      if ((pa0 || pa1) && (pb0 || pb1)) {
+      if (pa && (pb0 || pb1)) {
 #pragma unroll
         for (int kk = 0; kk < kB; kk += 4) {
-          float a[4], b[4];
+          float a[2], b[4];
 #pragma unroll
-          for (int m = 0; m < 4; ++m) a[m] = sA[buf][kk + fk][wr * 64 + m * 16 + fr];
+          for (int m = 0; m < 2; ++m) a[m] = sA[buf][kk + fk][wr * kB + m * 16 + fr];
 #pragma unroll
           for (int q = 0; q < 4; ++q) b[q] = sB[buf][kk + fk][wc * 64 + q * 16 + fr];
 #pragma unroll
-          for (int bi = 0; bi < 2; ++bi) {
+          for (int bj = 0; bj < 2; ++bj) {
+            if (!(bj ? pb1 : pb0)) continue;
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
-              if (!((bi ? pa1 : pa0) && (bj ? pb1 : pb0))) continue;
+            for (int m = 0; m < 2; ++m)
 #pragma unroll
-              for (int mm = 0; mm < 2; ++mm)
-#pragma unroll
-                for (int qq = 0; qq < 2; ++qq) {
-                  const int m = 2 * bi + mm, q = 2 * bj + qq;
-                  acc[m][q] =
-                      __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], b[q], acc[m][q], 0, 0, 0);
-                }
-            }
+              for (int qq = 0; qq < 2; ++qq) {
+                const int q = 2 * bj + qq;
+                acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], b[q], acc[m][q], 0, 0, 0);
+              }
           }
         }
       }
@@ -319,17 +312,16 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
     }
   }
 
-  // Epilogue.  Wave (wr, wc) holds blocks (2 wr + bi, 2 wc + bj) of the super-tile; the
-  // f32 MFMA accumulator of lane l, register v is row 4 (l / 16) + v, column l % 16 of its
-  // 16x16 piece (m, q): block bi = m / 2, row (m % 2) 16 + ..., block bj = q / 2.
+  // Epilogue.  Wave (wr, wc) holds blocks (wr, 2 wc + bj) of the super-tile; the f32 MFMA
+  // accumulator of lane l, register v is row 4 (l / 16) + v, column l % 16 of its 16x16
+  // piece (m, q): rows m 16 + ... of block row wr, block bj = q / 2.
   const double c2 = st->c2, c1 = st->c1, c0 = st->c0;
   const int want_e = st->want_e;
   double e2 = 0.0, t1 = 0.0;
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi) {
+  {
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
-      const int I = kSup * TI + 2 * wr + bi, J = kSup * TJ + 2 * wc + bj;
+      const int I = kSup * TI + wr, J = kSup * TJ + 2 * wc + bj;
       if (I >= nb || J >= nb) continue;
       if (I > J) continue;                       // lower blocks come from their mirror
       const int pp = bsr_find(g.P.row_ptr, g.P.bm, g.P.pre, W, I, J);
@@ -344,7 +336,7 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
       for (int mm = 0; mm < 2; ++mm) {
 #pragma unroll
         for (int qq = 0; qq < 2; ++qq) {
-          const int m = 2 * bi + mm, q = 2 * bj + qq;
+          const int m = mm, q = 2 * bj + qq;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int r = mm * 16 + 4 * (lane >> 4) + v;
@@ -385,8 +377,13 @@ __global__ __launch_bounds__(256, 2) void bsr_product_kernel(const SnfState* __r
   }
   __syncthreads();
   if (tid == 0) {
-    g.partials[blockIdx.x * 4 + 0] = ((red[0] + red[3]) + red[6]) + red[9];
-    g.partials[blockIdx.x * 4 + 1] = ((red[1] + red[4]) + red[7]) + red[10];
+    double se = 0.0, st1 = 0.0;
+    for (int k = 0; k < 8; ++k) {       // wave order
+      se += red[k * 3 + 0];
+      st1 += red[k * 3 + 1];
+    }
+    g.partials[blockIdx.x * 4 + 0] = se;
+    g.partials[blockIdx.x * 4 + 1] = st1;
     g.partials[blockIdx.x * 4 + 2] = 0.0;
     g.partials[blockIdx.x * 4 + 3] = 0.0;
   }
@@ -784,7 +781,7 @@ static int bsr_step(BsrWorkspace* w, int cur, int nb, int W, double tau2, int* s
   args.W = W;
   if (ev_a) BSR_HIP(hipEventRecord(ev_a, s));
   if (ntiles > 0)
-    hipLaunchKernelGGL(bsr_product_kernel, dim3(ntiles), dim3(256), 0, s, w->state, args);
+    hipLaunchKernelGGL(bsr_product_kernel, dim3(ntiles), dim3(512), 0, s, w->state, args);
   if (ev_b) BSR_HIP(hipEventRecord(ev_b, s));
   BSR_HIP(hipGetLastError());
   // 5. truncation (threshold from the norm histogram under error control)
