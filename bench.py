@@ -33,12 +33,29 @@ LATTICE = (16, 16, 8)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xx_f64_lattice_n4096_traffic.json")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files=("kernels_dense.hip", "snf_internal.h", "schedule_math.h")) -> str:
     h = hashlib.sha256()
-    for f in ("kernels_dense.hip", "snf_internal.h", "schedule_math.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1101_0265_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+BSR_SOURCES = ("bsr.hip", "kernels_dense.hip", "snf_internal.h", "schedule_math.h")
+BSR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bsr_lattice_n65536_traffic.json")
+
+
+def load_bsr_traffic():
+    """Counter-measured bytes and time of the block-sparse product kernel for the solves of
+    the block-sparse workload, or None if taken on other sources."""
+    try:
+        with open(BSR_TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash(BSR_SOURCES):
+        return None
+    return t
 
 
 def load_traffic(n_products_per_launch: int = 1):
@@ -392,6 +409,15 @@ def run_bsr(args):
                             traffic=None, kernel="bsr_product_kernel (f32 MFMA super-tiles)",
                             note="achieved = 2*32^3 flops per stored-block triple (I,K,J), "
                                  "I<=J, over the summed numeric-kernel time")
+    bt = load_bsr_traffic()
+    if bt is not None:
+        per_launch = bt["product_bytes"] / bt["product_launches"]
+        line["roofline"]["traffic"] = per_launch
+        line["hbm"] = dict(kernel="bsr_product_kernel", achieved_tbs=round(
+            bt["product_bytes"] / (bt["product_ms"] * 1e-3) / 1e12, 2), peak_tbs=8.0,
+            frac=round(bt["product_bytes"] / (bt["product_ms"] * 1e-3) / 8e12, 3),
+            note="FETCH_SIZE + WRITE_SIZE of the product kernel over both solves (rocprofv3 "
+                 "counter runs, copy-calibrated), over its summed time")
     line["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         # the dense block-masked FP64 oracle cannot hold n = 65536 (34 GB per matrix, hours
