@@ -12,6 +12,9 @@ Follows the paper's steps on n x n matrices with ``numpy.matmul``:
 * The same with P_{3,3} or P_{5,5} in place of P_{1,1} (Eq. 2 for odd m): X <- P_{m,m}(X_s),
   evaluated by Horner's rule in X_s on the exact coefficients; the count reported is the
   scheme's m + 1 products per iteration, not the oracle's own.
+* P_{i,j} with i, j odd, scaled about its fixed point x*: X_0 = (mu I - F)/gamma + x* I,
+  X <- P_{i,j}(a (X - x* I) + x* I), Horner in X_s on the exact coefficients (the schedule
+  and its reading are in ``oracle.schedule``); the count is the scheme's (i + j)/2 + 1.
 
 Stopping rule (reading of the open loop length): X_{i-1}^2 is formed, and if
 ||X_{i-1}^2 - X_{i-1}||_F <= tol the result is D = X_{i-1}.  The scheme's product count
@@ -37,18 +40,27 @@ from . import schedule as sch
 
 
 def f0(F: np.ndarray, scheme: str, lambda_min: float, lambda_max: float,
-       mu: float = None) -> np.ndarray:
+       mu: float = None, st: "sch.SchemeState" = None) -> np.ndarray:
     n = F.shape[0]
     I = np.eye(n)
     if scheme in ("sp2", "tc2", "snf_varmu"):
         return (lambda_max * I - F) / (lambda_max - lambda_min)       # Algorithm 2, f_0
+    if scheme in sch.GENERAL:                                          # mu onto x*
+        return (mu * I - F) / st.gamma + st.xs * I
     gamma = sch.alg1_gamma(lambda_min, lambda_max, mu)
     return (mu * I - F) / gamma + 0.5 * I                              # Algorithm 1, X_0
 
 
-def step(X: np.ndarray, branch: str, alpha: float) -> np.ndarray:
+def step(X: np.ndarray, branch: str, alpha: float, st: "sch.SchemeState" = None) -> np.ndarray:
     """One purification transformation f_i, as printed."""
     I = np.eye(X.shape[0])
+    if branch == sch.PIJ:                      # P_{i,j}(a (X - x* I) + x* I), Horner in X_s
+        Xs = alpha * (X - st.xs * I) + st.xs * I
+        c = [float(v) for v in poly.p_ij_exact(st.i, st.j)]
+        Y = c[-1] * I
+        for k in range(len(c) - 2, -1, -1):
+            Y = Y @ Xs + c[k] * I
+        return Y
     if branch == sch.SQUARE:
         Y = (1.0 + alpha) * X - alpha * I
         return Y @ Y
@@ -70,7 +82,7 @@ def step(X: np.ndarray, branch: str, alpha: float) -> np.ndarray:
 def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
            n_occ: int = None, homo: float = None, lumo: float = None, mu: float = None,
            xi: float = None, tol: float = 1e-10, max_iter: int = 200, mask=None,
-           force_branches: str = None) -> dict:
+           force_branches: str = None, poly_ij=None) -> dict:
     """Purify the dense symmetric ``F``.
 
     Returns dict(status, D, iterations, products, branches, log, e_final, trace) with the
@@ -80,12 +92,13 @@ def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
     """
     if F.ndim != 2 or F.shape[0] != F.shape[1]:
         raise ValueError("F must be square")
-    st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi)
-    X = f0(np.asarray(F, dtype=np.float64), scheme, lambda_min, lambda_max, mu)
+    st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi,
+                         poly_ij=poly_ij)
+    X = f0(np.asarray(F, dtype=np.float64), scheme, lambda_min, lambda_max, mu, st)
     gap_mask = mask is not None and getattr(mask, "needs_gap", False)
     if mask is not None and not gap_mask:
         X = mask(X)
-    per_it = sch.products_per_iteration(scheme)
+    per_it = sch.products_per_iteration(scheme, poly_ij)
     log, branches = [], []
     products = 0
     status = "noconv"
@@ -114,7 +127,7 @@ def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
                    margin=(sch.trace_margin(t1, t2, n_occ) if scheme == "sp2" else None))
         log.append(rec)
         branches.append(branch)
-        X = step(X, branch, alpha)
+        X = step(X, branch, alpha, st)
         st.advance(branch, alpha)
         if gap_mask:
             X = mask(X, st.betabar - st.beta)

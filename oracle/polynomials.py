@@ -7,14 +7,16 @@ the Hermite interpolation system; the closed forms used by the algorithms (P_{1,
 P_{0,1} = 2x - x^2, P_{1,1} = 3x^2 - 2x^3, Algorithm 1's update) are written separately and
 the tests pin one against the other.
 
-The higher-order fixed-mu schemes need P_{m,m} for odd m exactly: ``p_ij_exact`` solves the
-same Hermite system in rational arithmetic, so its coefficients carry no rounding.
+The higher-order fixed-mu schemes need P_{m,m} for odd m exactly, and the asymmetric ones
+P_{i,j} with i != j both odd: ``p_ij_exact`` solves the same Hermite system in rational
+arithmetic, so its coefficients carry no rounding.
 
 Parity: pinned (closed forms == definition; fixed points and derivative conditions; the exact
 coefficients against the binomial form of P_{i,j} and the derivative x^m (1-x)^m).
 """
 from __future__ import annotations
 
+import functools
 from fractions import Fraction
 
 import numpy as np
@@ -74,6 +76,11 @@ def p11(x):
 def p_ij_exact(i: int, j: int) -> list:
     """Monomial coefficients (ascending, ``Fraction``) of P_{i,j} from the same defining
     conditions as ``p_ij_coefficients``, solved by exact Gaussian elimination."""
+    return list(_p_ij_exact(i, j))
+
+
+@functools.lru_cache(maxsize=None)
+def _p_ij_exact(i: int, j: int) -> tuple:
     d = 1 + i + j
 
     def deriv_row(x: int, k: int) -> list:
@@ -96,7 +103,7 @@ def p_ij_exact(i: int, j: int) -> list:
             if r != c and rows[r][c] != 0:
                 f = rows[r][c] / rows[c][c]
                 rows[r] = [a - f * b for a, b in zip(rows[r], rows[c])]
-    return [rows[k][size] / rows[k][k] for k in range(size)]
+    return tuple(rows[k][size] / rows[k][k] for k in range(size))
 
 
 def pmm(m: int, x):
@@ -106,4 +113,23 @@ def pmm(m: int, x):
     y = c[-1]
     for k in range(len(c) - 2, -1, -1):
         y = y * x + c[k]
+    return y
+
+
+def pij(i: int, j: int, x):
+    """P_{i,j}(x) in FP64, Horner on the exact coefficients rounded once to FP64 (any i, j;
+    ``pmm`` is the case i = j)."""
+    c = [float(v) for v in p_ij_exact(i, j)]
+    x = np.asarray(x, dtype=np.float64) if not np.isscalar(x) else float(x)
+    y = c[-1]
+    for k in range(len(c) - 2, -1, -1):
+        y = y * x + c[k]
+    return y
+
+
+def pij_fraction(i: int, j: int, x: Fraction) -> Fraction:
+    """P_{i,j}(x) exactly, for a rational x."""
+    y = Fraction(0)
+    for c in reversed(p_ij_exact(i, j)):
+        y = y * x + c
     return y

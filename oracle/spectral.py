@@ -25,16 +25,20 @@ from . import schedule as sch
 
 
 def f0_eigs(eigvals: np.ndarray, scheme: str, lambda_min: float, lambda_max: float,
-            mu: float = None) -> np.ndarray:
-    """Eigenvalues of X_0 = f_0(F) (Algorithm 2 / trace scheme, or Algorithm 1)."""
+            mu: float = None, st: "sch.SchemeState" = None) -> np.ndarray:
+    """Eigenvalues of X_0 = f_0(F) (Algorithm 2 / trace scheme, or Algorithm 1; the P_{i,j}
+    schemes centre mu on their fixed point x* with the scale ``st.gamma``)."""
     lam = np.asarray(eigvals, dtype=np.float64)
     if scheme in ("sp2", "tc2", "snf_varmu"):
         return (lambda_max - lam) / (lambda_max - lambda_min)
+    if scheme in sch.GENERAL:
+        return (mu - lam) / st.gamma + st.xs
     gamma = sch.alg1_gamma(lambda_min, lambda_max, mu)
     return (mu - lam) / gamma + 0.5
 
 
-def apply_branch(p: np.ndarray, branch: str, alpha: float) -> np.ndarray:
+def apply_branch(p: np.ndarray, branch: str, alpha: float,
+                 st: "sch.SchemeState" = None) -> np.ndarray:
     """One f_i on eigenvalues, written as the paper's transformation."""
     if branch == sch.SQUARE:                 # P_{1,0}((1+a) x - a), Eq. 4
         y = (1.0 + alpha) * p - alpha
@@ -42,6 +46,8 @@ def apply_branch(p: np.ndarray, branch: str, alpha: float) -> np.ndarray:
     if branch == sch.FOLD:                   # P_{0,1}((1+a) x), Eq. 5
         z = (1.0 + alpha) * p
         return 2.0 * z - z * z
+    if branch == sch.PIJ:                    # P_{i,j}(a (x - x*) + x*)
+        return poly.pij(st.i, st.j, alpha * (p - st.xs) + st.xs)
     xs = alpha * (p - 0.5) + 0.5             # P_{m,m}(a (x - 1/2) + 1/2), Eq. 2
     if branch == sch.MCW:
         return 3.0 * xs * xs - 2.0 * xs * xs * xs
@@ -54,16 +60,17 @@ products_per_iteration = sch.products_per_iteration
 def purify_spectrum(eigvals: np.ndarray, scheme: str, *, lambda_min: float,
                     lambda_max: float, n_occ: int = None, homo: float = None,
                     lumo: float = None, mu: float = None, xi: float = None,
-                    tol: float = 1e-10, max_iter: int = 200) -> dict:
+                    tol: float = 1e-10, max_iter: int = 200, poly_ij=None) -> dict:
     """Run ``scheme`` on the spectrum; returns the final eigenvalues of D and the log.
 
     Returned keys: status ("ok" | "noconv" | "nonfinite"), p (eigenvalues of D), iterations,
     products, branches (string of S/F/M), log (list of per-iteration dicts with i, branch,
     alpha, beta, betabar, e, t1, t2 of X_{i-1} before the step), e_final, trace.
     """
-    st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi)
-    p = f0_eigs(eigvals, scheme, lambda_min, lambda_max, mu)
-    per_it = products_per_iteration(scheme)
+    st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi,
+                         poly_ij=poly_ij)
+    p = f0_eigs(eigvals, scheme, lambda_min, lambda_max, mu, st)
+    per_it = products_per_iteration(scheme, poly_ij)
     log, branches = [], []
     products = 0
     status = "noconv"
@@ -88,7 +95,7 @@ def purify_spectrum(eigvals: np.ndarray, scheme: str, *, lambda_min: float,
         rec.update(branch=branch, alpha=alpha)
         log.append(rec)
         branches.append(branch)
-        p = apply_branch(p, branch, alpha)
+        p = apply_branch(p, branch, alpha, st)
         st.advance(branch, alpha)
         products += per_it - 1                     # Algorithm 1's second product
     return dict(status=status, p=p, iterations=len(branches), products=products,
@@ -98,10 +105,11 @@ def purify_spectrum(eigvals: np.ndarray, scheme: str, *, lambda_min: float,
 
 def decision_sequence(scheme: str, *, lambda_min: float, lambda_max: float, homo: float,
                       lumo: float, mu: float = None, xi: float = None,
-                      steps: int = 64) -> list:
+                      steps: int = 64, poly_ij=None) -> list:
     """(branch, alpha, beta, betabar) for the first ``steps`` iterations of the scalar
     recurrence alone (Algorithms 1 and 2 decide without looking at X)."""
-    st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi)
+    st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi,
+                         poly_ij=poly_ij)
     out = []
     for _ in range(steps):
         branch, alpha = st.choose()
@@ -125,6 +133,24 @@ def products_to_accuracy(scheme: str, mu01: float, xi: float, acc: float = 1e-9,
         pass
     st = sch.SchemeState(scheme, **kw)
     per_it = products_per_iteration(scheme)
+    prods = 0
+    for _ in range(max_iter):
+        if st.bound() <= acc:
+            return prods
+        branch, alpha = st.choose()
+        st.advance(branch, alpha)
+        prods += per_it
+    raise RuntimeError("did not reach the requested accuracy")
+
+
+def products_to_accuracy_pij(poly_ij, *, lambda_min: float, lambda_max: float, mu: float,
+                             xi: float, acc: float = 1e-9, scaled: bool = True,
+                             max_iter: int = 200) -> int:
+    """Products of the P_{i,j} fixed-mu scheme until max(a, a-bar) <= acc, for a spectrum in
+    [lambda_min, lambda_max] with a gap of width xi centred at mu and exact bounds."""
+    st = sch.SchemeState("snf_pij" if scaled else "pij", lambda_min, lambda_max, mu=mu, xi=xi,
+                         poly_ij=poly_ij)
+    per_it = products_per_iteration(st.scheme, poly_ij)
     prods = 0
     for _ in range(max_iter):
         if st.bound() <= acc:
