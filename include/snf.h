@@ -6,7 +6,8 @@
  * arXiv:1101.0265) by recursive purification, Eq. 1:
  *     X_0 = f_0(F),   X_i = f_i(X_{i-1}),  i = 1, 2, ...
  * where f_0 is linear and every f_i costs one matrix-matrix product X.X (two for
- * Algorithm 1, m + 1 for the P_{m,m} schemes).  Nine schemes are offered:
+ * Algorithm 1, m + 1 for the P_{m,m} schemes, (i + j)/2 + 1 for P_{i,j}).  Eleven schemes
+ * are offered:
  *
  *   SNF_SP2_TRACE   second-order trace-correcting purification, x^2 / 2x - x^2 chosen from
  *                   the trace of X (the unscaled scheme the paper compares against).
@@ -23,6 +24,23 @@
  *   The P_{m,m} schemes evaluate P_{m,m}(1/2 + v) = 1/2 + v r(v^2) (the polynomial is
  *   point-symmetric about (1/2, 1/2); r has degree m): v^2, r by Horner's rule, then v r.
  *   They take the inputs of Algorithm 1 and run in SNF_P_FP64 only.
+ *   SNF_SNF_FIXMU_PIJ  fixed-mu scale-and-fold with P_{i,j}, i and j odd (poly_i, poly_j in
+ *                   snf_params, each 1, 3 or 5), scaled about the polynomial's unstable
+ *                   fixed point x* (the remark closing the P_{m,m} paragraph before
+ *                   Algorithm 1; x* != 1/2 when i != j):
+ *                     X_0 = (mu I - F) / gamma + x* I,
+ *                     gamma = max((mu - lambda_min) / (1 - x*), (lambda_max - mu) / x*),
+ *                     f_i(X) = P_{i,j}(alpha (X - x* I) + x* I).
+ *                   The unoccupied part of the spectrum lies in [0, a], the occupied part
+ *                   in [1 - a', 1]; each side has its own Eq. 3 (the folded image of its
+ *                   interval end equals the image of its gap edge), and alpha is the
+ *                   smaller root: the largest scaling that speeds up both sides.  For
+ *                   i = j this is SNF_SNF_FIXMU / SNF_SNF_FIXMU3 / SNF_SNF_FIXMU5.
+ *                   Evaluation: P(x* + v) = x* + v Q(v), Q by Horner's rule in v^2 with
+ *                   coefficients linear in v.  Inputs of Algorithm 1; SNF_P_FP64 only;
+ *                   SNF_EINVAL for poly_i / poly_j outside {1, 3, 5} or a gap edge that
+ *                   falls outside [0, 1] (xi / (2 gamma) >= min(x*, 1 - x*)).
+ *   SNF_PIJ         SNF_SNF_FIXMU_PIJ with alpha = 1 (unscaled grand-canonical P_{i,j}).
  *
  * Conventions shared by every entry point:
  *  - Matrices are row-major FP64.  Only the upper triangle of F (j >= i) is read; the
@@ -69,7 +87,9 @@ typedef enum {
   SNF_SNF_FIXMU3 = 5,
   SNF_SNF_FIXMU5 = 6,
   SNF_PMM3 = 7,
-  SNF_PMM5 = 8
+  SNF_PMM5 = 8,
+  SNF_SNF_FIXMU_PIJ = 9,
+  SNF_PIJ = 10
 } snf_scheme;
 
 typedef enum {
@@ -85,6 +105,7 @@ typedef enum {
 #define SNF_BRANCH_P11    2   /* P_{1,1}: X <- 3 Xs^2 - 2 Xs^3, Xs = a (X - I/2) + I/2 (Eq. 2) */
 #define SNF_BRANCH_P33    3   /* P_{3,3}(Xs)                                                 */
 #define SNF_BRANCH_P55    4   /* P_{5,5}(Xs)                                                 */
+#define SNF_BRANCH_PIJ    5   /* P_{i,j}(a (X - x* I) + x* I)                                */
 
 /* Flags (snf_params.flags). */
 #define SNF_FLAG_TIME_PRODUCTS 1  /* bracket every product kernel with HIP events and report
@@ -112,6 +133,9 @@ typedef enum {
  *             eigenvalue error max(beta, 1 - beta-bar) is below this value (0 = default
  *             1e-4 for FP32, 1e-2 for BF16).
  *  flags:     SNF_FLAG_* bits.
+ *  poly_i, poly_j: the polynomial P_{i,j} of SNF_SNF_FIXMU_PIJ / SNF_PIJ (odd, 1..5);
+ *             ignored by the other schemes.  For these two schemes the log's beta is a and
+ *             its beta-bar is 1 - a' (the bounds of the two parts above).
  */
 typedef struct {
   double lambda_min, lambda_max;
@@ -123,6 +147,7 @@ typedef struct {
   int32_t flags;
   double gap_switch;
   double lowp_floor;
+  int32_t poly_i, poly_j;
 } snf_params;
 
 #define SNF_LOG_MAX 256

@@ -80,7 +80,8 @@ static void free_buffers(Workspace* w) {
   w->lp_bytes = 0;
 }
 
-// nbuf: FP64 n_pad x n_pad buffers the call needs (3, or 4 for the P_{m,m} schemes).
+// nbuf: FP64 n_pad x n_pad buffers the call needs (3, or 4 for the P_{m,m} and P_{i,j}
+// schemes).
 static int ensure_workspace(Workspace* w, int64_t np, int lp_bytes, int partial_need,
                             int nbuf = 3) {
   if (!w->state) {
@@ -176,7 +177,7 @@ static bool finite(double v) { return isfinite(v) != 0; }
 
 int validate(int64_t n, const snf_params* p, snf_scheme scheme, snf_precision prec) {
   if (!p || n <= 0) return SNF_EINVAL;
-  if ((int)scheme < SNF_SP2_TRACE || (int)scheme > SNF_PMM5) return SNF_EINVAL;
+  if ((int)scheme < SNF_SP2_TRACE || (int)scheme > SNF_PIJ) return SNF_EINVAL;
   if ((int)prec < SNF_P_FP64 || (int)prec > SNF_P_BF16_REF64) return SNF_EINVAL;
   if (!finite(p->lambda_min) || !finite(p->lambda_max) || !(p->lambda_min < p->lambda_max))
     return SNF_EINVAL;
@@ -194,6 +195,21 @@ int validate(int64_t n, const snf_params* p, snf_scheme scheme, snf_precision pr
     case SNF_SNF_VARMU:
       if (!gap_edges) return SNF_EINVAL;
       break;
+    case SNF_SNF_FIXMU_PIJ:
+    case SNF_PIJ: {
+      if (prec != SNF_P_FP64) return SNF_EINVAL;
+      const int pi = p->poly_i, pj = p->poly_j;
+      if (pi < 1 || pj < 1 || pi > sched::kPijMax || pj > sched::kPijMax || !(pi & 1) ||
+          !(pj & 1))
+        return SNF_EINVAL;
+      if (!finite(p->mu) || !finite(p->xi) || !(p->mu > p->lambda_min) ||
+          !(p->mu < p->lambda_max) || !(p->xi > 0.0))
+        return SNF_EINVAL;
+      const double xs = sched::pij_xstar(pi, pj);
+      const double h = p->xi / (2.0 * sched::pij_gamma(p->lambda_min, p->lambda_max, p->mu, xs));
+      if (!(h < xs) || !(h < 1.0 - xs)) return SNF_EINVAL;
+      break;
+    }
     case SNF_SNF_FIXMU3:
     case SNF_SNF_FIXMU5:
     case SNF_PMM3:
@@ -234,7 +250,19 @@ void init_state(SnfState* s, int64_t n, const snf_params* p, snf_scheme scheme,
   s->gap_switch = p->gap_switch;
   s->lowp_floor = p->lowp_floor > 0.0 ? p->lowp_floor : (prec == SNF_P_BF16_REF64 ? 1e-2 : 1e-4);
   s->pmm_m = scheme_pmm_m(scheme);
-  if (scheme == SNF_MCWEENY || scheme == SNF_SNF_FIXMU || s->pmm_m) {
+  s->xstar = 0.5;
+  if (scheme_is_pij(scheme)) {
+    // mu onto the fixed point x* of P_{i,j}; gap edges x* -/+ xi / (2 gamma)
+    s->pij_i = p->poly_i;
+    s->pij_j = p->poly_j;
+    s->xstar = sched::pij_xstar(s->pij_i, s->pij_j);
+    s->gamma = sched::pij_gamma(p->lambda_min, p->lambda_max, p->mu, s->xstar);
+    const double h = p->xi / (2.0 * s->gamma);
+    s->beta = s->xstar - h;
+    s->abar = (1.0 - s->xstar) - h;
+    s->betabar = 1.0 - s->abar;
+    sched::pij_taylor(s->pij_i, s->pij_j, s->xstar, s->pq);
+  } else if (scheme == SNF_MCWEENY || scheme == SNF_SNF_FIXMU || s->pmm_m) {
     s->gamma = sched::alg1_gamma(p->lambda_min, p->lambda_max, p->mu);
     s->beta = sched::alg1_beta0(p->xi, s->gamma);
     s->betabar = 1.0 - s->beta;
@@ -340,7 +368,7 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
   const int sym = 1;
   const int tiles = num_product_tiles(np, sym);
   rc = ensure_workspace(w, np, lowp_bytes_for(precision), tiles + 16 * kSplitCap,
-                        scheme_pmm_m(scheme) ? 4 : 3);
+                        (scheme_pmm_m(scheme) || scheme_is_pij(scheme)) ? 4 : 3);
   if (rc != SNF_OK) {
     out->status = rc;
     return rc;
@@ -351,7 +379,7 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
   // np, so every buffer just needs np*np elements.
   init_state(w->state_host, n, params, scheme, precision);
   const bool time_products = (params->flags & SNF_FLAG_TIME_PRODUCTS) != 0;
-  const int per_it = products_per_iteration(scheme);
+  const int per_it = products_per_iteration(scheme, params->poly_i, params->poly_j);
   const int max_steps = (params->max_iter + 1) * per_it + 1;
   if (time_products && (int)w->prod_ev.size() < 2 * max_steps) {
     const size_t old = w->prod_ev.size();
@@ -370,6 +398,7 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
   // Launch-ahead loop: chunks of `chunk` steps, two chunks in flight.
   const int chunk = np >= 2048 ? 2 : (np >= 1024 ? 4 : 8);
   const bool lowp = precision != SNF_P_FP64;
+  const bool pij = scheme_is_pij(scheme);
   int enq = 0, chunks = 0, checked = 0;
   int ev_used = 0;
   bool stopped = false;
@@ -378,6 +407,7 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
     for (int k = 0; k < chunk && enq < max_steps; ++k, ++enq) {
       if (time_products) SNF_HIP(hipEventRecord(w->prod_ev[ev_used], s));
       launch_product(kPrecF64, w->state, w->bufs_dev, grid, s);
+      if (pij) launch_product_dual(w->state, w->bufs_dev, grid, s);
       if (lowp) launch_product(lowp_kind_for(precision), w->state, w->bufs_dev, grid, s);
       launch_split_fixup(w->state, w->bufs_dev, grid, s);
       if (time_products) SNF_HIP(hipEventRecord(w->prod_ev[ev_used + 1], s));

@@ -87,8 +87,10 @@ __global__ __launch_bounds__(256) void f0_kernel(const double* __restrict__ F, i
                                                  int lowp_kind, double* __restrict__ partials) {
   __shared__ double tile[32][33];
   __shared__ double red[24];
-  const int alg1 = (st->scheme == SNF_MCWEENY || st->scheme == SNF_SNF_FIXMU || st->pmm_m);
+  const int alg1 = (st->scheme == SNF_MCWEENY || st->scheme == SNF_SNF_FIXMU || st->pmm_m ||
+                    st->pij_i);
   const double lmin = st->lambda_min, lmax = st->lambda_max, mu = st->mu, gamma = st->gamma;
+  const double xs = st->xstar;
   double* X = bufs->x[st->cur];
   void* LP = bufs->lp[st->cur];
   const int64_t nt = np / 32;
@@ -111,7 +113,7 @@ __global__ __launch_bounds__(256) void f0_kernel(const double* __restrict__ F, i
       if (gr < n && gc < n) {
         const bool d = (gr == gc);
         if (alg1) {
-          x = ((d ? mu : 0.0) - v) / gamma + (d ? 0.5 : 0.0);
+          x = ((d ? mu : 0.0) - v) / gamma + (d ? xs : 0.0);
         } else {
           x = ((d ? lmax : 0.0) - v) / (lmax - lmin);
         }
@@ -208,9 +210,11 @@ struct EpiArgs {
   const double* Xt;  // linear term X (FP64)
   double* Y;         // output (FP64)
   void* LPY;         // low-precision copy of the output, or unused
+  double* Y2;        // second output d2 P + d1 X + d0 I (FP64), or null
   int lowp_kind;     // kPrecF32 / kPrecBF16 / -1
   int want_e;
   double c2, c1, c0;
+  double d2, d1, d0;
 };
 
 __device__ __forceinline__ EpiArgs epi_args(const SnfState* st, const Buffers* bufs) {
@@ -218,6 +222,10 @@ __device__ __forceinline__ EpiArgs epi_args(const SnfState* st, const Buffers* b
   e.Xt = bufs->x[st->ix];
   e.Y = bufs->x[st->io];
   e.LPY = bufs->lp[st->io];
+  e.Y2 = st->dual ? bufs->x[st->io2] : nullptr;
+  e.d2 = st->d2;
+  e.d1 = st->d1;
+  e.d0 = st->d0;
   e.lowp_kind = st->write_lowp ? (st->mode == SNF_P_BF16_REF64 ? kPrecBF16 : kPrecF32) : -1;
   e.want_e = st->want_e;
   e.c2 = st->c2;
@@ -229,7 +237,9 @@ __device__ __forceinline__ EpiArgs epi_args(const SnfState* st, const Buffers* b
 // Epilogue of one product entry p at global (r, c): Y = c2 p + c1 X + c0 [r == c], the FP64
 // sums, the mirror write.  In symmetric mode a diagonal tile keeps its upper half and
 // mirrors it, so the result is exactly symmetric; every off-diagonal entry then stands for
-// two.
+// two.  With DUAL the second output Y2 is written too (compiled only into the kernel variants
+// that need it, so the others keep their register budget).
+template <bool DUAL = false>
 __device__ __forceinline__ void epi_elem(double p, int64_t r, int64_t c, int sym, int diag,
                                          int64_t n, int64_t np, const EpiArgs& ea, double& e2,
                                          double& t1, double& t2) {
@@ -247,6 +257,12 @@ __device__ __forceinline__ void epi_elem(double p, int64_t r, int64_t c, int sym
   t2 += w * (y * y);
   ea.Y[r * np + c] = y;
   if (mirror) ea.Y[c * np + r] = y;
+  if (DUAL && ea.Y2) {
+    double y2 = ea.d2 * p + ea.d1 * x + (r == c ? ea.d0 : 0.0);
+    if (r >= n || c >= n) y2 = 0.0;
+    ea.Y2[r * np + c] = y2;
+    if (mirror) ea.Y2[c * np + r] = y2;
+  }
   if (ea.lowp_kind == kPrecF32) {
     const float yf = (float)y;
     ((float*)ea.LPY)[r * np + c] = yf;
@@ -268,7 +284,7 @@ __device__ __forceinline__ int acc_row(int lane, int v) {
 }
 
 // One 16x16 MFMA block (m, q) of the wave tile: acc4 holds its four values of this lane.
-template <bool ROWS_INTERLEAVED, typename Acc4>
+template <bool ROWS_INTERLEAVED, bool DUAL, typename Acc4>
 __device__ __forceinline__ void epilogue_block(const Acc4& acc4, int m, int q, int gi0, int gj0,
                                                int sym, int diag, int64_t n, int64_t np,
                                                const EpiArgs& ea, double& e2, double& t1,
@@ -278,11 +294,11 @@ __device__ __forceinline__ void epilogue_block(const Acc4& acc4, int m, int q, i
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int64_t r = gi0 + m * 16 + acc_row<ROWS_INTERLEAVED>(lane, v);
-    epi_elem((double)acc4[v], r, c, sym, diag, n, np, ea, e2, t1, t2);
+    epi_elem<DUAL>((double)acc4[v], r, c, sym, diag, n, np, ea, e2, t1, t2);
   }
 }
 
-template <bool ROWS_INTERLEAVED, int MT, int QT, typename AccT>
+template <bool ROWS_INTERLEAVED, bool DUAL, int MT, int QT, typename AccT>
 __device__ __forceinline__ void epilogue(const AccT (&acc)[MT][QT], int gi0, int gj0, int sym,
                                          int diag, int64_t n, int64_t np, const EpiArgs& ea,
                                          double& e2, double& t1, double& t2) {
@@ -290,8 +306,8 @@ __device__ __forceinline__ void epilogue(const AccT (&acc)[MT][QT], int gi0, int
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int q = 0; q < QT; ++q)
-      epilogue_block<ROWS_INTERLEAVED>(acc[m][q], m, q, gi0, gj0, sym, diag, n, np, ea, e2, t1,
-                                       t2);
+      epilogue_block<ROWS_INTERLEAVED, DUAL>(acc[m][q], m, q, gi0, gj0, sym, diag, n, np, ea,
+                                             e2, t1, t2);
 }
 
 __device__ __forceinline__ void write_partials(double e2, double t1, double t2,
@@ -370,7 +386,7 @@ template <> struct Layout<float> {    // 8 waves of 32x64: 32 accumulator regist
   static constexpr int NT = 512, WC = 2;   // 4 waves per SIMD
 };
 
-template <typename T, int PREC>
+template <typename T, int PREC, bool DUAL = false>
 __device__ __forceinline__ void product_body(const SnfState* __restrict__ st,
                                              const Buffers* __restrict__ bufs,
                                              const ProductGrid& g, const WorkItem& wi) {
@@ -450,8 +466,8 @@ __device__ __forceinline__ void product_body(const SnfState* __restrict__ st,
   }
   const EpiArgs ea = epi_args(st, bufs);
   double e2 = 0.0, t1 = 0.0, t2 = 0.0;
-  epilogue<PREC == kPrecF64>(acc, (int)(i0 + wr * TR), (int)(j0 + wc * TC), g.sym, bi == bj,
-                             g.n, np, ea, e2, t1, t2);
+  epilogue<PREC == kPrecF64, DUAL>(acc, (int)(i0 + wr * TR), (int)(j0 + wc * TC), g.sym,
+                                   bi == bj, g.n, np, ea, e2, t1, t2);
   write_partials(e2, t1, t2, g.partials, wi.tile);
 }
 
@@ -541,16 +557,27 @@ __device__ __forceinline__ void product_bf16_body(const SnfState* __restrict__ s
   }
   const EpiArgs ea = epi_args(st, bufs);
   double e2 = 0.0, t1 = 0.0, t2 = 0.0;
-  epilogue<false>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), g.sym, bi == bj, g.n, np, ea,
-                  e2, t1, t2);
+  epilogue<false, false>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), g.sym, bi == bj, g.n,
+                         np, ea, e2, t1, t2);
   write_partials(e2, t1, t2, g.partials, wi.tile);
 }
 
 __global__ __launch_bounds__(512, 2) void product_f64_kernel(const SnfState* __restrict__ st,
                                                              const Buffers* __restrict__ bufs,
                                                              ProductGrid g) {
-  if (st->stop || st->prec != kPrecF64) return;
+  if (st->stop || st->prec != kPrecF64 || st->dual) return;
   product_body<double, kPrecF64>(st, bufs, g, work_item(g, (int)(g.np / Mfma<double>::kBK)));
+}
+
+// The FP64 product whose epilogue also writes the second output (the first product of a
+// P_{i,j} iteration); the host launches it beside product_f64_kernel for those schemes and
+// exactly one of the two runs.
+__global__ __launch_bounds__(512, 2) void product_f64_dual_kernel(const SnfState* __restrict__ st,
+                                                                  const Buffers* __restrict__ bufs,
+                                                                  ProductGrid g) {
+  if (st->stop || st->prec != kPrecF64 || !st->dual) return;
+  product_body<double, kPrecF64, true>(st, bufs, g,
+                                       work_item(g, (int)(g.np / Mfma<double>::kBK)));
 }
 
 __global__ __launch_bounds__(512, 2) void product_f32_kernel(const SnfState* __restrict__ st,
@@ -601,8 +628,8 @@ __global__ __launch_bounds__(256) void split_fixup_kernel(const SnfState* __rest
   const int64_t gr = (int64_t)bi * kTile + r;
 #pragma unroll
   for (int v = 0; v < 4; ++v)
-    epi_elem(sum[v], gr, (int64_t)bj * kTile + c0 + v, g.sym, bi == bj, g.n, g.np, ea, e2, t1,
-             t2);
+    epi_elem<true>(sum[v], gr, (int64_t)bj * kTile + c0 + v, g.sym, bi == bj, g.n, g.np, ea,
+                   e2, t1, t2);
   write_partials(e2, t1, t2, g.partials, g.dp_tiles + blockIdx.x);
 }
 
@@ -650,6 +677,13 @@ void launch_product(int prec, SnfState* st, const Buffers* bufs_dev, const Produ
   }
 }
 
+void launch_product_dual(SnfState* st, const Buffers* bufs_dev, const ProductGrid& g,
+                         hipStream_t s) {
+  const int grid = g.dp_tiles + g.tail_tiles * g.split_s;
+  hipLaunchKernelGGL(product_f64_dual_kernel, dim3(grid), dim3(Layout<double>::NT), 0, s, st,
+                     bufs_dev, g);
+}
+
 void launch_split_fixup(SnfState* st, const Buffers* bufs_dev, const ProductGrid& g,
                         hipStream_t s) {
   if (g.tail_tiles == 0) return;
@@ -678,7 +712,13 @@ __device__ void decide(SnfState* s) {
 
   double a = 0.0;
   int br;
-  if (scheme == SNF_SP2_TRACE) {
+  s->dual = 0;
+  if (scheme_is_pij(scheme)) {
+    br = SNF_BRANCH_PIJ;
+    a = (scheme == SNF_SNF_FIXMU_PIJ)
+            ? sched::pij_alpha(s->pij_i, s->pij_j, s->xstar, s->beta, s->abar)
+            : 1.0;
+  } else if (scheme == SNF_SP2_TRACE) {
     br = sched::trace_square(s->t1, s->t2, (double)s->n_occ) ? SNF_BRANCH_SQUARE
                                                              : SNF_BRANCH_FOLD;
   } else if (scheme == SNF_TC2_BETA || scheme == SNF_SNF_VARMU) {
@@ -696,7 +736,19 @@ __device__ void decide(SnfState* s) {
   }
   s->branch = br;
   s->alpha = a;
-  if (br == SNF_BRANCH_P33 || br == SNF_BRANCH_P55) {
+  if (br == SNF_BRANCH_PIJ) {
+    // W = V^2, V = a (X - x* I): W = a^2 P - 2 a^2 x* X + a^2 x*^2 I; and beside it the top
+    // Horner level T = q_2h W + q_(2h-1) V + q_(2h-2) I in the same epilogue
+    const double xs = s->xstar, a2 = a * a;
+    const int h = (s->pij_i + s->pij_j) / 2;
+    const double qt = s->pq[2 * h], qo = s->pq[2 * h - 1], qc = s->pq[2 * h - 2];
+    s->c2 = a2;
+    s->c1 = -2.0 * a2 * xs;
+    s->c0 = a2 * xs * xs;
+    s->d2 = qt * a2;
+    s->d1 = qo * a - 2.0 * qt * a2 * xs;
+    s->d0 = qt * a2 * xs * xs - qo * a * xs + qc;
+  } else if (br == SNF_BRANCH_P33 || br == SNF_BRANCH_P55) {
     // W = (a (X - I/2))^2 = a^2 P - a^2 X + (a^2 / 4) I
     const double a2 = a * a;
     s->c2 = a2;
@@ -723,6 +775,12 @@ __device__ void decide(SnfState* s) {
     s->bw = (s->cur + 1) & 3;
     s->io = s->bw;
     s->horner_left = s->pmm_m - 1;
+  } else if (br == SNF_BRANCH_PIJ) {
+    s->bw = (s->cur + 1) & 3;
+    s->io = s->bw;
+    s->dual = 1;
+    s->io2 = s->bt = (s->cur + 2) & 3;
+    s->horner_left = (s->pij_i + s->pij_j) / 2 - 1;
   } else {
     s->io = (br == SNF_BRANCH_P11) ? 2 : 1 - s->cur;
   }
@@ -739,6 +797,13 @@ __device__ void advance_beta(SnfState* s, int br, double a) {
   } else if (br == SNF_BRANCH_P11) {
     s->beta = sched::alg1_beta_next(s->beta, a);
     s->betabar = 1.0 - s->beta;
+  } else if (br == SNF_BRANCH_PIJ) {
+    const double xs = s->xstar;
+    const double an = sched::pij_side_next(s->pij_i, s->pij_j, xs, s->beta, a);
+    const double bn = sched::pij_side_next(s->pij_j, s->pij_i, 1.0 - xs, s->abar, a);
+    s->beta = an;
+    s->abar = bn;
+    s->betabar = 1.0 - bn;
   } else {
     s->beta = sched::pmm_beta_next(s->pmm_m, s->beta, a);
     s->betabar = 1.0 - s->beta;
@@ -783,6 +848,38 @@ __device__ void pmm_next(SnfState* s) {
   s->c2 = s->alpha;
   s->c1 = -0.5 * s->alpha;
   s->c0 = 0.5;
+}
+
+// Set up the next product of a P_{i,j} iteration: P(x* + v) = x* + v Q(v), v = a (X - x* I),
+// W = v^2, Q(v) = sum_k (q_2k + q_(2k+1) v) W^k.  The first product gave W and the top level
+// T; then T <- T.W + q_(2k+1) V + q_2k I for k = h - 2 .. 0; then X_new = x* I + V T.
+__device__ void pij_next(SnfState* s) {
+#pragma clang fp contract(off)
+  const double a = s->alpha, xs = s->xstar;
+  const int ta = (s->cur + 2) & 3, tb = (s->cur + 3) & 3;
+  s->want_e = 0;
+  s->dual = 0;
+  if (s->horner_left > 0) {
+    const int k = s->horner_left - 1;
+    s->kind = kKindHorner;
+    s->ia = s->bt;
+    s->ib = s->bw;
+    s->ix = s->cur;
+    s->io = (s->bt == ta) ? tb : ta;
+    s->bt = s->io;
+    s->c2 = 1.0;
+    s->c1 = s->pq[2 * k + 1] * a;
+    s->c0 = s->pq[2 * k] - s->pq[2 * k + 1] * a * xs;
+    return;
+  }
+  // X_new = a X.T - a x* T + x* I, written over W
+  s->kind = kKindFinal;
+  s->ia = s->cur;
+  s->ib = s->ix = s->bt;
+  s->io = s->bw;
+  s->c2 = a;
+  s->c1 = -(a * xs);
+  s->c0 = xs;
 }
 
 __device__ void finish(SnfState* s, int status) {
@@ -850,6 +947,10 @@ __device__ void schedule_body(SnfState* __restrict__ s, const double* __restrict
       pmm_next(s);
       return;
     }
+    if (s->pij_i) {
+      pij_next(s);
+      return;
+    }
     if (s->branch == SNF_BRANCH_P11) {
       // second product of Algorithm 1: R = S2.X; X_new = (3 - 2c) S2 - 2 a R
       const double a = s->alpha, c = 0.5 * (1.0 - a);
@@ -872,7 +973,7 @@ __device__ void schedule_body(SnfState* __restrict__ s, const double* __restrict
     decide(s);
   } else if (s->kind == kKindHorner) {
     s->horner_left -= 1;
-    pmm_next(s);
+    if (s->pij_i) pij_next(s); else pmm_next(s);
   } else {                                  // kKindCube or kKindFinal: X_new is complete
     advance_beta(s, s->branch, s->alpha);
     s->iter += 1;

@@ -110,6 +110,113 @@ __host__ __device__ inline double pmm_beta_next(int m, double beta, double alpha
   return pmm_eval(m, alpha * (beta - 0.5) + 0.5);
 }
 
+// ---- P_{i,j}, i and j odd: scale-and-fold about the unstable fixed point x* -------------
+//
+// X_0 = (mu I - F) / gamma + x* I puts mu on x*; the unoccupied part of the spectrum then
+// lies in [0, a], the occupied part in [1 - a', 1].  f_i(X) = P(alpha (X - x* I) + x* I).
+// Each side has its own form of Eq. 3 (the folded image of its interval end equals the image
+// of its gap edge; that alpha minimises the side's new bound), and alpha is the smaller of
+// the two.  The occupied side is the unoccupied side of the mirrored polynomial:
+// 1 - P_{i,j}(1 - y) = P_{j,i}(y), whose fixed point is 1 - x*.
+constexpr int kPijMax = 5;                 // i, j in {1, 3, 5}
+constexpr int kPijQ = 2 * kPijMax + 1;     // coefficients of Q, degree i + j
+
+// P_{i,j}(x) = x^(i+1) sum_{k=0..j} C(i+k, k) (1-x)^k, Horner's rule in y = 1 - x; accurate
+// relative to its value near 0 and for x < 0 (every term positive there).
+__host__ __device__ inline double pij_eval(int i, int j, double x) {
+#pragma clang fp contract(off)
+  const double y = 1.0 - x;
+  double acc = 0.0;
+  for (int k = j; k >= 0; --k) {
+    int64_t c = 1;                           // C(i+k, k)
+    for (int t = 1; t <= k; ++t) c = c * (i + t) / t;
+    acc = acc * y + (double)c;
+  }
+  double xp = x;
+  for (int t = 0; t < i; ++t) xp = xp * x;
+  return xp * acc;
+}
+
+// The root of P(x) = x inside (0, 1): P(x) - x is negative above 0 and positive below 1 and
+// P is S-shaped, so the root is unique; bisection until the bracket stops shrinking.
+__host__ __device__ inline double pij_xstar(int i, int j) {
+#pragma clang fp contract(off)
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 1100; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    const double g = pij_eval(i, j, mid) - mid;
+    if (g == 0.0) return mid;
+    if (g < 0.0) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// gamma = max((mu - lambda_min) / (1 - x*), (lambda_max - mu) / x*): the spectrum of X_0
+// fills [0, 1]
+__host__ __device__ inline double pij_gamma(double lmin, double lmax, double mu, double xs) {
+#pragma clang fp contract(off)
+  const double a = (mu - lmin) / (1.0 - xs), b = (lmax - mu) / xs;
+  return a > b ? a : b;
+}
+
+// One side's Eq. 3: the root alpha >= 1 of P(x* (1 - alpha)) = P(x* - alpha (x* - a)), for
+// 0 < a < x*.  The difference is -P(a) < 0 at alpha = 1 and positive where the scaled edge
+// reaches 0 (alpha = x* / (x* - a)); P falls on x < 0 and rises on [0, x*], so bisection
+// converges to the unique root.  Outside (0, x*): 1.
+__host__ __device__ inline double pij_alpha_side(int i, int j, double xs, double a) {
+#pragma clang fp contract(off)
+  if (!(a > 0.0 && a < xs)) return 1.0;
+  double lo = 1.0, hi = xs / (xs - a);
+  for (int it = 0; it < 2200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    const double g = pij_eval(i, j, xs * (1.0 - mid)) - pij_eval(i, j, xs - mid * (xs - a));
+    if (g < 0.0) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__host__ __device__ inline double pij_alpha(int i, int j, double xs, double a, double abar) {
+  const double lo = pij_alpha_side(i, j, xs, a);
+  const double hi = pij_alpha_side(j, i, 1.0 - xs, abar);
+  return lo < hi ? lo : hi;
+}
+
+// New bound of one side: the larger image of its interval end and of its gap edge.
+__host__ __device__ inline double pij_side_next(int i, int j, double xs, double a,
+                                                double alpha) {
+#pragma clang fp contract(off)
+  const double u = pij_eval(i, j, xs * (1.0 - alpha));
+  const double v = pij_eval(i, j, xs - alpha * (xs - a));
+  return u > v ? u : v;
+}
+
+// Q(v) = (P(x* + v) - x*) / v = sum_k q_k v^k, k = 0..i+j, from P' = C x^i (1-x)^j with
+// C = (i+j+1)! / (i! j!): q_k = P^(k+1)(x*) / (k+1)! = C / (k+1) [v^k] (x*+v)^i (1-x*-v)^j.
+__host__ __device__ inline void pij_taylor(int i, int j, double xs, double* q) {
+#pragma clang fp contract(off)
+  double cc = 1.0;                           // C = (i+j+1)! / (i! j!) = (i+j+1) C(i+j, i)
+  for (int t = 1; t <= i; ++t) cc = cc * (double)(j + t) / (double)t;
+  cc = cc * (double)(i + j + 1);
+  const double xm = 1.0 - xs;
+  for (int k = 0; k <= i + j; ++k) {
+    double sum = 0.0;
+    for (int l = 0; l <= i && l <= k; ++l) {
+      const int r = k - l;
+      if (r > j) continue;
+      double bi = 1.0, bj = 1.0;
+      for (int t = 0; t < l; ++t) bi = bi * (double)(i - t) / (double)(t + 1);
+      for (int t = 0; t < r; ++t) bj = bj * (double)(j - t) / (double)(t + 1);
+      double term = bi * bj;
+      for (int t = 0; t < i - l; ++t) term = term * xs;
+      for (int t = 0; t < j - r; ++t) term = term * xm;
+      sum = (r & 1) ? sum - term : sum + term;
+    }
+    q[k] = cc / (double)(k + 1) * sum;
+  }
+}
+
 // ---- Algorithm 2 (P_{0,1} & P_{1,0} varying-mu purification) ---------------------------
 
 // f0(lambda) = (lambda_max - lambda) / (lambda_max - lambda_min)

@@ -537,7 +537,8 @@ int snf_serve_submit(snf_server* sv, const double* F_host, int64_t n, const snf_
                      uint64_t* ticket) {
   if (!sv || !F_host || !D_host_out || !ticket) return SNF_EINVAL;
   int rc = validate(n, params, scheme, precision);
-  if (rc == SNF_OK && scheme_pmm_m(scheme)) rc = SNF_EINVAL;   // three buffers per request
+  if (rc == SNF_OK && (scheme_pmm_m(scheme) || scheme_is_pij(scheme)))
+    rc = SNF_EINVAL;   // three buffers per request
   if (rc != SNF_OK) return rc;
   ServeRequest* r = new_request(sv, n, params, scheme, precision);
   r->D_host = D_host_out;
@@ -562,7 +563,8 @@ int snf_serve_submit_device(snf_server* sv, const double* F_dev, int64_t n,
   if (!sv || !F_dev || !D_dev_out || !ticket || (const void*)F_dev == (const void*)D_dev_out)
     return SNF_EINVAL;
   int rc = validate(n, params, scheme, precision);
-  if (rc == SNF_OK && scheme_pmm_m(scheme)) rc = SNF_EINVAL;   // three buffers per request
+  if (rc == SNF_OK && (scheme_pmm_m(scheme) || scheme_is_pij(scheme)))
+    rc = SNF_EINVAL;   // three buffers per request
   if (rc != SNF_OK) return rc;
   ServeRequest* r = new_request(sv, n, params, scheme, precision);
   r->device_io = true;

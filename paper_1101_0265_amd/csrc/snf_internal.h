@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/snf.h"
+#include "schedule_math.h"
 
 namespace snf {
 
@@ -25,8 +26,10 @@ enum : int32_t { kPhaseHigh = 0, kPhaseLow = 1, kPhaseRefine = 2 };
 enum : int32_t {
   kKindSquare = 0,   // P = X.X, epilogue Y = c2 P + c1 X + c0 I, idempotency of X checked
   kKindCube = 1,     // Algorithm 1 second product: R = S2.X, Y = c2 R + c1 S2
-  kKindHorner = 2,   // P_{m,m} schemes: T <- W.T + r_k I (or the first level from W.W)
-  kKindFinal = 3     // P_{m,m} schemes: X_new = a X.T0 - (a/2) T0 + I/2
+  kKindHorner = 2,   // P_{m,m}: T <- W.T + r_k I (or the first level from W.W);
+                     // P_{i,j}: T <- T.W + c1 X + c0 I
+  kKindFinal = 3     // P_{m,m}: X_new = a X.T0 - (a/2) T0 + I/2;
+                     // P_{i,j}: X_new = a X.T0 - a x* T0 + x* I
 };
 
 // m of a P_{m,m} scheme (3 or 5), 0 for the other schemes.
@@ -35,10 +38,16 @@ inline __host__ __device__ int scheme_pmm_m(int scheme) {
        : (scheme == SNF_SNF_FIXMU5 || scheme == SNF_PMM5) ? 5 : 0;
 }
 
-// Matrix products one f_i costs.
-inline int products_per_iteration(int scheme) {
+// The P_{i,j} schemes (i, j from snf_params).
+inline __host__ __device__ bool scheme_is_pij(int scheme) {
+  return scheme == SNF_SNF_FIXMU_PIJ || scheme == SNF_PIJ;
+}
+
+// Matrix products one f_i costs (pi, pj: the P_{i,j} schemes' polynomial).
+inline int products_per_iteration(int scheme, int pi = 0, int pj = 0) {
   const int m = scheme_pmm_m(scheme);
   if (m) return m + 1;
+  if (scheme_is_pij(scheme)) return (pi + pj) / 2 + 1;
   return (scheme == SNF_MCWEENY || scheme == SNF_SNF_FIXMU) ? 2 : 1;
 }
 
@@ -73,7 +82,14 @@ struct SnfState {
   int32_t ia, ib, ix, io; // operand / linear-term / output buffer indices of the pending product
   int32_t pmm_m;          // m of a P_{m,m} scheme, else 0
   int32_t horner_left;    // P_{m,m}: Horner products still to run in this iteration
-  int32_t bw, bt;         // P_{m,m}: buffers holding W = (a (X - I/2))^2 and the last T
+  int32_t bw, bt;         // P_{m,m}, P_{i,j}: buffers holding W and the last Horner T
+  int32_t pij_i, pij_j;   // P_{i,j} schemes: the polynomial, else 0
+  double xstar;           // fixed-mu schemes: image of mu in X_0 (1/2, or x* of P_{i,j})
+  double abar;            // P_{i,j}: distance of the occupied part's lower bound from 1
+  double pq[sched::kPijQ];  // P_{i,j}: P(x* + v) = x* + v sum_k pq[k] v^k
+  int32_t dual;           // pending product also writes Y2 = d2 P + d1 X + d0 I to x[io2]
+  int32_t io2;
+  double d2, d1, d0;
   int32_t want_e;         // pending product checks idempotency of its A operand
   int32_t write_lowp;     // epilogue also writes the low-precision operand copy
   int32_t nlog;
@@ -119,6 +135,10 @@ constexpr int kSplitCap = 512;   // slices held by the split buffer (64*256 doub
 // precision (so the host can enqueue all variants without knowing the device's choice).
 void launch_product(int prec, SnfState* st, const Buffers* bufs_dev, const ProductGrid& g,
                     hipStream_t s);
+// FP64 product with the second epilogue output (P_{i,j} schemes: launched beside
+// launch_product(kPrecF64, ...); exactly one of the two runs, as the state asks).
+void launch_product_dual(SnfState* st, const Buffers* bufs_dev, const ProductGrid& g,
+                         hipStream_t s);
 void launch_split_fixup(SnfState* st, const Buffers* bufs_dev, const ProductGrid& g,
                         hipStream_t s);
 void launch_copy_out(const SnfState* st, const Buffers* bufs_dev, int64_t n, int64_t np,

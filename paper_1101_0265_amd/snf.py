@@ -22,9 +22,9 @@ STATUS_NAMES = {OK: "ok", PENDING: "pending", OK_FLOOR: "ok_floor", EINVAL: "ein
                 EDEVICE: "edevice"}
 
 SCHEMES = {"sp2": 0, "tc2": 1, "snf_varmu": 2, "mcweeny": 3, "snf_fixmu": 4,
-           "snf_fixmu3": 5, "snf_fixmu5": 6, "pmm3": 7, "pmm5": 8}
+           "snf_fixmu3": 5, "snf_fixmu5": 6, "pmm3": 7, "pmm5": 8, "snf_pij": 9, "pij": 10}
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_ref64": 2, "bf16_ref64": 3}
-BRANCH_LETTERS = {0: "S", 1: "F", 2: "M", 3: "3", 4: "5"}
+BRANCH_LETTERS = {0: "S", 1: "F", 2: "M", 3: "3", 4: "5", 5: "P"}
 LOG_MAX = 256
 FLAG_TIME_PRODUCTS = 1
 FLAG_TRUNC_ERROR_CONTROL = 2
@@ -36,7 +36,8 @@ class Params(ctypes.Structure):
                 ("homo", ctypes.c_double), ("lumo", ctypes.c_double),
                 ("n_occ", ctypes.c_int64), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("gap_switch", ctypes.c_double), ("lowp_floor", ctypes.c_double)]
+                ("gap_switch", ctypes.c_double), ("lowp_floor", ctypes.c_double),
+                ("poly_i", ctypes.c_int32), ("poly_j", ctypes.c_int32)]
 
 
 class LogRec(ctypes.Structure):
@@ -151,14 +152,15 @@ def _check_dense(t, name):
 
 def make_params(*, lambda_min, lambda_max, mu=float("nan"), xi=float("nan"),
                 homo=float("nan"), lumo=float("nan"), n_occ=-1, tol=1e-10, max_iter=200,
-                flags=0, gap_switch=0.0, lowp_floor=0.0) -> Params:
+                flags=0, gap_switch=0.0, lowp_floor=0.0, poly_ij=None) -> Params:
     return Params(float(lambda_min), float(lambda_max),
                   float("nan") if mu is None else float(mu),
                   float("nan") if xi is None else float(xi),
                   float("nan") if homo is None else float(homo),
                   float("nan") if lumo is None else float(lumo),
                   -1 if n_occ is None else int(n_occ), float(tol), int(max_iter), int(flags),
-                  float(gap_switch), float(lowp_floor))
+                  float(gap_switch), float(lowp_floor),
+                  int(poly_ij[0]) if poly_ij else 0, int(poly_ij[1]) if poly_ij else 0)
 
 
 def result_dict(res: Result, log_arr=None) -> dict:
@@ -185,7 +187,8 @@ def purify_dense(F, scheme: str = "snf_varmu", precision: str = "fp64", *, out=N
     """Purify the symmetric float64 CUDA tensor ``F``.  Returns (D, result-dict).
 
     ``params``: lambda_min, lambda_max, and per scheme mu/xi (fixed-mu), homo/lumo
-    (varying-mu), n_occ, tol, max_iter, flags, gap_switch, lowp_floor (see snf_params).
+    (varying-mu), n_occ, tol, max_iter, flags, gap_switch, lowp_floor, poly_ij = (i, j) for
+    the P_{i,j} schemes (see snf_params).
     """
     import torch
     _check_dense(F, "F")

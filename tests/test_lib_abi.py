@@ -11,6 +11,8 @@ import pytest
 
 from paper_1101_0265_amd import build_lib
 
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
 
 @pytest.fixture(scope="module")
 def lib():
@@ -45,9 +47,42 @@ def test_host_only_entry_points(lib):
 def test_binding_structs_match_header():
     """Field layout of the ctypes mirrors against the sizes the header implies."""
     from paper_1101_0265_amd import snf
-    assert ctypes.sizeof(snf.Params) == 6 * 8 + 8 + 8 + 4 + 4 + 8 + 8
+    assert ctypes.sizeof(snf.Params) == 6 * 8 + 8 + 8 + 4 + 4 + 8 + 8 + 4 + 4
     assert ctypes.sizeof(snf.LogRec) == 4 * 4 + 6 * 8
     assert ctypes.sizeof(snf.Result) == 6 * 4 + 8 * 8 + snf.LOG_MAX + 8 + 8
+
+
+def test_binding_offsets_match_compiled_header(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors against what a C compiler
+    makes of include/snf.h."""
+    import shutil
+    import subprocess
+    from paper_1101_0265_amd import snf
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"snf_params": snf.Params, "snf_log_rec": snf.LogRec, "snf_result": snf.Result,
+               "snf_bsr": snf.Bsr}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "snf.h"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        cname, key, val = line.split()
+        got[(cname, key)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
