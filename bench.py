@@ -216,6 +216,82 @@ def run_precision(args):
     return line
 
 
+def run_fixmu(args):
+    """n = 4096, spectrum in [-1, 1] with a 0.01 gap centred at mu = -0.5 (a quarter of the
+    way up; N_occ = 1024), Haar Q: the fixed-mu schemes -- Algorithm 1 (P_{1,1}), P_{m,m},
+    and P_{i,j} (i != j) scaled about its fixed point x* -- and their alpha = 1 forms."""
+    import numpy as np
+    import torch
+    from paper_1101_0265_amd import hamiltonians as H
+    from paper_1101_0265_amd import snf
+    n, mu, gap = 4096, -0.5, 0.01
+    n_occ = int(round(n * (mu + 1.0) / 2.0))
+    lam = H.two_interval_spectrum(n_occ, n - n_occ, -1.0, mu - gap / 2, mu + gap / 2, 1.0,
+                                  np.random.default_rng(11))
+    F, Q = H.rotated_spectrum_torch(lam, seed=11)
+    qo = Q[:, :n_occ].contiguous()
+    D_exact = qo @ qo.T
+    del Q, qo
+    D = torch.empty_like(F)
+    kw = dict(lambda_min=-1.0, lambda_max=1.0, n_occ=n_occ, mu=mu, xi=gap, tol=1e-8,
+              max_iter=120, flags=snf.FLAG_TIME_PRODUCTS)
+    runs = [("snf_fixmu", None), ("mcweeny", None), ("snf_fixmu3", None), ("snf_fixmu5", None),
+            ("snf_pij", (3, 1)), ("snf_pij", (1, 3)), ("snf_pij", (5, 1)), ("snf_pij", (1, 5)),
+            ("snf_pij", (5, 3)), ("snf_pij", (3, 5)), ("pij", (3, 1)), ("pij", (1, 3))]
+    flops_one = float(n) * n * (n + 1)
+    out = {}
+    for scheme, pij in runs:
+        name = scheme + ("" if pij is None else f"{pij[0]}{pij[1]}")
+        snf.purify_dense(F, scheme, out=D, want_log=False, poly_ij=pij, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = max(1, args.steps)
+        for _ in range(steps):
+            _, r = snf.purify_dense(F, scheme, out=D, want_log=False, poly_ij=pij, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        out[name] = dict(ms=round(ms, 2), status=r["status"], products=r["products"],
+                         iterations=r["iterations"], idem_err=r["idem_err"],
+                         trace_err=r["trace_err"],
+                         dist_to_exact_D=float(torch.linalg.norm(D - D_exact)),
+                         product_ms=round(r["product_ms"], 2),
+                         product_tflops=round(r["products"] * flops_one / r["product_ms"] / 1e9,
+                                              2))
+    base = out["snf_pij31"]
+    line = _base_line("time-to-solution ms at ‖X²−X‖≤1e-8, fixed-mu schemes, mu off-centre "
+                      "(n=4096)", base["ms"], "ms", args, False, "f64",
+                      {"workload": "dense FP64 n=4096, Haar Q (seed 11), spectrum uniform in "
+                                   "[-1,1] with a 0.01 gap centred at mu=-0.5, N_occ=1024, "
+                                   "tol 1e-8"})
+    line["ms_per_step"] = base["ms"]
+    line["runs"] = out
+    line["speedup_vs_mcweeny"] = round(out["mcweeny"]["ms"] / base["ms"], 3)
+    achieved = base["product_tflops"]
+    line["roofline"] = dict(bound="mfma", achieved=achieved, peak=78.6, unit="TFLOP/s",
+                            frac=round(achieved / 78.6, 4), traffic=None,
+                            kernel="product_f64_kernel and product_f64_dual_kernel (P_{3,1})",
+                            note="n^2 (n+1) flops per product over the summed HIP-event time "
+                                 "of the product launches of one solve")
+    line["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        # one iteration of the oracle on the same F (the check X^2 and the four Horner
+        # products of P_{3,1} in X_s), scaled to the solve's iterations
+        from oracle import dense
+        Fh = F.cpu().numpy()
+        okw = dict(lambda_min=-1.0, lambda_max=1.0, n_occ=n_occ, mu=mu, xi=gap)
+        t0 = time.perf_counter()
+        dense.purify(Fh, "snf_pij", tol=1e-300, max_iter=1, poly_ij=(3, 1), **okw)
+        dt = time.perf_counter() - t0
+        its = base["iterations"]
+        line["cpu_baseline"] = dict(
+            value=round(dt * 1e3 * (5 * its + 1) / 6, 1), unit="ms", cores=int(_blas_threads()),
+            kind="oracle",
+            sample=f"one iteration of the FP64 oracle on the same n=4096 F (6 dense products: "
+                   f"2 checks, 4 Horner steps; {dt:.1f} s), scaled to the solve's "
+                   f"{5 * its + 1} ({its} iterations of check + 4 steps, one certifying check)")
+    return line
+
+
 def run_bounds(args):
     """n = 4096 lattice: bounds estimated on the device (Lanczos, 40 steps) instead of given.
     The trace scheme with estimated extremal bounds, gap bounds from its D, then scale-and-fold
@@ -552,10 +628,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="dense",
-                    choices=["dense", "small", "bsr", "serve", "precision", "bounds"],
+                    choices=["dense", "small", "bsr", "serve", "precision", "bounds",
+                             "fixmu"],
                     help="dense: n=4096 lattice (default line); small: n=256 gap-0.05 latency "
                          "of all five schemes; bsr: block-sparse 32^3-site lattice n=65536; "
-                         "serve: 512-request continuous-batching trace")
+                         "serve: 512-request continuous-batching trace; precision: n=8192 "
+                         "FP64 vs FP32/BF16 products; bounds: device-estimated bounds; fixmu: "
+                         "fixed-mu schemes incl. P_{i,j} with mu off-centre, n=4096")
     ap.add_argument("--bsr-sweep", action="store_true",
                     help="with --workload bsr: one solve per (scheme, truncation threshold) of "
                          "the sweep, one JSON line each")
@@ -585,7 +664,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload != "dense":
         line = {"small": run_small, "bsr": run_bsr, "serve": run_serve,
-                "precision": run_precision, "bounds": run_bounds}[args.workload](args)
+                "precision": run_precision, "bounds": run_bounds,
+                "fixmu": run_fixmu}[args.workload](args)
         print(json.dumps(line), flush=True)
         return
     h = H.lattice_hamiltonian(LATTICE, seed=2)
