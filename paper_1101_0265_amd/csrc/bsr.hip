@@ -191,7 +191,11 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
   const int TI = packed >> 16, TJ = packed & 0xFFFF;
   const int W = g.W, nb = g.nb;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
+  // waves w and w + 4 share a SIMD (waves go to the SIMDs in turn): give them opposite A
+  // rows (0/3, 1/2) and opposite B pairs, so a stage whose blocks are present on one side of
+  // the super-tile only still spreads its MFMAs over all four SIMDs
+  const int wr = wid < 4 ? (wid >> 1) : 3 - ((wid - 4) >> 1);
+  const int wc = wid < 4 ? (wid & 1) : 1 - ((wid - 4) & 1);
   const int ci0 = kSup * TI, cj0 = kSup * TJ;   // first block column of the A / B panels
 
   // 8 waves: wave (wr, wc) holds A block row wr (32 rows) against B blocks 2 wc, 2 wc + 1
@@ -204,9 +208,9 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
   // Threads 0-255 move the A panel, 256-511 the B panel: one 16-byte piece of each of the 4
   // blocks of their side, block row k = t / 8, columns 4 (t % 8) .. +3 (t = tid mod 256).
   const int side = tid >> 8, lk = (tid & 255) >> 3, lc = (tid & 7) * 4;
-  u32x4 rv[kSup];
-  uint32_t pres = 0;   // presence of the stage's blocks: bits 0-3 A panel, 4-7 B panel
-  auto gload = [&](int s) {
+  u32x4 rA[kSup], rB[kSup];
+  uint32_t pA = 0, pB = 0;   // presence of the stage's blocks: bits 0-3 A panel, 4-7 B panel
+  auto gload = [&](int s, u32x4 (&rv)[kSup], uint32_t& pres) {
     // the 4 panel columns of each side share one bitmap word of block row K
     const uint32_t wa = kwa[s], wb = kwb[s];
     pres = ((wa >> (ci0 & 31)) & 0xFu) | (((wb >> (cj0 & 31)) & 0xFu) << 4);
@@ -220,7 +224,7 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
                          : u32x4{0, 0, 0, 0};
     }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int buf, const u32x4 (&rv)[kSup], uint32_t pres) {
     float(*dst)[kBsrLdsW] = side ? sB[buf] : sA[buf];
 #pragma unroll
     for (int a = 0; a < kSup; ++a) *(u32x4*)(&dst[lk][a * kB + lc]) = rv[a];
@@ -228,6 +232,34 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
   };
 
   const int fr = lane & 15, fk = lane >> 4;
+  auto compute = [&](int buf) {
+    // this wave's A block (row wr) and two B blocks; absent blocks are zero, so their
+    // MFMAs are skipped (the test is uniform across the wave)
+    const uint32_t pm = spres[buf];
+    const bool pa = (pm >> wr) & 1u;
+    const bool pb0 = (pm >> (4 + 2 * wc)) & 1u, pb1 = (pm >> (4 + 2 * wc + 1)) & 1u;
+    if (pa && (pb0 || pb1)) {
+#pragma unroll
+      for (int kk = 0; kk < kB; kk += 4) {
+        float a[2], b[4];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) a[m] = sA[buf][kk + fk][wr * kB + m * 16 + fr];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = sB[buf][kk + fk][wc * 64 + q * 16 + fr];
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          if (!(bj ? pb1 : pb0)) continue;
+#pragma unroll
+          for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int qq = 0; qq < 2; ++qq) {
+              const int q = 2 * bj + qq;
+              acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], b[q], acc[m][q], 0, 0, 0);
+            }
+        }
+      }
+    }
+  };
   // k-stages: block columns K present in both (rows I_a) and (rows J_b), taken in chunks
   // of kChunkWords bitmap words
   for (int w0 = 0; w0 < W; w0 += kChunkWords) {
@@ -274,40 +306,21 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
     }
     __syncthreads();
     if (nk == 0) continue;
-    gload(0);
-    lstore(0);
+    // two stages in flight in registers: stage s in LDS buffer s & 1, s + 1 loaded into
+    // registers, s + 2 being loaded
+    gload(0, rA, pA);
+    if (nk > 1) gload(1, rB, pB);
+    lstore(0, rA, pA);
     __syncthreads();
-    for (int s = 0; s < nk; ++s) {
-      const int buf = s & 1;
-      const bool more = s + 1 < nk;
-      if (more) gload(s + 1);
-      // this wave's A block (row wr) and two B blocks; absent blocks are zero, so their
-      // MFMAs are skipped (the test is uniform across the wave)
-      const uint32_t pm = spres[buf];
-      const bool pa = (pm >> wr) & 1u;
-      const bool pb0 = (pm >> (4 + 2 * wc)) & 1u, pb1 = (pm >> (4 + 2 * wc + 1)) & 1u;
-      if (pa && (pb0 || pb1)) {
-#pragma unroll
-        for (int kk = 0; kk < kB; kk += 4) {
-          float a[2], b[4];
-#pragma unroll
-          for (int m = 0; m < 2; ++m) a[m] = sA[buf][kk + fk][wr * kB + m * 16 + fr];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) b[q] = sB[buf][kk + fk][wc * 64 + q * 16 + fr];
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj) {
-            if (!(bj ? pb1 : pb0)) continue;
-#pragma unroll
-            for (int m = 0; m < 2; ++m)
-#pragma unroll
-              for (int qq = 0; qq < 2; ++qq) {
-                const int q = 2 * bj + qq;
-                acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], b[q], acc[m][q], 0, 0, 0);
-              }
-          }
-        }
-      }
-      if (more) lstore(buf ^ 1);
+    for (int s = 0; s < nk; s += 2) {
+      if (s + 2 < nk) gload(s + 2, rA, pA);
+      compute(0);
+      if (s + 1 < nk) lstore(1, rB, pB);
+      __syncthreads();
+      if (s + 1 >= nk) break;
+      if (s + 3 < nk) gload(s + 3, rB, pB);
+      compute(1);
+      if (s + 2 < nk) lstore(0, rA, pA);
       __syncthreads();
     }
   }
