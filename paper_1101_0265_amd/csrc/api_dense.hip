@@ -399,6 +399,9 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
   const int chunk = np >= 2048 ? 2 : (np >= 1024 ? 4 : 8);
   const bool lowp = precision != SNF_P_FP64;
   const bool pij = scheme_is_pij(scheme);
+  // small orders in FP64: 32x32 tiles with the k range split inside the workgroup
+  const bool small = !lowp && !pij && np <= kSmallMaxNp;
+  const SmallGrid sgrid = make_small_grid(np, n, w->partials);
   int enq = 0, chunks = 0, checked = 0;
   int ev_used = 0;
   bool stopped = false;
@@ -406,13 +409,17 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
   auto enqueue_chunk = [&]() -> int {
     for (int k = 0; k < chunk && enq < max_steps; ++k, ++enq) {
       if (time_products) SNF_HIP(hipEventRecord(w->prod_ev[ev_used], s));
-      launch_product(kPrecF64, w->state, w->bufs_dev, grid, s);
-      if (pij) launch_product_dual(w->state, w->bufs_dev, grid, s);
-      if (lowp) launch_product(lowp_kind_for(precision), w->state, w->bufs_dev, grid, s);
-      launch_split_fixup(w->state, w->bufs_dev, grid, s);
+      if (small) {
+        launch_product_small(w->state, w->bufs_dev, sgrid, s);
+      } else {
+        launch_product(kPrecF64, w->state, w->bufs_dev, grid, s);
+        if (pij) launch_product_dual(w->state, w->bufs_dev, grid, s);
+        if (lowp) launch_product(lowp_kind_for(precision), w->state, w->bufs_dev, grid, s);
+        launch_split_fixup(w->state, w->bufs_dev, grid, s);
+      }
       if (time_products) SNF_HIP(hipEventRecord(w->prod_ev[ev_used + 1], s));
       if (time_products) ev_used += 2;
-      launch_schedule(w->state, w->partials, grid.partial_count, 0, s);
+      launch_schedule(w->state, w->partials, small ? sgrid.tiles : grid.partial_count, 0, s);
     }
     SNF_HIP(hipGetLastError());
     SNF_HIP(hipMemcpyAsync((void*)(flags + (chunks & 1)), &w->state->stop, sizeof(int32_t),

@@ -472,6 +472,119 @@ __device__ __forceinline__ void product_body(const SnfState* __restrict__ st,
 }
 
 // ---------------------------------------------------------------------------------------
+// Small orders: FP64 product in 32x32 output tiles with the k range split over the four
+// waves of a workgroup and summed in LDS, so a step needs no split fix-up launch (at
+// n = 256 the 128x128 engine has 3 tiles, which it splits 16 ways and then fixes up).
+// Wave w sums k in [w np/4, (w + 1) np/4) in chunks of 32; in MFMA step s of a chunk the lane
+// group g = l / 16 takes k = chunk + 8 g + s, so each lane reads 8 consecutive values of a
+// row (operands are symmetric: row j of B is column j).  The four partial tiles are added
+// in wave order, then the shared epilogue runs on 4 entries per thread.
+// ---------------------------------------------------------------------------------------
+constexpr int kSmallTile = 32;
+constexpr int kSmallThreads = 256;
+
+__global__ __launch_bounds__(kSmallThreads) void product_f64_small_kernel(
+    const SnfState* __restrict__ st, const Buffers* __restrict__ bufs, SmallGrid g) {
+  if (st->stop || st->prec != kPrecF64 || st->dual) return;
+  __shared__ double part[4][kSmallTile][kSmallTile + 1];
+  const int64_t np = g.np;
+  const double* A = bufs->x[st->ia];
+  const double* B = bufs->x[st->ib];
+  int bi, bj;
+  tile_coords(blockIdx.x, (int)(np / kSmallTile), 1, bi, bj);
+  const int64_t i0 = (int64_t)bi * kSmallTile, j0 = (int64_t)bj * kSmallTile;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int64_t kw0 = (int64_t)wid * (np / 4), kw1 = kw0 + np / 4;
+
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[m][q] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  // chunk registers: rows m (A) and q (B), 8 consecutive k values each (4 x 16 bytes); two
+  // sets, so the next chunk's loads are in flight while this one's MFMAs run
+  u32x4 ra0[2][4], rb0[2][4], ra1[2][4], rb1[2][4];
+  auto gload = [&](int64_t kc, u32x4 (&ra)[2][4], u32x4 (&rb)[2][4]) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const double* pa = A + (i0 + m * 16 + fr) * np + kc + fg * 8;
+      const double* pb = B + (j0 + m * 16 + fr) * np + kc + fg * 8;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        ra[m][v] = gload16(pa + 2 * v);
+        rb[m][v] = gload16(pb + 2 * v);
+      }
+    }
+  };
+  auto compute = [&](const u32x4 (&ra)[2][4], const u32x4 (&rb)[2][4]) {
+    double a[2][8], b[2][8];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double2 da = __builtin_bit_cast(double2, ra[m][v]);
+        const double2 db = __builtin_bit_cast(double2, rb[m][v]);
+        a[m][2 * v] = da.x;
+        a[m][2 * v + 1] = da.y;
+        b[m][2 * v] = db.x;
+        b[m][2 * v + 1] = db.y;
+      }
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m][s], b[q][s], acc[m][q], 0, 0, 0);
+  };
+  // the wave's range is a multiple of 32 (np is a multiple of 128)
+  gload(kw0, ra0, rb0);
+  for (int64_t kc = kw0; kc < kw1; kc += 64) {
+    if (kc + 32 < kw1) gload(kc + 32, ra1, rb1);
+    compute(ra0, rb0);
+    if (kc + 64 < kw1) gload(kc + 64, ra0, rb0);
+    if (kc + 32 < kw1) compute(ra1, rb1);
+  }
+  // accumulator of lane l, register v: row (l / 16) + 4 v, column l % 16 of block (m, q)
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        part[wid][m * 16 + fg + 4 * v][q * 16 + fr] = acc[m][q][v];
+  __syncthreads();
+  const EpiArgs ea = epi_args(st, bufs);
+  double e2 = 0.0, t1 = 0.0, t2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int idx = e * kSmallThreads + tid;
+    const int r = idx / kSmallTile, c = idx % kSmallTile;
+    const double p = ((part[0][r][c] + part[1][r][c]) + part[2][r][c]) + part[3][r][c];
+    epi_elem(p, i0 + r, j0 + c, 1, bi == bj, g.n, np, ea, e2, t1, t2);
+  }
+  write_partials(e2, t1, t2, g.partials, blockIdx.x);
+}
+
+SmallGrid make_small_grid(int64_t np, int64_t n, double* partials) {
+  SmallGrid g;
+  g.np = np;
+  g.n = n;
+  g.partials = partials;
+  const int nt = (int)(np / kSmallTile);
+  g.tiles = nt * (nt + 1) / 2;
+  return g;
+}
+
+void launch_product_small(SnfState* st, const Buffers* bufs_dev, const SmallGrid& g,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(product_f64_small_kernel, dim3(g.tiles), dim3(kSmallThreads), 0, s, st,
+                     bufs_dev, g);
+}
+
+// ---------------------------------------------------------------------------------------
 // Product kernel, bf16 MFMA 16x16x32 with f32 accumulation.
 //   Here the LDS tiles are 'row panels' with k contiguous: sA[i][k] = A[i0+i][k0+k] and
 //   sB[j][k] = B[j0+j][k0+k] (B[k][j] = B[j][k] by symmetry), because a lane's MFMA operand

@@ -135,6 +135,17 @@ constexpr int kSplitCap = 512;   // slices held by the split buffer (64*256 doub
 // precision (so the host can enqueue all variants without knowing the device's choice).
 void launch_product(int prec, SnfState* st, const Buffers* bufs_dev, const ProductGrid& g,
                     hipStream_t s);
+// Small orders: FP64 product in 32x32 tiles of the upper triangle, k split over the four
+// waves of a workgroup and summed in LDS (no split fix-up); one partial slot per tile.
+constexpr int64_t kSmallMaxNp = 896;   // padded orders that take this path (FP64 mode)
+struct SmallGrid {
+  int64_t np, n;
+  int tiles;
+  double* partials;
+};
+SmallGrid make_small_grid(int64_t np, int64_t n, double* partials);
+void launch_product_small(SnfState* st, const Buffers* bufs_dev, const SmallGrid& g,
+                          hipStream_t s);
 // FP64 product with the second epilogue output (P_{i,j} schemes: launched beside
 // launch_product(kPrecF64, ...); exactly one of the two runs, as the state asks).
 void launch_product_dual(SnfState* st, const Buffers* bufs_dev, const ProductGrid& g,

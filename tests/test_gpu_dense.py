@@ -136,9 +136,13 @@ def test_small_gap_256_counts(snf):
     assert got["snf_varmu"] * 1.5 <= got["tc2"] and got["snf_fixmu"] * 1.5 <= got["mcweeny"]
 
 
-@pytest.mark.parametrize("n,n_occ", [(2, 1), (37, 20), (130, 40), (300, 151), (1000, 480)])
+@pytest.mark.parametrize("n,n_occ", [(2, 1), (37, 20), (130, 40), (300, 151), (600, 290),
+                                     (700, 333), (1000, 480)])
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_ragged_sizes_parity(snf, n, n_occ, scheme):
+    """Orders up to 896 (padded) run the 32x32-tile product with the k range split inside the
+    workgroup: 600 pads to 640 (five k-chunks per wave, an odd count), 700 to 768; 1000 runs
+    the 128x128 engine with its split tail."""
     h = H.random_spectrum_hamiltonian(n, n_occ, -0.9, 0.02, 0.08, 1.1, seed=n)
     _compare_to_oracle(snf, h, scheme)
 
