@@ -93,6 +93,8 @@ struct ServeRequest {
   int slot = -1;
   size_t off = 0, bytes = 0;
   hipEvent_t ev = nullptr;
+  bool started = false;     // admission work enqueued: takes part in the next grouped step
+  bool finished = false;    // its stop flag came back: retired behind the next step
   int status = SNF_PENDING;
   snf_result result;
 };
@@ -141,6 +143,8 @@ struct snf_server {
   // requests), joined by events before the schedule
   hipStream_t stream2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t stream3 = nullptr;      // admissions and retirements, beside the steps
+  hipEvent_t ev_adm = nullptr;        // recorded on stream3 behind the latest admissions
   size_t budget = 0;
   int max_slots = 0;
   char* arena_base = nullptr;     // device arena (the HBM budget)
@@ -229,7 +233,7 @@ static hipEvent_t take_event_locked(snf_server* sv) {
 
 // Admission of one request into slot r->slot: tables, F into x[2] (row stride n), f_0 and
 // the initial schedule -- all stream-ordered, no host waits.
-static int start_request(snf_server* sv, ServeRequest* r) {
+static int start_request(snf_server* sv, ServeRequest* r, hipStream_t s) {
   const int k = r->slot;
   const RequestLayout L = request_layout(r->n, r->prec);
   char* base = sv->arena_base + r->off;
@@ -247,7 +251,6 @@ static int start_request(snf_server* sv, ServeRequest* r) {
   d.np = r->np;
   d.n = r->n;
   init_state(&sv->state_stage[k], r->n, &r->params, r->scheme, r->prec);
-  hipStream_t s = sv->stream;
   SV_HIP(hipMemcpyAsync(sv->bufs + k, &b, sizeof(Buffers), hipMemcpyHostToDevice, s));
   SV_HIP(hipMemcpyAsync(sv->slots + k, &d, sizeof(SlotDesc), hipMemcpyHostToDevice, s));
   SV_HIP(hipMemcpyAsync(sv->states + k, &sv->state_stage[k], sizeof(SnfState),
@@ -267,9 +270,8 @@ static int start_request(snf_server* sv, ServeRequest* r) {
 // Retirement of a finished request: D out (device copy, or through x[2] to the pinned D
 // staging), the state to pinned memory, an event behind them; the finisher thread completes
 // it on the host.  Stream order keeps a later admission into the same memory behind these.
-static int retire_request(snf_server* sv, ServeRequest* r) {
+static int retire_request(snf_server* sv, ServeRequest* r, hipStream_t s) {
   const int k = r->slot;
-  hipStream_t s = sv->stream;
   const Buffers& b = sv->bufs_stage[k];
   if (r->device_io) {
     launch_copy_out(sv->states + k, sv->bufs + k, r->n, r->np, r->D_dev, r->n, s);
@@ -316,13 +318,81 @@ static void finisher(snf_server* sv) {
   }
 }
 
+// One iteration: launch the grouped step over the requests started earlier; while it runs,
+// enqueue on a third stream the retirement of the requests whose stop flag came back from the
+// previous step and the admission of pending requests into free slots (none of them is in
+// the step, so both overlap its products); then wait for the step and read its stop flags.
+// The next step waits for the admissions (event).  A request joins the step after the one
+// during which it was admitted and is copied out during the step after its stop flag.
 static void scheduler(snf_server* sv) {
   (void)hipSetDevice(sv->device);
-  std::vector<ServeRequest*> admitted;
+  std::vector<ServeRequest*> admitted, finished;
   std::vector<int> active;
+  bool adm_pending = false;
   for (;;) {
+    int rc = SNF_OK;
+    hipStream_t s = sv->stream, s3 = sv->stream3;
+    if (adm_pending) {   // the step below reads the admitted requests' state and X_0
+      if (hipStreamWaitEvent(s, sv->ev_adm, 0) != hipSuccess) rc = SNF_EDEVICE;
+      adm_pending = false;
+    }
+    // 1. grouped step over every started, unfinished request
+    active.clear();
+    int prec_mask = 1 << kPrecF64;
+    for (int i = 0; i < sv->max_slots; ++i) {   // slot_req is written by this thread only
+      const ServeRequest* r = sv->slot_req[i];
+      if (r && r->started && !r->finished) {
+        active.push_back(i);
+        if (r->prec == SNF_P_FP32 || r->prec == SNF_P_FP32_REF64) prec_mask |= 1 << kPrecF32;
+        if (r->prec == SNF_P_BF16_REF64) prec_mask |= 1 << kPrecBF16;
+      }
+    }
+    // largest orders first: their tiles run the longest k-loops, so dispatching them first
+    // lets the short tiles of small requests fill the end of the step (dispatch order only;
+    // every request keeps its own tiles and reduction order)
+    std::stable_sort(active.begin(), active.end(), [&](int x, int y) {
+      return sv->desc_stage[x].np > sv->desc_stage[y].np;
+    });
+    const int na = (int)active.size();
+    if (na > 0 && rc == SNF_OK) {
+      int* idx = sv->index_stage;
+      int total = 0;
+      for (int a = 0; a < na; ++a) {
+        idx[a] = active[a];
+        idx[na + a] = total;
+        total += num_product_tiles(sv->desc_stage[active[a]].np, 1);
+      }
+      idx[2 * na] = total;
+      if (hipMemcpyAsync(sv->active_dev, idx, na * sizeof(int), hipMemcpyHostToDevice, s) !=
+              hipSuccess ||
+          hipMemcpyAsync(sv->offs_dev, idx + na, (na + 1) * sizeof(int), hipMemcpyHostToDevice,
+                         s) != hipSuccess)
+        rc = SNF_EDEVICE;
+      if (rc == SNF_OK) {
+        launch_grouped_step(prec_mask, sv->slots, sv->active_dev, sv->offs_dev, na, total,
+                            sv->stop_dev, s, sv->stream2, sv->ev_fork, sv->ev_join);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(sv->stop_stage, sv->stop_dev, na * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s) != hipSuccess)
+          rc = SNF_EDEVICE;
+      }
+    }
+    // 2. retire the requests finished in the previous step (their buffers are untouched by
+    //    this step: they are not in it, and stopped states make every kernel exit)
+    for (size_t f = 0; f < finished.size() && rc == SNF_OK; ++f) {
+      ServeRequest* r = finished[f];
+      rc = retire_request(sv, r, s3);
+      if (rc != SNF_OK) break;
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->arena.release(r->off, r->bytes);
+      sv->slot_req[r->slot] = nullptr;
+      sv->finishing.push_back(r);
+      sv->fin_cv.notify_one();
+    }
+    finished.clear();
+    // 3. admission into free slots (stream order keeps it behind the retirements)
     admitted.clear();
-    {
+    if (rc == SNF_OK) {
       std::unique_lock<std::mutex> lk(sv->mu);
       for (;;) {
         bool any_running = false;
@@ -362,7 +432,7 @@ static void scheduler(snf_server* sv) {
           admitted.push_back(r);
           any_running = true;
         }
-        if (any_running) break;
+        if (any_running || na > 0) break;   // work to launch, or a step to wait for
         if (sv->stopping && sv->pending.empty()) {
           sv->sched_done = true;
           sv->fin_cv.notify_all();
@@ -371,63 +441,30 @@ static void scheduler(snf_server* sv) {
         sv->cv.wait(lk);
       }
     }
-    int rc = SNF_OK;
-    for (ServeRequest* r : admitted)
-      if ((rc = start_request(sv, r)) != SNF_OK) break;
-    // grouped step over every running request
-    active.clear();
-    int prec_mask = 1 << kPrecF64;
-    for (int i = 0; i < sv->max_slots; ++i)   // slot_req is written by this thread only
-      if (sv->slot_req[i]) {
-        active.push_back(i);
-        const snf_precision p = sv->slot_req[i]->prec;
-        if (p == SNF_P_FP32 || p == SNF_P_FP32_REF64) prec_mask |= 1 << kPrecF32;
-        if (p == SNF_P_BF16_REF64) prec_mask |= 1 << kPrecBF16;
-      }
-    // largest orders first: their tiles run the longest k-loops, so dispatching them first
-    // lets the short tiles of small requests fill the end of the step (dispatch order only;
-    // every request keeps its own tiles and reduction order)
-    std::stable_sort(active.begin(), active.end(), [&](int x, int y) {
-      return sv->desc_stage[x].np > sv->desc_stage[y].np;
-    });
-    const int na = (int)active.size();
+    for (ServeRequest* r : admitted) {
+      if (rc != SNF_OK) break;
+      rc = start_request(sv, r, s3);
+      r->started = (rc == SNF_OK);
+    }
+    if (rc == SNF_OK && !admitted.empty()) {
+      if (hipEventRecord(sv->ev_adm, s3) != hipSuccess) rc = SNF_EDEVICE;
+      adm_pending = true;
+    }
+    // 4. wait for the step (and the work enqueued behind it); read its stop flags
     if (rc == SNF_OK && na > 0) {
-      int* idx = sv->index_stage;
-      int total = 0;
-      for (int a = 0; a < na; ++a) {
-        idx[a] = active[a];
-        idx[na + a] = total;
-        total += num_product_tiles(sv->desc_stage[active[a]].np, 1);
-      }
-      idx[2 * na] = total;
-      hipStream_t s = sv->stream;
-      if (hipMemcpyAsync(sv->active_dev, idx, na * sizeof(int), hipMemcpyHostToDevice, s) !=
-              hipSuccess ||
-          hipMemcpyAsync(sv->offs_dev, idx + na, (na + 1) * sizeof(int), hipMemcpyHostToDevice,
-                         s) != hipSuccess)
+      if (hipStreamSynchronize(s) != hipSuccess) {
         rc = SNF_EDEVICE;
-      if (rc == SNF_OK) {
-        launch_grouped_step(prec_mask, sv->slots, sv->active_dev, sv->offs_dev, na, total,
-                            sv->stop_dev, s, sv->stream2, sv->ev_fork, sv->ev_join);
-        if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(sv->stop_stage, sv->stop_dev, na * sizeof(int32_t),
-                           hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-          rc = SNF_EDEVICE;
-      }
-      for (int a = 0; a < na && rc == SNF_OK; ++a) {
-        if (!sv->stop_stage[a]) continue;
-        ServeRequest* r = sv->slot_req[active[a]];
-        rc = retire_request(sv, r);
-        if (rc != SNF_OK) break;
-        std::lock_guard<std::mutex> lk(sv->mu);
-        sv->arena.release(r->off, r->bytes);
-        sv->slot_req[r->slot] = nullptr;
-        sv->finishing.push_back(r);
-        sv->fin_cv.notify_one();
+      } else {
+        for (int a = 0; a < na; ++a) {
+          if (!sv->stop_stage[a]) continue;
+          ServeRequest* r = sv->slot_req[active[a]];
+          r->finished = true;
+          finished.push_back(r);
+        }
       }
     }
     if (rc != SNF_OK) {
+      finished.clear();
       std::lock_guard<std::mutex> lk(sv->mu);
       fail_all_locked(sv, rc);
       if (sv->stopping) {
@@ -497,7 +534,9 @@ int snf_serve_create(size_t hbm_budget_bytes, int32_t max_slots, snf_server** ou
             hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) == hipSuccess &&
             hipStreamCreateWithFlags(&sv->stream2, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&sv->ev_fork, hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&sv->ev_join, hipEventDisableTiming) == hipSuccess;
+            hipEventCreateWithFlags(&sv->ev_join, hipEventDisableTiming) == hipSuccess &&
+            hipStreamCreateWithFlags(&sv->stream3, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&sv->ev_adm, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipMalloc(&sv->arena_base, hbm_budget_bytes) == hipSuccess;
   ok = ok && hipHostMalloc(&sv->pin_base, pin, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipMalloc(&sv->states, max_slots * sizeof(SnfState)) == hipSuccess &&
@@ -625,6 +664,8 @@ int snf_serve_destroy(snf_server* sv) {
   sv->fin_cv.notify_all();
   if (sv->finisher.joinable()) sv->finisher.join();
   if (sv->stream) (void)hipStreamSynchronize(sv->stream);
+  if (sv->stream3) (void)hipStreamSynchronize(sv->stream3);
+  if (sv->stream2) (void)hipStreamSynchronize(sv->stream2);
   for (auto& kv : sv->by_ticket) delete kv.second;
   for (hipEvent_t e : sv->free_events) (void)hipEventDestroy(e);
   if (sv->arena_base) (void)hipFree(sv->arena_base);
@@ -644,6 +685,8 @@ int snf_serve_destroy(snf_server* sv) {
   if (sv->ev_fork) (void)hipEventDestroy(sv->ev_fork);
   if (sv->ev_join) (void)hipEventDestroy(sv->ev_join);
   if (sv->stream2) (void)hipStreamDestroy(sv->stream2);
+  if (sv->ev_adm) (void)hipEventDestroy(sv->ev_adm);
+  if (sv->stream3) (void)hipStreamDestroy(sv->stream3);
   if (sv->stream) (void)hipStreamDestroy(sv->stream);
   const int rc = sv->sticky_error;
   delete sv;
