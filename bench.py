@@ -83,10 +83,26 @@ def cpu_baseline(h, kw):
     t0 = time.perf_counter()
     r = dense.purify(h.F, "snf_varmu", **kw)
     dt = time.perf_counter() - t0
-    return dict(value=round(dt * 1e3, 1), unit="ms", cores=int(threads), kind="oracle",
-                sample=("one full solve of the same workload (n=4096 lattice, SnF varying-mu, "
-                        f"FP64 numpy, {r['products']} method products; the oracle also forms "
-                        "X^2 separately for its check)"))
+    out = dict(value=round(dt * 1e3, 1), unit="ms", cores=int(threads), kind="oracle",
+               sample=("one full solve of the same workload (n=4096 lattice, SnF varying-mu, "
+                       f"FP64 numpy, {r['products']} method products; the oracle also forms "
+                       "X^2 separately for its check)"))
+    # the same oracle on one core: its first iteration (a check and a step, 3 dense
+    # products), scaled to the solve's 2 * iterations + 1 products
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1, user_api="blas"):
+            t0 = time.perf_counter()
+            dense.purify(h.F, "snf_varmu", **dict(kw, tol=1e-300, max_iter=1))
+            dt1 = time.perf_counter() - t0
+        its = r["iterations"]
+        out["single_core"] = dict(
+            value=round(dt1 * 1e3 * (2 * its + 1) / 3, 1), unit="ms", cores=1,
+            sample=f"first iteration on one core ({dt1:.1f} s for 3 dense products), scaled to "
+                   f"the solve's {2 * its + 1}")
+    except Exception as exc:  # noqa: BLE001
+        out["single_core"] = dict(value=None, note=f"not measured: {exc}")
+    return out
 
 
 def _blas_threads():

@@ -1004,18 +1004,10 @@ __device__ void finish(SnfState* s, int status) {
   s->stop = 1;
 }
 
-__device__ void schedule_body(SnfState* __restrict__ s, const double* __restrict__ partials,
-                              int count, int init) {
-  __shared__ double red[24];
-  double e2 = 0.0, t1 = 0.0, t2 = 0.0;
-  for (int i = threadIdx.x; i < count; i += kReduceThreads) {
-    e2 += partials[i * 4 + 0];
-    t1 += partials[i * 4 + 1];
-    t2 += partials[i * 4 + 2];
-  }
-  block_sum3(e2, t1, t2, red);
-  if (threadIdx.x != 0) return;
-
+// The scalar state machine, run by one thread on a copy of the state's header in LDS (s);
+// the per-iteration log record goes straight to the state in device memory (sg).
+__device__ void schedule_step(SnfState* __restrict__ s, SnfState* __restrict__ sg, double e2,
+                              double t1, double t2, int init) {
   if (init) {
     s->t1 = t1;
     s->t2 = t2;
@@ -1028,7 +1020,7 @@ __device__ void schedule_body(SnfState* __restrict__ s, const double* __restrict
     const double e = sqrt(e2);
     s->e_last = e;
     const int it = s->iter;
-    snf_log_rec* rec = &s->log[it < SNF_LOG_MAX ? it : SNF_LOG_MAX - 1];
+    snf_log_rec* rec = &sg->log[it < SNF_LOG_MAX ? it : SNF_LOG_MAX - 1];
     rec->i = it;
     rec->branch = s->branch;
     rec->precision = s->prec;
@@ -1095,6 +1087,32 @@ __device__ void schedule_body(SnfState* __restrict__ s, const double* __restrict
     s->t2 = t2;
     decide(s);
   }
+}
+
+// Reduce the partial sums in a fixed order, then advance the scalar state.  The state's
+// header (everything before the log) is staged in LDS by all threads, advanced there by
+// thread 0 and written back by all threads: one pass of coalesced accesses instead of a
+// chain of dependent single-thread loads and stores to device memory.
+constexpr int kStateHeaderBytes = (int)offsetof(SnfState, log);
+
+__device__ void schedule_body(SnfState* __restrict__ sg, const double* __restrict__ partials,
+                              int count, int init) {
+  __shared__ double red[24];
+  __shared__ __attribute__((aligned(16))) SnfState hs;   // only the header is used
+  unsigned char* hb = (unsigned char*)&hs;
+  const unsigned char* gb = (const unsigned char*)sg;
+  for (int i = threadIdx.x; i < kStateHeaderBytes; i += kReduceThreads) hb[i] = gb[i];
+  double e2 = 0.0, t1 = 0.0, t2 = 0.0;
+  for (int i = threadIdx.x; i < count; i += kReduceThreads) {
+    e2 += partials[i * 4 + 0];
+    t1 += partials[i * 4 + 1];
+    t2 += partials[i * 4 + 2];
+  }
+  block_sum3(e2, t1, t2, red);             // its barrier also publishes the header copy
+  if (threadIdx.x == 0) schedule_step(&hs, sg, e2, t1, t2, init);
+  __syncthreads();
+  unsigned char* gw = (unsigned char*)sg;
+  for (int i = threadIdx.x; i < kStateHeaderBytes; i += kReduceThreads) gw[i] = hb[i];
 }
 
 __global__ __launch_bounds__(kReduceThreads) void schedule_kernel(SnfState* __restrict__ s,
