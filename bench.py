@@ -151,6 +151,19 @@ def run_small(args):
     line["ms_per_step"] = out["snf_varmu"]["ms"]
     line["schemes"] = out
     line["speedup_vs_sp2"] = round(out["sp2"]["ms"] / out["snf_varmu"]["ms"], 3)
+    # the product kernel of this order (32x32 tiles, k split inside the workgroup), timed with
+    # HIP events around every product launch of one solve
+    _, rt = snf.purify_dense(F, "snf_varmu", out=D, want_log=False,
+                             flags=snf.FLAG_TIME_PRODUCTS, **kw)
+    n = h.n
+    achieved = rt["products"] * float(n) * n * (n + 1) / rt["product_ms"] / 1e9
+    line["roofline"] = dict(bound="mfma", achieved=round(achieved, 3), peak=78.6,
+                            unit="TFLOP/s", frac=round(achieved / 78.6, 5), traffic=None,
+                            kernel="product_f64_small_kernel (32x32 tiles, n=256)",
+                            avg_launch_us=round(rt["product_ms"] * 1e3 / rt["products"], 2),
+                            note="n^2 (n+1) flops per product over the HIP-event time of its "
+                                 "launch; at this order a launch is latency-bound (36 "
+                                 "workgroups of 1.1 MFLOP each)")
     from oracle import dense
     t0 = time.perf_counter()
     reps = 20
@@ -202,6 +215,10 @@ def run_precision(args):
             products_fp64=r["products_fp64"], products_lowp=r["products_lowp"],
             idem_err=r["idem_err"], trace_err=r["trace_err"], dist_to_exact_D=err,
             commutator=comm)
+    # FP32 product kernel alone: the FP32-only mode from the start, every product timed
+    _, rf = snf.purify_dense(F, "snf_varmu", "fp32", out=D, want_log=False, gap_switch=0.0,
+                             flags=snf.FLAG_TIME_PRODUCTS, **kw)
+    f32_tflops = rf["products"] * float(n) * n * (n + 1) / rf["product_ms"] / 1e9
     base = out["snf_varmu/fp64/gsw0.0"]
     line = _base_line("time-to-solution ms at ‖X²−X‖≤1e-8 by precision mode (n=8192)",
                       base["ms"], "ms", args, False, "f64",
@@ -211,6 +228,13 @@ def run_precision(args):
     line["ms_per_step"] = base["ms"]
     line["runs"] = out
     line["speedup_vs_sp2"] = round(out["sp2/fp64/gsw0.0"]["ms"] / base["ms"], 3)
+    line["roofline"] = dict(bound="mfma", achieved=round(f32_tflops, 2), peak=157.3,
+                            unit="TFLOP/s", frac=round(f32_tflops / 157.3, 4), traffic=None,
+                            kernel="product_f32_kernel (f32 MFMA, 128x128 tiles, n=8192)",
+                            avg_launch_ms=round(rf["product_ms"] / rf["products"], 3),
+                            note="n^2 (n+1) flops per product over the HIP-event time of the "
+                                 "product launches of an FP32-only solve (the low-precision "
+                                 "products of the other modes run the same kernel)")
     line["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         # the oracle on the same F for its first two iterations, scaled per iteration to the
@@ -349,10 +373,17 @@ def run_bounds(args):
     b, r1, r2 = pipeline()
     torch.cuda.synchronize()
     t["pipeline_ms"] = (time.perf_counter() - t0) * 1e3
+    b_est = (b[0], b[1], b[4], b[5])
     t0 = time.perf_counter()
     _, rx = snf.purify_dense(F, "snf_varmu", out=D2, want_log=False, **exact_kw)
     torch.cuda.synchronize()
     t["snf_exact_bounds_ms"] = (time.perf_counter() - t0) * 1e3
+    # the pipeline's dominant kernel, the FP64 product: the SnF solve with estimated bounds,
+    # every product timed
+    _, rt = snf.purify_dense(F, "snf_varmu", out=D2, want_log=False,
+                             flags=snf.FLAG_TIME_PRODUCTS, lambda_min=b_est[0],
+                             lambda_max=b_est[1], homo=b_est[2], lumo=b_est[3],
+                             n_occ=h.n_occ, tol=1e-8, max_iter=100)
     w = np.linalg.eigvalsh(h.F)
     line = _base_line("time ms: bounds estimated on the device, then SP2 and SnF (n=4096)",
                       round(t["pipeline_ms"], 2), "ms", args, False, "f64",
@@ -365,6 +396,15 @@ def run_bounds(args):
                                                         h.lumo])
     line["products"] = dict(sp2_estimated=r1["products"], snf_estimated=r2["products"],
                             snf_exact=rx["products"])
+    nn = h.n
+    achieved = rt["products"] * float(nn) * nn * (nn + 1) / rt["product_ms"] / 1e9
+    line["roofline"] = dict(bound="mfma", achieved=round(achieved, 2), peak=78.6,
+                            unit="TFLOP/s", frac=round(achieved / 78.6, 4), traffic=None,
+                            kernel="product_f64_kernel (the pipeline's dominant kernel)",
+                            note="n^2 (n+1) flops per product over the HIP-event time of the "
+                                 "products of the SnF solve with estimated bounds; the "
+                                 "Lanczos matrix-vector product is HBM-bound (68.2 MB per "
+                                 "launch)")
     line["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         from oracle import bounds as obounds, dense
