@@ -145,6 +145,7 @@ struct snf_server {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipStream_t stream3 = nullptr;      // admissions and retirements, beside the steps
   hipEvent_t ev_adm = nullptr;        // recorded on stream3 behind the latest admissions
+  hipEvent_t ev_step = nullptr;       // recorded behind a step's stop flags
   size_t budget = 0;
   int max_slots = 0;
   char* arena_base = nullptr;     // device arena (the HBM budget)
@@ -373,7 +374,8 @@ static void scheduler(snf_server* sv) {
                             sv->stop_dev, s, sv->stream2, sv->ev_fork, sv->ev_join);
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(sv->stop_stage, sv->stop_dev, na * sizeof(int32_t),
-                           hipMemcpyDeviceToHost, s) != hipSuccess)
+                           hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipEventRecord(sv->ev_step, s) != hipSuccess)
           rc = SNF_EDEVICE;
       }
     }
@@ -452,7 +454,11 @@ static void scheduler(snf_server* sv) {
     }
     // 4. wait for the step (and the work enqueued behind it); read its stop flags
     if (rc == SNF_OK && na > 0) {
-      if (hipStreamSynchronize(s) != hipSuccess) {
+      // poll the step's event: a blocking wait would add the wake-up latency of the
+      // runtime's sleep to every step
+      hipError_t q;
+      while ((q = hipEventQuery(sv->ev_step)) == hipErrorNotReady) std::this_thread::yield();
+      if (q != hipSuccess) {
         rc = SNF_EDEVICE;
       } else {
         for (int a = 0; a < na; ++a) {
@@ -536,7 +542,8 @@ int snf_serve_create(size_t hbm_budget_bytes, int32_t max_slots, snf_server** ou
             hipEventCreateWithFlags(&sv->ev_fork, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&sv->ev_join, hipEventDisableTiming) == hipSuccess &&
             hipStreamCreateWithFlags(&sv->stream3, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&sv->ev_adm, hipEventDisableTiming) == hipSuccess;
+            hipEventCreateWithFlags(&sv->ev_adm, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&sv->ev_step, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipMalloc(&sv->arena_base, hbm_budget_bytes) == hipSuccess;
   ok = ok && hipHostMalloc(&sv->pin_base, pin, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipMalloc(&sv->states, max_slots * sizeof(SnfState)) == hipSuccess &&
@@ -686,6 +693,7 @@ int snf_serve_destroy(snf_server* sv) {
   if (sv->ev_join) (void)hipEventDestroy(sv->ev_join);
   if (sv->stream2) (void)hipStreamDestroy(sv->stream2);
   if (sv->ev_adm) (void)hipEventDestroy(sv->ev_adm);
+  if (sv->ev_step) (void)hipEventDestroy(sv->ev_step);
   if (sv->stream3) (void)hipStreamDestroy(sv->stream3);
   if (sv->stream) (void)hipStreamDestroy(sv->stream);
   const int rc = sv->sticky_error;
