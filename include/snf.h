@@ -179,7 +179,9 @@ typedef struct {
   double trace_err;       /* tr D - n_occ (0 if n_occ unknown)                          */
   double alpha_last, beta_last, betabar_last;
   double device_ms;       /* f_0 through the copy-out of D, HIP events on `stream`      */
-  double product_ms;      /* summed product-kernel time (SNF_FLAG_TIME_PRODUCTS)        */
+  double product_ms;      /* summed product-kernel time (SNF_FLAG_TIME_PRODUCTS); at
+                             padded order <= 256 in FP64 the whole step loop is one
+                             launch, and this is its duration                          */
   uint8_t branch[SNF_LOG_MAX]; /* SNF_BRANCH_* of iteration i                            */
   double flops;           /* algorithmic flops of all products: n^2 (n+1) each (only the
                              upper triangle of a symmetric product is needed); block-sparse:

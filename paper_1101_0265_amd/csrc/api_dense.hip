@@ -428,8 +428,23 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
     ++chunks;
     return SNF_OK;
   };
-  rc = enqueue_chunk();
-  if (rc != SNF_OK) return out->status = rc;
+  // the smallest orders run the whole step loop in one cooperative launch (not the P_{m,m}
+  // schemes: their per-step bisection for alpha runs slower inside that launch, measured)
+  bool persistent = false;
+  if (small && np <= kPersistMaxNp && !scheme_pmm_m(scheme)) {
+    if (time_products) SNF_HIP(hipEventRecord(w->prod_ev[0], s));
+    persistent = launch_solve_small(w->state, w->bufs_dev, sgrid, w->partials, max_steps, s) == 0;
+    if (!persistent) (void)hipGetLastError();   // not co-resident: the launch-per-step path
+    else if (time_products) SNF_HIP(hipEventRecord(w->prod_ev[1], s));
+    if (persistent) {
+      ev_used = 2;
+      stopped = true;
+    }
+  }
+  if (!persistent) {
+    rc = enqueue_chunk();
+    if (rc != SNF_OK) return out->status = rc;
+  }
   while (!stopped && enq < max_steps) {
     rc = enqueue_chunk();
     if (rc != SNF_OK) return out->status = rc;
@@ -451,7 +466,12 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
   float ms = 0.f;
   SNF_HIP(hipEventElapsedTime(&ms, w->ev[0], w->ev[1]));
   out->device_ms = ms;
-  if (time_products) {
+  if (time_products && persistent) {
+    // one launch ran every product and every schedule step
+    float m = 0.f;
+    SNF_HIP(hipEventElapsedTime(&m, w->prod_ev[0], w->prod_ev[1]));
+    out->product_ms = m;
+  } else if (time_products) {
     // step k of the loop ran the k-th product; steps after the stop were empty launches
     double tot = 0.0;
     const int real = st->products;

@@ -15,6 +15,7 @@
 //  * copy kernels     -- padded <-> caller layout.
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
+#include <hip/hip_cooperative_groups.h>
 
 #include "schedule_math.h"
 #include "snf_internal.h"
@@ -483,15 +484,18 @@ __device__ __forceinline__ void product_body(const SnfState* __restrict__ st,
 constexpr int kSmallTile = 32;
 constexpr int kSmallThreads = 256;
 
-__global__ __launch_bounds__(kSmallThreads) void product_f64_small_kernel(
-    const SnfState* __restrict__ st, const Buffers* __restrict__ bufs, SmallGrid g) {
-  if (st->stop || st->prec != kPrecF64 || st->dual) return;
-  __shared__ double part[4][kSmallTile][kSmallTile + 1];
+// One 32x32 tile of the pending product (st: the scalar state, in device memory or an LDS
+// copy of it); its FP64 sums go to partials[tile].
+__device__ __forceinline__ void small_tile_product(const SnfState* __restrict__ st,
+                                                   const Buffers* __restrict__ bufs,
+                                                   const SmallGrid& g, int tile,
+                                                   double* __restrict__ partials,
+                                                   double (*part)[kSmallTile][kSmallTile + 1]) {
   const int64_t np = g.np;
   const double* A = bufs->x[st->ia];
   const double* B = bufs->x[st->ib];
   int bi, bj;
-  tile_coords(blockIdx.x, (int)(np / kSmallTile), 1, bi, bj);
+  tile_coords(tile, (int)(np / kSmallTile), 1, bi, bj);
   const int64_t i0 = (int64_t)bi * kSmallTile, j0 = (int64_t)bj * kSmallTile;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int fr = lane & 15, fg = lane >> 4;
@@ -565,8 +569,16 @@ __global__ __launch_bounds__(kSmallThreads) void product_f64_small_kernel(
     const double p = ((part[0][r][c] + part[1][r][c]) + part[2][r][c]) + part[3][r][c];
     epi_elem(p, i0 + r, j0 + c, 1, bi == bj, g.n, np, ea, e2, t1, t2);
   }
-  write_partials(e2, t1, t2, g.partials, blockIdx.x);
+  write_partials(e2, t1, t2, partials, tile);
 }
+
+__global__ __launch_bounds__(kSmallThreads) void product_f64_small_kernel(
+    const SnfState* __restrict__ st, const Buffers* __restrict__ bufs, SmallGrid g) {
+  if (st->stop || st->prec != kPrecF64 || st->dual) return;
+  __shared__ double part[4][kSmallTile][kSmallTile + 1];
+  small_tile_product(st, bufs, g, blockIdx.x, g.partials, part);
+}
+
 
 SmallGrid make_small_grid(int64_t np, int64_t n, double* partials) {
   SmallGrid g;
@@ -1005,7 +1017,8 @@ __device__ void finish(SnfState* s, int status) {
 }
 
 // The scalar state machine, run by one thread on a copy of the state's header in LDS (s);
-// the per-iteration log record goes straight to the state in device memory (sg).
+// the per-iteration log record goes straight to the state in device memory (sg; not written
+// when sg is null).
 __device__ void schedule_step(SnfState* __restrict__ s, SnfState* __restrict__ sg, double e2,
                               double t1, double t2, int init) {
   if (init) {
@@ -1020,7 +1033,8 @@ __device__ void schedule_step(SnfState* __restrict__ s, SnfState* __restrict__ s
     const double e = sqrt(e2);
     s->e_last = e;
     const int it = s->iter;
-    snf_log_rec* rec = &sg->log[it < SNF_LOG_MAX ? it : SNF_LOG_MAX - 1];
+    snf_log_rec dummy;
+    snf_log_rec* rec = sg ? &sg->log[it < SNF_LOG_MAX ? it : SNF_LOG_MAX - 1] : &dummy;
     rec->i = it;
     rec->branch = s->branch;
     rec->precision = s->prec;
@@ -1113,6 +1127,60 @@ __device__ void schedule_body(SnfState* __restrict__ sg, const double* __restric
   __syncthreads();
   unsigned char* gw = (unsigned char*)sg;
   for (int i = threadIdx.x; i < kStateHeaderBytes; i += kReduceThreads) gw[i] = hb[i];
+}
+
+// ---------------------------------------------------------------------------------------
+// Small orders, whole solve in one cooperative launch: every workgroup owns one 32x32 tile
+// and a private LDS copy of the scalar state.  A step is the tile product, one grid barrier,
+// then every workgroup reduces all tiles' partial sums in the same fixed order and advances
+// its own copy of the state: identical inputs and code give identical states, so all
+// workgroups agree on the next product and on when to stop without a second barrier
+// (workgroup 0 also writes the log and, at the end, the state).  Partial sums alternate
+// between two buffers by step parity, so a step's sums are not overwritten before every
+// workgroup has read them.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kSmallThreads) void solve_small_kernel(SnfState* __restrict__ sg,
+                                                                    const Buffers* __restrict__ bufs,
+                                                                    SmallGrid g,
+                                                                    double* __restrict__ partials2,
+                                                                    int max_steps) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  __shared__ double part[4][kSmallTile][kSmallTile + 1];
+  __shared__ double red[24];
+  __shared__ __attribute__((aligned(16))) SnfState hs;   // only the header is used
+  unsigned char* hb = (unsigned char*)&hs;
+  const unsigned char* gb = (const unsigned char*)sg;
+  for (int i = threadIdx.x; i < kStateHeaderBytes; i += kSmallThreads) hb[i] = gb[i];
+  __syncthreads();
+  SnfState* log_to = blockIdx.x == 0 ? sg : nullptr;
+  for (int step = 0; step < max_steps; ++step) {
+    if (hs.stop) break;                     // the same decision in every workgroup
+    double* pbuf = partials2 + (size_t)(step & 1) * g.tiles * 4;
+    small_tile_product(&hs, bufs, g, blockIdx.x, pbuf, part);
+    grid.sync();
+    double e2 = 0.0, t1 = 0.0, t2 = 0.0;
+    for (int i = threadIdx.x; i < g.tiles; i += kSmallThreads) {
+      e2 += pbuf[i * 4 + 0];
+      t1 += pbuf[i * 4 + 1];
+      t2 += pbuf[i * 4 + 2];
+    }
+    block_sum3(e2, t1, t2, red);
+    if (threadIdx.x == 0) schedule_step(&hs, log_to, e2, t1, t2, 0);
+    __syncthreads();
+  }
+  if (blockIdx.x == 0) {
+    unsigned char* gw = (unsigned char*)sg;
+    for (int i = threadIdx.x; i < kStateHeaderBytes; i += kSmallThreads) gw[i] = hb[i];
+  }
+}
+
+int launch_solve_small(SnfState* st, const Buffers* bufs_dev, const SmallGrid& g,
+                       double* partials2, int max_steps, hipStream_t s) {
+  void* args[] = {(void*)&st, (void*)&bufs_dev, (void*)&g, (void*)&partials2, (void*)&max_steps};
+  return hipLaunchCooperativeKernel((const void*)solve_small_kernel, dim3(g.tiles),
+                                    dim3(kSmallThreads), args, 0, s) == hipSuccess
+             ? 0
+             : -1;
 }
 
 __global__ __launch_bounds__(kReduceThreads) void schedule_kernel(SnfState* __restrict__ s,

@@ -146,6 +146,12 @@ struct SmallGrid {
 SmallGrid make_small_grid(int64_t np, int64_t n, double* partials);
 void launch_product_small(SnfState* st, const Buffers* bufs_dev, const SmallGrid& g,
                           hipStream_t s);
+// The whole step loop of a small-order FP64 solve in one cooperative launch (one workgroup
+// per 32x32 tile, a grid barrier per step); partials2 holds 2 x tiles slots.  Returns 0, or
+// -1 when the runtime refuses the cooperative launch.
+constexpr int64_t kPersistMaxNp = 256;
+int launch_solve_small(SnfState* st, const Buffers* bufs_dev, const SmallGrid& g,
+                       double* partials2, int max_steps, hipStream_t s);
 // FP64 product with the second epilogue output (P_{i,j} schemes: launched beside
 // launch_product(kPrecF64, ...); exactly one of the two runs, as the state asks).
 void launch_product_dual(SnfState* st, const Buffers* bufs_dev, const ProductGrid& g,

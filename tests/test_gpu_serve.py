@@ -90,9 +90,13 @@ def test_budget_serialises_admission(snf):
     hs = [_req(n, 240, seed=s) for s in range(4)]
     with snf.Server(int(one * 1.5), max_slots=8) as sv:
         tickets = [sv.submit(h.F, "snf_varmu", "fp64", **_kw(h)) for h in hs]
-        for t in tickets:
-            _, r = sv.wait(t)
+        for h, t in zip(hs, tickets):
+            # each admission reuses the memory the previous request was retired from (the
+            # retirement's copy-out and the admission's writes share one stream)
+            D, r = sv.wait(t)
             assert r["status"] == "ok"
+            o = dense.purify(h.F, "snf_varmu", **_kw(h))
+            assert np.linalg.norm(D - o["D"]) <= 1e-8 * math.sqrt(n)
         times = [sv.timing(t) for t in tickets]
         with pytest.raises(RuntimeError):                  # larger than the whole budget
             sv.submit(_req(900, 400, seed=9).F, "snf_varmu", "fp64",
