@@ -157,8 +157,7 @@ struct snf_server {
   SnfState* states = nullptr;
   Buffers* bufs = nullptr;
   SlotDesc* slots = nullptr;
-  int* active_dev = nullptr;     // [max_slots]
-  int* offs_dev = nullptr;       // [max_slots + 1]
+  int* index_dev = nullptr;      // [2 * max_slots + 1]: active slots, then tile offsets
   int32_t* stop_dev = nullptr;   // [max_slots]
   // pinned host staging of the tables
   SnfState* state_stage = nullptr;   // [max_slots]
@@ -364,13 +363,12 @@ static void scheduler(snf_server* sv) {
         total += num_product_tiles(sv->desc_stage[active[a]].np, 1);
       }
       idx[2 * na] = total;
-      if (hipMemcpyAsync(sv->active_dev, idx, na * sizeof(int), hipMemcpyHostToDevice, s) !=
-              hipSuccess ||
-          hipMemcpyAsync(sv->offs_dev, idx + na, (na + 1) * sizeof(int), hipMemcpyHostToDevice,
+      // one copy: the active slots at [0, na), the tile offsets at [na, 2 na]
+      if (hipMemcpyAsync(sv->index_dev, idx, (2 * na + 1) * sizeof(int), hipMemcpyHostToDevice,
                          s) != hipSuccess)
         rc = SNF_EDEVICE;
       if (rc == SNF_OK) {
-        launch_grouped_step(prec_mask, sv->slots, sv->active_dev, sv->offs_dev, na, total,
+        launch_grouped_step(prec_mask, sv->slots, sv->index_dev, sv->index_dev + na, na, total,
                             sv->stop_dev, s, sv->stream2, sv->ev_fork, sv->ev_join);
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(sv->stop_stage, sv->stop_dev, na * sizeof(int32_t),
@@ -549,8 +547,7 @@ int snf_serve_create(size_t hbm_budget_bytes, int32_t max_slots, snf_server** ou
   ok = ok && hipMalloc(&sv->states, max_slots * sizeof(SnfState)) == hipSuccess &&
        hipMalloc(&sv->bufs, max_slots * sizeof(Buffers)) == hipSuccess &&
        hipMalloc(&sv->slots, max_slots * sizeof(SlotDesc)) == hipSuccess &&
-       hipMalloc(&sv->active_dev, max_slots * sizeof(int)) == hipSuccess &&
-       hipMalloc(&sv->offs_dev, (max_slots + 1) * sizeof(int)) == hipSuccess &&
+       hipMalloc(&sv->index_dev, (2 * max_slots + 1) * sizeof(int)) == hipSuccess &&
        hipMalloc(&sv->stop_dev, max_slots * sizeof(int32_t)) == hipSuccess;
   ok = ok &&
        hipHostMalloc(&sv->state_stage, max_slots * sizeof(SnfState), hipHostMallocDefault) ==
@@ -680,8 +677,7 @@ int snf_serve_destroy(snf_server* sv) {
   if (sv->states) (void)hipFree(sv->states);
   if (sv->bufs) (void)hipFree(sv->bufs);
   if (sv->slots) (void)hipFree(sv->slots);
-  if (sv->active_dev) (void)hipFree(sv->active_dev);
-  if (sv->offs_dev) (void)hipFree(sv->offs_dev);
+  if (sv->index_dev) (void)hipFree(sv->index_dev);
   if (sv->stop_dev) (void)hipFree(sv->stop_dev);
   if (sv->state_stage) (void)hipHostFree(sv->state_stage);
   if (sv->bufs_stage) (void)hipHostFree(sv->bufs_stage);
