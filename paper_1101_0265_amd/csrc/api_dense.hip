@@ -6,7 +6,8 @@
 // stop flag once ||X^2 - X||_F <= tol (or an error / iteration limit).  Kernels enqueued after
 // the stop exit immediately.  The host keeps two chunks of steps in flight and reads the
 // stop flag of the older chunk from pinned memory, so the GPU never waits for the host and
-// at most one chunk of empty launches follows convergence.
+// at most one chunk of empty launches follows convergence.  At the smallest orders the whole
+// loop is one cooperative launch instead.
 #include <hip/hip_runtime.h>
 
 #include <math.h>

@@ -10,9 +10,15 @@
 //                        the mirror written by the same workgroup; fused epilogue
 //                        Y = c2 P + c1 X + c0 I and FP64 partial sums of ||P - X||_F^2,
 //                        tr Y, ||Y||_F^2 per tile.
+//                        The FP64 variant with a second epilogue output serves the first
+//                        product of a P_{i,j} iteration.
+//  * small orders     -- 32x32 output tiles with the k range split over the four waves of a
+//                        workgroup (no split fix-up), and, at the smallest orders, the whole
+//                        step loop of a solve in one cooperative launch.
 //  * schedule_kernel  -- one workgroup: fixed-order reduction of the per-tile partials and the
 //                        scalar state machine (branch, alpha, beta, beta-bar, stopping).
 //  * copy kernels     -- padded <-> caller layout.
+//  * grouped kernels  -- the serving loop's step over many requests in one launch.
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 #include <hip/hip_cooperative_groups.h>

@@ -1,13 +1,15 @@
 // Serving loop: continuous batching of many independent dense purifications on one GPU.
 //
-// A scheduler thread owns a HIP stream and a device arena (the HBM budget).  Each loop turn
-//   1. admits queued requests (FIFO) while a slot is free and the arena can hold the
-//      request's workspace: copies F in, runs f_0 and the initial schedule for it;
-//   2. launches one grouped step over every running request: the product tiles of all of
-//      them in one launch per precision variant, then every request's schedule, then a
-//      gather of their stop flags;
-//   3. reads the stop flags back and retires the finished requests (D and the result to
-//      the host, arena and slot released).
+// A scheduler thread owns three HIP streams and a device arena (the HBM budget).  Each loop
+// turn
+//   1. launches one grouped step over every started request: the product tiles of all of
+//      them in one launch per precision variant (FP64 and low precision on two streams),
+//      then every request's schedule, then a gather of their stop flags;
+//   2. while that step runs, enqueues on the third stream the retirement of the requests
+//      whose stop flag came back from the previous step (D and the result to the host,
+//      arena and slot released) and admits queued requests (FIFO) while a slot is free and
+//      the arena can hold the request's workspace (F in, f_0 and the initial schedule);
+//   3. waits for the step and reads its stop flags.
 // Nothing is allocated on the device while serving (the arena is sub-allocated), so a
 // finishing request never waits on a device-wide free.
 #include <hip/hip_runtime.h>
