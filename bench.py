@@ -16,6 +16,7 @@ Prints one JSON line.  Extra keys:
 """
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -33,11 +34,19 @@ LATTICE = (16, 16, 8)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xx_f64_lattice_n4096_traffic.json")
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and with whitespace collapsed: the hash follows the code
+    the counters measured, not its comments."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash(files=("kernels_dense.hip", "snf_internal.h", "schedule_math.h")) -> str:
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(ROOT, "paper_1101_0265_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1101_0265_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
