@@ -824,6 +824,14 @@ void launch_split_fixup(SnfState* st, const Buffers* bufs_dev, const ProductGrid
 // ---------------------------------------------------------------------------------------
 // Schedule: reduce the partials in a fixed order, then advance the scalar state.
 // ---------------------------------------------------------------------------------------
+// alpha of a scaled P_{i,j} step: the smaller of the two sides' roots (tables from the state)
+__device__ double pij_alpha_state(const SnfState* s) {
+  const double lo = sched::pij_alpha_side_tab(s->pij_i, s->pij_j, s->pbin[0], s->xstar, s->beta);
+  const double hi =
+      sched::pij_alpha_side_tab(s->pij_j, s->pij_i, s->pbin[1], 1.0 - s->xstar, s->abar);
+  return lo < hi ? lo : hi;
+}
+
 __device__ void decide(SnfState* s) {
 #pragma clang fp contract(off)
   // precision phase (only for the mixed-precision modes)
@@ -847,7 +855,7 @@ __device__ void decide(SnfState* s) {
   if (scheme_is_pij(scheme)) {
     br = SNF_BRANCH_PIJ;
     a = (scheme == SNF_SNF_FIXMU_PIJ)
-            ? sched::pij_alpha(s->pij_i, s->pij_j, s->xstar, s->beta, s->abar)
+            ? pij_alpha_state(s)
             : 1.0;
   } else if (scheme == SNF_SP2_TRACE) {
     br = sched::trace_square(s->t1, s->t2, (double)s->n_occ) ? SNF_BRANCH_SQUARE
@@ -859,7 +867,8 @@ __device__ void decide(SnfState* s) {
       a = sq ? sched::alg2_square_alpha(s->beta) : sched::alg2_fold_alpha(s->betabar);
   } else if (scheme_pmm_m(scheme)) {
     br = s->pmm_m == 3 ? SNF_BRANCH_P33 : SNF_BRANCH_P55;
-    a = (scheme == SNF_SNF_FIXMU3 || scheme == SNF_SNF_FIXMU5) ? sched::pmm_alpha(s->pmm_m, s->beta)
+    a = (scheme == SNF_SNF_FIXMU3 || scheme == SNF_SNF_FIXMU5)
+            ? sched::pmm_alpha_tab(s->pmm_m, s->pbin[0], s->beta)
                                                                : 1.0;
   } else {
     br = SNF_BRANCH_P11;
@@ -930,13 +939,14 @@ __device__ void advance_beta(SnfState* s, int br, double a) {
     s->betabar = 1.0 - s->beta;
   } else if (br == SNF_BRANCH_PIJ) {
     const double xs = s->xstar;
-    const double an = sched::pij_side_next(s->pij_i, s->pij_j, xs, s->beta, a);
-    const double bn = sched::pij_side_next(s->pij_j, s->pij_i, 1.0 - xs, s->abar, a);
+    const double an = sched::pij_side_next_tab(s->pij_i, s->pij_j, s->pbin[0], xs, s->beta, a);
+    const double bn =
+        sched::pij_side_next_tab(s->pij_j, s->pij_i, s->pbin[1], 1.0 - xs, s->abar, a);
     s->beta = an;
     s->abar = bn;
     s->betabar = 1.0 - bn;
   } else {
-    s->beta = sched::pmm_beta_next(s->pmm_m, s->beta, a);
+    s->beta = sched::pij_eval_tab(s->pmm_m, s->pmm_m, s->pbin[0], a * (s->beta - 0.5) + 0.5);
     s->betabar = 1.0 - s->beta;
   }
 }
@@ -948,7 +958,7 @@ __device__ void pmm_next(SnfState* s) {
 #pragma clang fp contract(off)
   const int m = s->pmm_m;
   double r[sched::kPmmMaxM + 1];
-  sched::pmm_coeffs(m, r);
+  for (int k = 0; k <= m; ++k) r[k] = s->pr[k];
   const int ta = (s->cur + 2) & 3, tb = (s->cur + 3) & 3;
   s->want_e = 0;
   if (s->kind == kKindSquare) {             // W done: first Horner level from W.W

@@ -217,6 +217,67 @@ __host__ __device__ inline void pij_taylor(int i, int j, double xs, double* q) {
   }
 }
 
+// ---- table-driven forms for the on-device schedule ----------------------------------------
+// The same arithmetic as pij_eval / pmm_eval with the binomial coefficients C(i+k, k) taken
+// from a table filled once at set-up (exact integers in FP64), so the schedule kernel does
+// not rebuild them with integer divisions at every evaluation; results are bitwise those of
+// the forms above.
+__host__ __device__ inline void pij_binoms(int i, int j, double* bin) {
+  for (int k = 0; k <= j; ++k) {
+    int64_t c = 1;                           // C(i+k, k)
+    for (int t = 1; t <= k; ++t) c = c * (i + t) / t;
+    bin[k] = (double)c;
+  }
+}
+
+__host__ __device__ inline double pij_eval_tab(int i, int j, const double* bin, double x) {
+#pragma clang fp contract(off)
+  const double y = 1.0 - x;
+  double acc = 0.0;
+  for (int k = j; k >= 0; --k) acc = acc * y + bin[k];
+  double xp = x;
+  for (int t = 0; t < i; ++t) xp = xp * x;
+  return xp * acc;
+}
+
+// pmm_alpha with the table of C(m+k, k)
+__host__ __device__ inline double pmm_alpha_tab(int m, const double* bin, double beta) {
+#pragma clang fp contract(off)
+  if (!(beta > 0.0 && beta < 0.5)) return 1.0;
+  double lo = 1.0, hi = 1.0 / (1.0 - 2.0 * beta);
+  for (int it = 0; it < 2200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    const double g = pij_eval_tab(m, m, bin, 0.5 * (1.0 - mid)) -
+                     pij_eval_tab(m, m, bin, mid * (beta - 0.5) + 0.5);
+    if (g < 0.0) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__host__ __device__ inline double pij_alpha_side_tab(int i, int j, const double* bin, double xs,
+                                                     double a) {
+#pragma clang fp contract(off)
+  if (!(a > 0.0 && a < xs)) return 1.0;
+  double lo = 1.0, hi = xs / (xs - a);
+  for (int it = 0; it < 2200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    const double g = pij_eval_tab(i, j, bin, xs * (1.0 - mid)) -
+                     pij_eval_tab(i, j, bin, xs - mid * (xs - a));
+    if (g < 0.0) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__host__ __device__ inline double pij_side_next_tab(int i, int j, const double* bin, double xs,
+                                                    double a, double alpha) {
+#pragma clang fp contract(off)
+  const double u = pij_eval_tab(i, j, bin, xs * (1.0 - alpha));
+  const double v = pij_eval_tab(i, j, bin, xs - alpha * (xs - a));
+  return u > v ? u : v;
+}
+
 // ---- Algorithm 2 (P_{0,1} & P_{1,0} varying-mu purification) ---------------------------
 
 // f0(lambda) = (lambda_max - lambda) / (lambda_max - lambda_min)

@@ -87,6 +87,8 @@ struct SnfState {
   double xstar;           // fixed-mu schemes: image of mu in X_0 (1/2, or x* of P_{i,j})
   double abar;            // P_{i,j}: distance of the occupied part's lower bound from 1
   double pq[sched::kPijQ];  // P_{i,j}: P(x* + v) = x* + v sum_k pq[k] v^k
+  double pbin[2][sched::kPijMax + 1];   // C(i+k, k) (k <= j) and C(j+k, k) (k <= i)
+  double pr[sched::kPmmMaxM + 1];       // P_{m,m}: r_0 .. r_m
   int32_t dual;           // pending product also writes Y2 = d2 P + d1 X + d0 I to x[io2]
   int32_t io2;
   double d2, d1, d0;
