@@ -68,48 +68,6 @@ __host__ __device__ inline void pmm_coeffs(int m, double* r) {
   for (int k = 0; k <= m; ++k) r[k] = pmm_r(m, k);
 }
 
-// P_{m,m}(x) = x^(m+1) sum_{k=0..m} C(m+k, k) (1-x)^k (the incomplete-beta form of P_{i,j}),
-// accurate relative to its value near x = 0, where the scalar schedule evaluates it: the
-// centred form 1/2 + v r(v^2) cancels there.  Horner's rule in y = 1 - x.
-__host__ __device__ inline double pmm_eval(int m, double x) {
-#pragma clang fp contract(off)
-  const double y = 1.0 - x;
-  double binom = 1.0;                        // C(m+k, k) for k = m, built upwards first
-  for (int t = 1; t <= m; ++t) binom = binom * (double)(m + t) / (double)t;
-  double acc = binom;
-  for (int k = m - 1; k >= 0; --k) {
-    binom = binom * (double)(k + 1) / (double)(m + k + 1);   // C(m+k, k) from C(m+k+1, k+1)
-    acc = acc * y + binom;
-  }
-  double xp = x;
-  for (int t = 0; t < m; ++t) xp = xp * x;
-  return xp * acc;
-}
-
-// The root alpha >= 1 of Eq. 3, P(alpha (beta - 1/2) + 1/2) = P((1 - alpha) / 2), for
-// 0 < beta < 1/2: G(alpha) = P((1 - alpha) / 2) - P(alpha (beta - 1/2) + 1/2) is -P(beta) < 0
-// at alpha = 1 and positive at alpha = 1 / (1 - 2 beta) (the scaled gap edge reaches 0); P
-// falls on x < 0 and rises on [0, 1], so G increases in between and bisection converges to
-// the unique root.  Outside (0, 1/2), alpha = 1.
-__host__ __device__ inline double pmm_alpha(int m, double beta) {
-#pragma clang fp contract(off)
-  if (!(beta > 0.0 && beta < 0.5)) return 1.0;
-  double lo = 1.0, hi = 1.0 / (1.0 - 2.0 * beta);
-  for (int it = 0; it < 2200; ++it) {     // a bracket of doubles stops shrinking long before
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    const double g = pmm_eval(m, 0.5 * (1.0 - mid)) - pmm_eval(m, mid * (beta - 0.5) + 0.5);
-    if (g < 0.0) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-// beta <- P_{m,m}(alpha (beta - 1/2) + 1/2)
-__host__ __device__ inline double pmm_beta_next(int m, double beta, double alpha) {
-#pragma clang fp contract(off)
-  return pmm_eval(m, alpha * (beta - 0.5) + 0.5);
-}
-
 // ---- P_{i,j}, i and j odd: scale-and-fold about the unstable fixed point x* -------------
 //
 // X_0 = (mu I - F) / gamma + x* I puts mu on x*; the unoccupied part of the spectrum then
@@ -160,38 +118,6 @@ __host__ __device__ inline double pij_gamma(double lmin, double lmax, double mu,
   return a > b ? a : b;
 }
 
-// One side's Eq. 3: the root alpha >= 1 of P(x* (1 - alpha)) = P(x* - alpha (x* - a)), for
-// 0 < a < x*.  The difference is -P(a) < 0 at alpha = 1 and positive where the scaled edge
-// reaches 0 (alpha = x* / (x* - a)); P falls on x < 0 and rises on [0, x*], so bisection
-// converges to the unique root.  Outside (0, x*): 1.
-__host__ __device__ inline double pij_alpha_side(int i, int j, double xs, double a) {
-#pragma clang fp contract(off)
-  if (!(a > 0.0 && a < xs)) return 1.0;
-  double lo = 1.0, hi = xs / (xs - a);
-  for (int it = 0; it < 2200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    const double g = pij_eval(i, j, xs * (1.0 - mid)) - pij_eval(i, j, xs - mid * (xs - a));
-    if (g < 0.0) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-__host__ __device__ inline double pij_alpha(int i, int j, double xs, double a, double abar) {
-  const double lo = pij_alpha_side(i, j, xs, a);
-  const double hi = pij_alpha_side(j, i, 1.0 - xs, abar);
-  return lo < hi ? lo : hi;
-}
-
-// New bound of one side: the larger image of its interval end and of its gap edge.
-__host__ __device__ inline double pij_side_next(int i, int j, double xs, double a,
-                                                double alpha) {
-#pragma clang fp contract(off)
-  const double u = pij_eval(i, j, xs * (1.0 - alpha));
-  const double v = pij_eval(i, j, xs - alpha * (xs - a));
-  return u > v ? u : v;
-}
-
 // Q(v) = (P(x* + v) - x*) / v = sum_k q_k v^k, k = 0..i+j, from P' = C x^i (1-x)^j with
 // C = (i+j+1)! / (i! j!): q_k = P^(k+1)(x*) / (k+1)! = C / (k+1) [v^k] (x*+v)^i (1-x*-v)^j.
 __host__ __device__ inline void pij_taylor(int i, int j, double xs, double* q) {
@@ -218,10 +144,9 @@ __host__ __device__ inline void pij_taylor(int i, int j, double xs, double* q) {
 }
 
 // ---- table-driven forms for the on-device schedule ----------------------------------------
-// The same arithmetic as pij_eval / pmm_eval with the binomial coefficients C(i+k, k) taken
-// from a table filled once at set-up (exact integers in FP64), so the schedule kernel does
-// not rebuild them with integer divisions at every evaluation; results are bitwise those of
-// the forms above.
+// The binomial coefficients C(i+k, k) come from a table filled once at set-up (exact integers
+// in FP64), so the schedule kernel does not rebuild them with integer divisions at every
+// evaluation; the arithmetic is that of pij_eval.
 __host__ __device__ inline void pij_binoms(int i, int j, double* bin) {
   for (int k = 0; k <= j; ++k) {
     int64_t c = 1;                           // C(i+k, k)
@@ -230,6 +155,9 @@ __host__ __device__ inline void pij_binoms(int i, int j, double* bin) {
   }
 }
 
+// P_{i,j}(x) = x^(i+1) sum_{k=0..j} bin[k] (1-x)^k, bin[k] = C(i+k, k): the incomplete-beta
+// form, accurate relative to its value near x = 0 and for x < 0, where the scalar schedule
+// evaluates it (the centred form 1/2 + v r(v^2) of P_{m,m} cancels there).
 __host__ __device__ inline double pij_eval_tab(int i, int j, const double* bin, double x) {
 #pragma clang fp contract(off)
   const double y = 1.0 - x;
@@ -240,7 +168,12 @@ __host__ __device__ inline double pij_eval_tab(int i, int j, const double* bin, 
   return xp * acc;
 }
 
-// pmm_alpha with the table of C(m+k, k)
+// The root alpha >= 1 of Eq. 3, P(alpha (beta - 1/2) + 1/2) = P((1 - alpha) / 2), for
+// P = P_{m,m} and 0 < beta < 1/2 (bin: C(m+k, k)): G(alpha) = P((1 - alpha) / 2) -
+// P(alpha (beta - 1/2) + 1/2) is -P(beta) < 0 at alpha = 1 and positive at
+// alpha = 1 / (1 - 2 beta) (the scaled gap edge reaches 0); P falls on x < 0 and rises on
+// [0, 1], so G increases in between and bisection (until the bracket of doubles stops
+// shrinking) converges to the unique root.  Outside (0, 1/2), alpha = 1.
 __host__ __device__ inline double pmm_alpha_tab(int m, const double* bin, double beta) {
 #pragma clang fp contract(off)
   if (!(beta > 0.0 && beta < 0.5)) return 1.0;
@@ -255,6 +188,11 @@ __host__ __device__ inline double pmm_alpha_tab(int m, const double* bin, double
   return lo;
 }
 
+// One side's Eq. 3 for P = P_{i,j} (bin: C(i+k, k)): the root alpha >= 1 of
+// P(x* (1 - alpha)) = P(x* - alpha (x* - a)), for 0 < a < x*.  The difference is -P(a) < 0
+// at alpha = 1 and positive where the scaled edge reaches 0 (alpha = x* / (x* - a)); P falls
+// on x < 0 and rises on [0, x*], so bisection converges to the unique root.  Outside (0, x*):
+// 1.  The occupied side is this with (j, i), 1 - x* and a-bar.
 __host__ __device__ inline double pij_alpha_side_tab(int i, int j, const double* bin, double xs,
                                                      double a) {
 #pragma clang fp contract(off)
@@ -270,6 +208,7 @@ __host__ __device__ inline double pij_alpha_side_tab(int i, int j, const double*
   return lo;
 }
 
+// New bound of one side: the larger image of its interval end and of its gap edge.
 __host__ __device__ inline double pij_side_next_tab(int i, int j, const double* bin, double xs,
                                                     double a, double alpha) {
 #pragma clang fp contract(off)
