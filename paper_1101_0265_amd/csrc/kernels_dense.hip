@@ -172,20 +172,56 @@ __device__ __forceinline__ int xcd_remap(int w, int total) {
   return xcd * base + (xcd < rem ? xcd : rem) + slot;
 }
 
+// Order of the upper-triangle tiles: the triangle is cut into blocks of kOrderG x kOrderG
+// tiles; the off-diagonal blocks come first (row-major over the blocks, row-major inside a
+// block), then the diagonal blocks (their upper triangles, row-major).  A full off-diagonal
+// block is 64 tiles, what one XCD runs at once (32 CUs x 2 workgroups), and needs 16 operand
+// panels (tile (i, j) reads row panels i and j, by symmetry).  Summed over the XCDs and
+// their waves of 64, the row-major order of the whole triangle touches 1.4x as many panels
+// at n = 4096 and 2.7x at n = 8192.
+constexpr int kOrderG = 8;
+
 __device__ __forceinline__ void tile_coords(int t, int nt, int sym, int& bi, int& bj) {
   if (!sym) {
     bi = t / nt;
     bj = t % nt;
     return;
   }
-  // row-major over the upper triangle: row r holds nt - r tiles
-  int r = 0, rem = t;
-  while (rem >= nt - r) {
-    rem -= nt - r;
-    ++r;
+  const int G = kOrderG;
+  const int nb = (nt + G - 1) / G;
+  // off-diagonal blocks: block row P holds G * (nt - (P + 1) G) tiles (only the last block
+  // row and column can be partial, and the last block row has no off-diagonal block)
+  int rem = t;
+  for (int P = 0; P + 1 < nb; ++P) {
+    const int right = nt - (P + 1) * G;
+    const int cnt = G * right;
+    if (rem < cnt) {
+      const int q = rem / (G * G);               // full blocks to the left in this row
+      const int Q = P + 1 + q;
+      const int hq = min(G, nt - Q * G);
+      const int rr = rem - q * G * G;
+      bi = P * G + rr / hq;
+      bj = Q * G + rr % hq;
+      return;
+    }
+    rem -= cnt;
   }
-  bi = r;
-  bj = r + rem;
+  // diagonal blocks: block P of h = min(G, nt - P G) tiles a side holds h (h + 1) / 2
+  for (int P = 0; P < nb; ++P) {
+    const int h = min(G, nt - P * G);
+    const int cnt = h * (h + 1) / 2;
+    if (rem < cnt || P + 1 == nb) {
+      int r = 0;
+      while (rem >= h - r) {
+        rem -= h - r;
+        ++r;
+      }
+      bi = P * G + r;
+      bj = P * G + r + rem;
+      return;
+    }
+    rem -= cnt;
+  }
 }
 
 // ---------------------------------------------------------------------------------------
