@@ -213,3 +213,81 @@ def test_error_control_rejects_zero_budget(snf):
     with pytest.raises(RuntimeError):
         snf.purify_bsr(*_dev_bsr(m), m.n, "snf_varmu", trunc_tau=0.0,
                        flags=snf.FLAG_TRUNC_ERROR_CONTROL, **kw)
+
+
+def test_step_full_lattice_65536_sampled(snf):
+    """Two steps at the size of the block-sparse workload (32x32x32 sites, n = 65536, 2048
+    block rows), no truncation: X_1 = X_0^2 from the trace scheme's X_0, then a fold-type
+    step Y = c2 X_1^2 + c1 X_1.  No dense oracle fits at this size, so: the pattern of sampled
+    block rows of Y equals the union of the patterns of the rows it combines (exact); sampled
+    blocks equal FP64 sums over the shared blocks within the FP32 dot-product bound; mirror
+    blocks are exact transposes; the fused sums equal sums over the returned blocks."""
+    m, h = H.lattice_bsr((32, 32, 32), seed=3)
+    n, nb, b = m.n, m.nb, 32
+    w = h.lambda_max - h.lambda_min
+    val = -m.val.astype(np.float64) / w
+    for i in range(nb):
+        lo, hi = m.row_ptr[i], m.row_ptr[i + 1]
+        p = lo + int(np.searchsorted(m.col_idx[lo:hi], i))
+        assert m.col_idx[p] == i
+        val[p] += np.eye(b) * (h.lambda_max / w)
+    X0 = H.BSRMatrix(n=n, b=b, row_ptr=m.row_ptr, col_idx=m.col_idx, val=val.astype(np.float32))
+    dev0 = _dev_bsr(X0)
+    (rp1, ci1, va1), s1, _ = snf.step_bsr(*dev0, n, 1.0, 0.0, 0.0, trunc_tau=0.0)
+
+    def keys(rp, ci):
+        rows = torch.repeat_interleave(torch.arange(nb, device=ci.device),
+                                       (rp[1:] - rp[:-1]).long())
+        return rows * nb + ci.long()
+
+    # e2 of the first step: ||X_0^2 - X_0||_F^2 over the returned blocks (X_0's pattern is
+    # inside X_0^2's: every row holds its diagonal block)
+    k1, k0 = keys(rp1, ci1), keys(dev0[0], dev0[1])
+    idx = torch.searchsorted(k1, k0)
+    assert torch.equal(k1[idx], k0)
+    diff = va1.double().clone()
+    diff[idx] -= dev0[2].double()
+    e2 = float((diff ** 2).sum())
+    assert abs(s1[0] - e2) <= 1e-4 * e2
+
+    c2, c1, c0 = -1.69, 2.6, 0.0
+    (rp2, ci2, va2), s2, _ = snf.step_bsr(rp1, ci1, va1, n, c2, c1, c0, trunc_tau=0.0)
+    rp1h, ci1h = rp1.cpu().numpy(), ci1.cpu().numpy()
+    rp2h, ci2h = rp2.cpu().numpy(), ci2.cpu().numpy()
+
+    def row(rp, ci, i):
+        return ci[rp[i]:rp[i + 1]]
+
+    rng = np.random.default_rng(65536)
+    u32 = 2.0 ** -24
+    checked = 0
+    for i in rng.choice(nb, size=16, replace=False):
+        cols_i = row(rp1h, ci1h, i)
+        union = np.unique(np.concatenate([row(rp1h, ci1h, k) for k in cols_i]))
+        assert np.array_equal(row(rp2h, ci2h, i), union), i
+        Xi = va1[rp1h[i]:rp1h[i + 1]].double().cpu().numpy()
+        for j in list(rng.choice(union, size=3, replace=False)) + [i]:
+            cols_j = row(rp1h, ci1h, j)
+            Xj = va1[rp1h[j]:rp1h[j + 1]].double().cpu().numpy()
+            shared, pi, pj = np.intersect1d(cols_i, cols_j, return_indices=True)
+            P = np.einsum("kab,kcb->ac", Xi[pi], Xj[pj])            # sum_K X_IK X_JK^T
+            A = np.einsum("kab,kcb->ac", np.abs(Xi[pi]), np.abs(Xj[pj]))
+            ref = c2 * P + (c0 * np.eye(b) if i == j else 0.0)
+            pij = np.searchsorted(cols_i, j)
+            if pij < cols_i.size and cols_i[pij] == j:
+                ref = ref + c1 * Xi[pij]
+            q = rp2h[i] + int(np.searchsorted(row(rp2h, ci2h, i), j))
+            got = va2[q].double().cpu().numpy()
+            bound = (32 * shared.size + 2) * u32 * abs(c2) * A + 1e-6 + 2.0 ** -23 * np.abs(ref)
+            assert np.all(np.abs(got - ref) <= bound), (i, j)
+            qm = rp2h[j] + int(np.searchsorted(row(rp2h, ci2h, j), i))
+            assert torch.equal(va2[qm], va2[q].T), (i, j)
+            checked += 1
+    diag = rp2h[:-1] + np.array([np.searchsorted(row(rp2h, ci2h, i), i) for i in range(nb)])
+    tr = float(va2[torch.tensor(diag, device=va2.device)].double()
+               .diagonal(dim1=1, dim2=2).sum())
+    f2 = float((va2.double() ** 2).sum())
+    assert abs(s2[1] - tr) <= 1e-6 * max(1.0, abs(tr))
+    assert abs(s2[2] - f2) <= 1e-5 * f2
+    print(f"\nBSR step at n = {n}: X_1 {ci1.numel() / nb:.0f} blocks per row, Y "
+          f"{ci2.numel() / nb:.0f}; {checked} sampled blocks within the FP32 bound")
