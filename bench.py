@@ -516,6 +516,29 @@ def run_bsr(args):
                                   blocks_per_row=round(r["blocks"] / m.nb, 1),
                                   peak_blocks_per_row=round(peak, 1))), flush=True)
             del D
+    if args.bsr_screen:
+        # norm screening of the block products at several thresholds (tau = 1e-6); accuracy
+        # from ||[F, D]||_F
+        D, _ = snf.purify_bsr(rp, ci, va, m.n, "snf_varmu", trunc_tau=1e-6, want_log=False,
+                              screen_tau=1e-7, **kw)
+        del D
+        for scheme in ("snf_varmu", "sp2"):
+            for tau_s in (0.0, 1e-9, 1e-8, 1e-7, 1e-6):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                D, r = snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=1e-6,
+                                      screen_tau=tau_s, **kw)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3
+                comm = _bsr_commutator((rp, ci, va), D, m.n)
+                print(json.dumps(dict(scheme=scheme, screen_tau=tau_s, ms=round(ms, 1),
+                                      product_ms=round(r["product_ms"], 1),
+                                      products=r["products"], status=r["status"],
+                                      e=r["idem_err"], trace_err=r["trace_err"],
+                                      commutator=comm,
+                                      blocks_per_row=round(r["blocks"] / m.nb, 1))),
+                      flush=True)
+                del D
     res = {}
     for scheme in ("snf_varmu", "sp2"):
         for _ in range(args.warmup):
@@ -708,6 +731,9 @@ def main():
                          "the sweep, one JSON line each")
     ap.add_argument("--serve-slots", type=int, default=256,
                     help="serving workload: requests in flight at most")
+    ap.add_argument("--bsr-screen", action="store_true",
+                    help="block-sparse workload: also run norm-screened products at several "
+                         "thresholds, with ||[F, D]||_F estimates")
     ap.add_argument("--bsr-ec", action="store_true",
                     help="block-sparse workload: also run fixed-threshold and error-controlled "
                          "truncation at several budgets, with ||[F, D]||_F estimates")

@@ -136,6 +136,8 @@ typedef enum {
  *  poly_i, poly_j: the polynomial P_{i,j} of SNF_SNF_FIXMU_PIJ / SNF_PIJ (odd, 1..5);
  *             ignored by the other schemes.  For these two schemes the log's beta is a and
  *             its beta-bar is 1 - a' (the bounds of the two parts above).
+ *  screen_tau: snf_purify_bsr only: norm screening of the block products, >= 0 (0 = off);
+ *             see snf_step_bsr.  Ignored by the dense paths.
  */
 typedef struct {
   double lambda_min, lambda_max;
@@ -148,6 +150,7 @@ typedef struct {
   double gap_switch;
   double lowp_floor;
   int32_t poly_i, poly_j;
+  double screen_tau;
 } snf_params;
 
 #define SNF_LOG_MAX 256
@@ -269,9 +272,17 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
  * the unit of work of the loop above; sums[0] = ||X.X - X||_F^2, sums[1] = tr Y,
  * sums[2] = ||Y||_F^2 (after truncation).  X as F above; *Y_out library-allocated.
  * kernel_ms (optional): duration of the numeric product kernel.
+ * screen_tau (>= 0; 0 = off): norm screening of the product, the other way to exploit the
+ *   decay of the blocks that the sparsity paragraph points to: the block product
+ *   X_IK X_KJ is left out of (X.X)_IJ when ||X_IK||_F ||X_KJ||_F < screen_tau (block norms
+ *   of the FP32 values, in FP64).  Each term left out has Frobenius norm below screen_tau,
+ *   so (X.X)_IJ moves by less than screen_tau times the number of such K.  The screened
+ *   product is used both for sums[0] and for Y; the pattern of Y is still that of X.X.
+ *   SNF_EINVAL for a negative or non-finite value.
  */
 int snf_step_bsr(const snf_bsr* X, double c2, double c1, double c0, double trunc_tau,
-                 snf_bsr** Y_out, double* sums, double* kernel_ms, void* stream);
+                 double screen_tau, snf_bsr** Y_out, double* sums, double* kernel_ms,
+                 void* stream);
 
 /* Copy the arrays of a (library-allocated) snf_bsr into caller device buffers of sizes
    nb + 1, nnzb and nnzb * b * b; enqueued on `stream`, returns after completion. */

@@ -22,6 +22,12 @@ includes that certifying product; Algorithm 1 counts two products per iteration.
 itself spends extra products (it forms X^2 for the check separately from the step) -- it is
 slow on purpose and the count it reports is the scheme's, not its own.
 
+``screen`` (optional, one-product schemes only): ``(b, tau_s)`` replaces X.X by the
+norm-screened block product (``screened_square``) in both the idempotency check and the step,
+and the step takes the printed polynomial in expanded form, c2 P + c1 X + c0 I, so that it
+uses that product.  Not in the paper: the screening is the other use of the decay of the
+blocks next to truncation, and its threshold rule is a reading.
+
 ``mask`` (optional): a callable applied to each new X, used by the block-truncation oracle
 (drop blocks below a threshold after every step, the BSR reading).  A mask with
 ``needs_gap = True`` is called as ``mask(X, gap)`` with the X-space gap beta-bar - beta of
@@ -79,10 +85,41 @@ def step(X: np.ndarray, branch: str, alpha: float, st: "sch.SchemeState" = None)
     return Y
 
 
+def screened_square(X: np.ndarray, b: int, tau_s: float) -> np.ndarray:
+    """X.X with every block product X_IK X_KJ whose factors have Frobenius norms with
+    product below ``tau_s`` left out of block (I, J): P = sum over block columns K of the
+    outer product of block column K and block row K, each block (I, J) of it kept iff
+    ||X_IK||_F ||X_KJ||_F >= tau_s.  Each term left out has norm below tau_s
+    (||AB||_F <= ||A||_F ||B||_F).  tau_s = 0 keeps every term."""
+    n = X.shape[0]
+    nb = n // b
+    blocks = X.reshape(nb, b, nb, b)
+    norms = np.sqrt(np.einsum("ibjc,ibjc->ij", blocks, blocks))
+    P = np.zeros_like(X)
+    for K in range(nb):
+        col = X[:, K * b:(K + 1) * b]
+        row = X[K * b:(K + 1) * b, :]
+        keep = np.outer(norms[:, K], norms[K, :]) >= tau_s
+        P += np.kron(keep, np.ones((b, b))) * (col @ row)
+    return P
+
+
+def step_expanded(X: np.ndarray, P: np.ndarray, branch: str, alpha: float) -> np.ndarray:
+    """Algorithm 2's two maps written out in powers of X, with P standing for X^2:
+    ((1+a) X - a I)^2 = (1+a)^2 P - 2 a (1+a) X + a^2 I and
+    2 (1+a) X - (1+a)^2 X^2 = 2 (1+a) X - (1+a)^2 P."""
+    I = np.eye(X.shape[0])
+    if branch == sch.SQUARE:
+        return (1.0 + alpha) ** 2 * P - 2.0 * alpha * (1.0 + alpha) * X + alpha ** 2 * I
+    if branch == sch.FOLD:
+        return 2.0 * (1.0 + alpha) * X - (1.0 + alpha) ** 2 * P
+    raise ValueError("the expanded step covers the one-product schemes only")
+
+
 def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
            n_occ: int = None, homo: float = None, lumo: float = None, mu: float = None,
            xi: float = None, tol: float = 1e-10, max_iter: int = 200, mask=None,
-           force_branches: str = None, poly_ij=None) -> dict:
+           force_branches: str = None, poly_ij=None, screen=None) -> dict:
     """Purify the dense symmetric ``F``.
 
     Returns dict(status, D, iterations, products, branches, log, e_final, trace) with the
@@ -92,6 +129,8 @@ def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
     """
     if F.ndim != 2 or F.shape[0] != F.shape[1]:
         raise ValueError("F must be square")
+    if screen is not None and scheme not in ("sp2", "tc2", "snf_varmu"):
+        raise ValueError("norm screening applies to the one-product schemes")
     st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi,
                          poly_ij=poly_ij)
     X = f0(np.asarray(F, dtype=np.float64), scheme, lambda_min, lambda_max, mu, st)
@@ -103,7 +142,7 @@ def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
     products = 0
     status = "noconv"
     for it in range(max_iter + 1):
-        X2 = X @ X
+        X2 = X @ X if screen is None else screened_square(X, *screen)
         products += 1
         e = float(np.linalg.norm(X2 - X))
         t1 = float(np.trace(X))
@@ -127,7 +166,7 @@ def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
                    margin=(sch.trace_margin(t1, t2, n_occ) if scheme == "sp2" else None))
         log.append(rec)
         branches.append(branch)
-        X = step(X, branch, alpha, st)
+        X = step(X, branch, alpha, st) if screen is None else step_expanded(X, X2, branch, alpha)
         st.advance(branch, alpha)
         if gap_mask:
             X = mask(X, st.betabar - st.beta)

@@ -11,6 +11,8 @@
 //                           the dense path, whose k-stages are the block columns K present in
 //                           both row unions; stage K gathers blocks (K, I_a) and (K, J_b) of
 //                           block row K (X symmetric: X_{I,K} = X_{K,I}^T), zero when absent.
+//                           With norm screening (bsr_block_norms_kernel first), a block pair
+//                           whose norm product is below the threshold is left out as if absent.
 //                           Fused epilogue: Y = c2 P + c1 X + c0 I, FP64 sums, block norms;
 //                           upper blocks written with their transposed mirror.
 //   5. bsr_truncate_kernel  keep (I,J) and (J,I) iff ||Y_IJ||_F >= tau (diagonal always);
@@ -166,8 +168,34 @@ struct BsrProductArgs {
   double* normP;       // squared Frobenius norm per candidate block
   const int32_t* tiles;  // (TI << 16) | TJ
   double* partials;    // [tiles][4]
+  const double* nrmX;  // squared Frobenius norm per block of X (screening only)
+  double screen2;      // screening threshold squared; 0: no screening
   int nb, W;
 };
+
+// Squared Frobenius norm of every block of X in FP64, one wave per block (lane l sums the
+// squares of its 16 values in order, then a fixed butterfly): the operand norms of the
+// product's norm screening.
+__global__ __launch_bounds__(256) void bsr_block_norms_kernel(const float* __restrict__ val,
+                                                              int64_t nnzb,
+                                                              double* __restrict__ nrm2) {
+  const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (blk >= nnzb) return;                 // uniform across the wave
+  const int lane = threadIdx.x & 63;
+  const float* p = val + blk * kBB + lane * 4;
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < kBB / 256; ++r) {
+    const float4 v = *(const float4*)(p + r * 256);
+    acc += (double)v.x * v.x;
+    acc += (double)v.y * v.y;
+    acc += (double)v.z * v.z;
+    acc += (double)v.w * v.w;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) nrm2[blk] = acc;
+}
 
 constexpr int kBsrLdsW = 128 + 16;   // LDS row stride (floats), as the dense f32 kernel
 constexpr int kChunkWords = 8;      // bitmap words per k-stage list chunk (256 columns)
@@ -182,6 +210,9 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
   // the value index of the first block of each panel (block row K's offset included)
   __shared__ uint32_t kwa[kChunkWords * 32], kwb[kChunkWords * 32];
   __shared__ int32_t kpa[kChunkWords * 32], kpb[kChunkWords * 32];
+  // per k-stage: the block pairs (A block a, B block b) the stage multiplies, bit 4 a + b
+  // (both present and, with screening, norm product at or above the threshold)
+  __shared__ uint16_t kmask[kChunkWords * 32];
   __shared__ uint32_t sw[kChunkWords];
   __shared__ int offs[kChunkWords + 1];
   __shared__ uint32_t spres[2];
@@ -209,19 +240,24 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
   // blocks of their side, block row k = t / 8, columns 4 (t % 8) .. +3 (t = tid mod 256).
   const int side = tid >> 8, lk = (tid & 255) >> 3, lc = (tid & 7) * 4;
   u32x4 rA[kSup], rB[kSup];
-  uint32_t pA = 0, pB = 0;   // presence of the stage's blocks: bits 0-3 A panel, 4-7 B panel
+  uint32_t pA = 0, pB = 0;   // block pairs of the stage (kmask)
   auto gload = [&](int s, u32x4 (&rv)[kSup], uint32_t& pres) {
-    // the 4 panel columns of each side share one bitmap word of block row K
-    const uint32_t wa = kwa[s], wb = kwb[s];
-    pres = ((wa >> (ci0 & 31)) & 0xFu) | (((wb >> (cj0 & 31)) & 0xFu) << 4);
-    const uint32_t wv = side ? wb : wa;
+    // the 4 panel columns of each side share one bitmap word of block row K; a block is
+    // loaded when some pair of the stage uses it, else it stays zero
+    const uint32_t m = kmask[s];
+    pres = m;
+    const uint32_t needA = ((m & 0x000Fu) ? 1u : 0u) | ((m & 0x00F0u) ? 2u : 0u) |
+                           ((m & 0x0F00u) ? 4u : 0u) | ((m & 0xF000u) ? 8u : 0u);
+    const uint32_t needB = (m | (m >> 4) | (m >> 8) | (m >> 12)) & 0xFu;
+    const uint32_t wv = side ? kwb[s] : kwa[s], need = side ? needB : needA;
     const int c0v = side ? cj0 : ci0, p0 = side ? kpb[s] : kpa[s];
 #pragma unroll
     for (int a = 0; a < kSup; ++a) {
       const uint32_t bit = 1u << ((c0v + a) & 31);
-      rv[a] = (wv & bit) ? bsr_gload16(g.X.val + (size_t)(p0 + __popc(wv & (bit - 1u))) * kBB +
-                                       lk * kB + lc)
-                         : u32x4{0, 0, 0, 0};
+      rv[a] = ((need >> a) & 1u)
+                  ? bsr_gload16(g.X.val + (size_t)(p0 + __popc(wv & (bit - 1u))) * kBB +
+                                lk * kB + lc)
+                  : u32x4{0, 0, 0, 0};
     }
   };
   auto lstore = [&](int buf, const u32x4 (&rv)[kSup], uint32_t pres) {
@@ -233,12 +269,11 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
 
   const int fr = lane & 15, fk = lane >> 4;
   auto compute = [&](int buf) {
-    // this wave's A block (row wr) and two B blocks; absent blocks are zero, so their
-    // MFMAs are skipped (the test is uniform across the wave)
+    // this wave's A block (row wr) and two B blocks; the MFMAs of pairs the stage leaves
+    // out (a block absent, or screened) are skipped (the test is uniform across the wave)
     const uint32_t pm = spres[buf];
-    const bool pa = (pm >> wr) & 1u;
-    const bool pb0 = (pm >> (4 + 2 * wc)) & 1u, pb1 = (pm >> (4 + 2 * wc + 1)) & 1u;
-    if (pa && (pb0 || pb1)) {
+    const bool pb0 = (pm >> (4 * wr + 2 * wc)) & 1u, pb1 = (pm >> (4 * wr + 2 * wc + 1)) & 1u;
+    if (pb0 || pb1) {
 #pragma unroll
       for (int kk = 0; kk < kB; kk += 4) {
         float a[2], b[4];
@@ -299,10 +334,34 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
     for (int t = tid; t < nk; t += 512) {
       const int K = klist[t];
       const int rp = g.X.row_ptr[K];
-      kwa[t] = g.X.bm[(size_t)K * W + (ci0 >> 5)];
-      kwb[t] = g.X.bm[(size_t)K * W + (cj0 >> 5)];
-      kpa[t] = rp + g.X.pre[(size_t)K * W + (ci0 >> 5)];
-      kpb[t] = rp + g.X.pre[(size_t)K * W + (cj0 >> 5)];
+      const uint32_t wa = g.X.bm[(size_t)K * W + (ci0 >> 5)];
+      const uint32_t wb = g.X.bm[(size_t)K * W + (cj0 >> 5)];
+      const int pa0 = rp + g.X.pre[(size_t)K * W + (ci0 >> 5)];
+      const int pb0 = rp + g.X.pre[(size_t)K * W + (cj0 >> 5)];
+      kwa[t] = wa;
+      kwb[t] = wb;
+      kpa[t] = pa0;
+      kpb[t] = pb0;
+      const uint32_t ba = (wa >> (ci0 & 31)) & 0xFu, bb = (wb >> (cj0 & 31)) & 0xFu;
+      uint32_t m = 0u;
+#pragma unroll
+      for (int a = 0; a < kSup; ++a)
+        if ((ba >> a) & 1u) m |= bb << (4 * a);
+      if (g.screen2 > 0.0 && m) {
+        double na[kSup], nbv[kSup];
+#pragma unroll
+        for (int a = 0; a < kSup; ++a) {
+          const uint32_t bita = 1u << ((ci0 + a) & 31), bitb = 1u << ((cj0 + a) & 31);
+          na[a] = ((ba >> a) & 1u) ? g.nrmX[pa0 + __popc(wa & (bita - 1u))] : 0.0;
+          nbv[a] = ((bb >> a) & 1u) ? g.nrmX[pb0 + __popc(wb & (bitb - 1u))] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < kSup; ++a)
+#pragma unroll
+          for (int b = 0; b < kSup; ++b)
+            if (na[a] * nbv[b] < g.screen2) m &= ~(1u << (4 * a + b));
+      }
+      kmask[t] = (uint16_t)m;
     }
     __syncthreads();
     if (nk == 0) continue;
@@ -625,6 +684,7 @@ struct BsrBuf {                 // one BSR matrix owned by the library, with loo
 struct BsrWorkspace {
   BsrBuf X[2], P, Fl;           // current / next X, candidate product, F's lookup tables
   DevArr<double> normP, partials, sums;
+  DevArr<double> nrmX;          // norm screening: squared norms of the operand's blocks
   DevArr<int32_t> cnt, rank, tiles;
   DevArr<int64_t> triples;
   int64_t last_triples = 0;
@@ -734,11 +794,19 @@ static int scan_counts(BsrWorkspace* w, const int32_t* cnt_dev, int nb, DevArr<i
 // eps_i >= 0 selects the error-controlled rule (tau2 is then derived from the block-norm
 // histogram of this product); eps_i < 0 keeps the fixed threshold tau2.
 static int bsr_step(BsrWorkspace* w, int cur, int nb, int W, double tau2, int* slots,
-                    hipEvent_t ev_a, hipEvent_t ev_b, hipStream_t s, double eps_i = -1.0) {
+                    hipEvent_t ev_a, hipEvent_t ev_b, hipStream_t s, double eps_i = -1.0,
+                    double screen2 = 0.0) {
   BsrBuf& X = w->X[cur];
   BsrBuf& N = w->X[1 - cur];
   BsrBuf& P = w->P;
   int rc;
+  // 1b. operand block norms for the screening
+  if (screen2 > 0.0 && X.nnzb > 0) {
+    if ((rc = w->nrmX.reserve(X.nnzb))) return rc;
+    hipLaunchKernelGGL(bsr_block_norms_kernel, dim3((unsigned)((X.nnzb + 3) / 4)), dim3(256), 0,
+                       s, X.val.p, X.nnzb, w->nrmX.p);
+    BSR_HIP(hipGetLastError());
+  }
   // 2. symbolic
   if ((rc = P.bm.reserve((size_t)nb * W)) || (rc = P.pre.reserve((size_t)nb * W)) ||
       (rc = w->cnt.reserve(nb)))
@@ -790,6 +858,8 @@ static int bsr_step(BsrWorkspace* w, int cur, int nb, int W, double tau2, int* s
   args.normP = w->normP.p;
   args.tiles = w->tiles.p;
   args.partials = w->partials.p;
+  args.nrmX = screen2 > 0.0 ? w->nrmX.p : nullptr;
+  args.screen2 = screen2 > 0.0 ? screen2 : 0.0;
   args.nb = nb;
   args.W = W;
   if (ev_a) BSR_HIP(hipEventRecord(ev_a, s));
@@ -975,7 +1045,8 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
       !(p.tol > 0.0) || p.max_iter < 1 || p.max_iter >= SNF_LOG_MAX ||
       !isfinite(p.homo) || !isfinite(p.lumo) || !(p.homo < p.lumo) ||
       p.homo < p.lambda_min || p.lumo > p.lambda_max || p.lowp_floor < 0.0 ||
-      !(p.lowp_floor < 0.5) || (scheme == SNF_SP2_TRACE && p.n_occ < 0))
+      !(p.lowp_floor < 0.5) || (scheme == SNF_SP2_TRACE && p.n_occ < 0) ||
+      !(p.screen_tau >= 0.0) || !isfinite(p.screen_tau))
     return fail(SNF_EINVAL);
   hipStream_t s = (hipStream_t)stream;
   std::vector<int32_t> rp, ci;
@@ -1031,7 +1102,7 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
     int slots = 0;
     const double eps_i = ec ? error_control_eps(sh, trunc_tau, n_pred) : -1.0;
     rc = bsr_step(w, cur, nb, W, tau2, &slots, timing ? w->ev[2] : nullptr,
-                  timing ? w->ev[3] : nullptr, s, eps_i);
+                  timing ? w->ev[3] : nullptr, s, eps_i, p.screen_tau * p.screen_tau);
     if (rc) return fail(rc);
     launch_schedule(w->state, w->partials.p, slots, 0, s);
     BSR_HIP(hipGetLastError());
@@ -1085,8 +1156,10 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
 }
 
 int snf_step_bsr(const snf_bsr* Xin, double c2, double c1, double c0, double trunc_tau,
-                 snf_bsr** Y_out, double* sums, double* kernel_ms, void* stream) {
-  if (!Y_out || !sums || !(trunc_tau >= 0.0) || !isfinite(c2) || !isfinite(c1) || !isfinite(c0))
+                 double screen_tau, snf_bsr** Y_out, double* sums, double* kernel_ms,
+                 void* stream) {
+  if (!Y_out || !sums || !(trunc_tau >= 0.0) || !isfinite(c2) || !isfinite(c1) ||
+      !isfinite(c0) || !(screen_tau >= 0.0) || !isfinite(screen_tau))
     return SNF_EINVAL;
   *Y_out = nullptr;
   hipStream_t s = (hipStream_t)stream;
@@ -1115,7 +1188,9 @@ int snf_step_bsr(const snf_bsr* Xin, double c2, double c1, double c0, double tru
   BSR_HIP(hipMemcpyAsync(X.val.p, Xin->val, (size_t)Xin->nnzb * kBB * 4, hipMemcpyDeviceToDevice, s));
   if ((rc = build_lookup(X, nb, W, s))) return rc;
   int slots = 0;
-  if ((rc = bsr_step(w, 0, nb, W, trunc_tau * trunc_tau, &slots, w->ev[2], w->ev[3], s))) return rc;
+  if ((rc = bsr_step(w, 0, nb, W, trunc_tau * trunc_tau, &slots, w->ev[2], w->ev[3], s, -1.0,
+                     screen_tau * screen_tau)))
+    return rc;
   if ((rc = ensure_pinned(w, 64)) || (rc = w->sums.reserve(4))) return rc;
   launch_sum_partials(w->partials.p, slots, w->sums.p, s);
   BSR_HIP(hipGetLastError());

@@ -37,7 +37,8 @@ class Params(ctypes.Structure):
                 ("n_occ", ctypes.c_int64), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("gap_switch", ctypes.c_double), ("lowp_floor", ctypes.c_double),
-                ("poly_i", ctypes.c_int32), ("poly_j", ctypes.c_int32)]
+                ("poly_i", ctypes.c_int32), ("poly_j", ctypes.c_int32),
+                ("screen_tau", ctypes.c_double)]
 
 
 class LogRec(ctypes.Structure):
@@ -90,7 +91,7 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.POINTER(Bsr)), ctypes.POINTER(Result),
                                  ctypes.POINTER(LogRec), i32, vp]
     L.snf_purify_bsr.restype = ctypes.c_int
-    L.snf_step_bsr.argtypes = [ctypes.POINTER(Bsr), dbl, dbl, dbl, dbl,
+    L.snf_step_bsr.argtypes = [ctypes.POINTER(Bsr), dbl, dbl, dbl, dbl, dbl,
                                ctypes.POINTER(ctypes.POINTER(Bsr)),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                vp]
@@ -152,7 +153,8 @@ def _check_dense(t, name):
 
 def make_params(*, lambda_min, lambda_max, mu=float("nan"), xi=float("nan"),
                 homo=float("nan"), lumo=float("nan"), n_occ=-1, tol=1e-10, max_iter=200,
-                flags=0, gap_switch=0.0, lowp_floor=0.0, poly_ij=None) -> Params:
+                flags=0, gap_switch=0.0, lowp_floor=0.0, poly_ij=None,
+                screen_tau=0.0) -> Params:
     return Params(float(lambda_min), float(lambda_max),
                   float("nan") if mu is None else float(mu),
                   float("nan") if xi is None else float(xi),
@@ -160,7 +162,8 @@ def make_params(*, lambda_min, lambda_max, mu=float("nan"), xi=float("nan"),
                   float("nan") if lumo is None else float(lumo),
                   -1 if n_occ is None else int(n_occ), float(tol), int(max_iter), int(flags),
                   float(gap_switch), float(lowp_floor),
-                  int(poly_ij[0]) if poly_ij else 0, int(poly_ij[1]) if poly_ij else 0)
+                  int(poly_ij[0]) if poly_ij else 0, int(poly_ij[1]) if poly_ij else 0,
+                  float(screen_tau))
 
 
 def result_dict(res: Result, log_arr=None) -> dict:
@@ -332,16 +335,16 @@ def purify_bsr(row_ptr, col_idx, val, n: int, scheme: str = "snf_varmu", *, trun
 
 
 def step_bsr(row_ptr, col_idx, val, n: int, c2: float, c1: float, c0: float,
-             trunc_tau: float = 0.0, stream=None) -> tuple:
-    """Y = truncation of (c2 X.X + c1 X + c0 I).  Returns ((row_ptr, col_idx, val), sums,
-    product-kernel ms)."""
+             trunc_tau: float = 0.0, screen_tau: float = 0.0, stream=None) -> tuple:
+    """Y = truncation of (c2 X.X + c1 X + c0 I), X.X norm-screened at ``screen_tau``.
+    Returns ((row_ptr, col_idx, val), sums, product-kernel ms)."""
     m = _bsr_struct(row_ptr, col_idx, val, n)
     out = ctypes.POINTER(Bsr)()
     sums = (ctypes.c_double * 3)()
     ms = ctypes.c_double(0.0)
     sh = _stream_handle(stream)
-    rc = lib().snf_step_bsr(ctypes.byref(m), c2, c1, c0, float(trunc_tau), ctypes.byref(out),
-                            sums, ctypes.byref(ms), sh)
+    rc = lib().snf_step_bsr(ctypes.byref(m), c2, c1, c0, float(trunc_tau), float(screen_tau),
+                            ctypes.byref(out), sums, ctypes.byref(ms), sh)
     if rc != OK:
         raise RuntimeError(f"snf_step_bsr: {strerror(rc)} ({rc})")
     return _take_bsr(out, sh), (sums[0], sums[1], sums[2]), ms.value

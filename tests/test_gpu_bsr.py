@@ -215,6 +215,72 @@ def test_error_control_rejects_zero_budget(snf):
                        flags=snf.FLAG_TRUNC_ERROR_CONTROL, **kw)
 
 
+
+@pytest.mark.parametrize("tau_s", [1e-4, 1e-3])
+def test_step_screened_matches_oracle(snf, tau_s):
+    """Norm screening of one step against the oracle's screened product on the same FP32
+    values: a graded X (X_0^4 of the lattice, block norms from 3e-4 to 1.1, so that 26% /
+    46% of the block triples fall below the two thresholds); the pattern is the unscreened
+    one, the values are those of the screened product within the FP32 dot-product bound,
+    while they differ from the unscreened product by far more than that bound."""
+    m, h = H.lattice_bsr((8, 8, 4), seed=7)
+    n = m.n
+    Fd = m.to_dense()
+    X0 = (h.lambda_max * np.eye(n) - Fd) / (h.lambda_max - h.lambda_min)
+    X1 = X0 @ X0
+    Xm = H.dense_to_bsr(X1 @ X1, 32)
+    X32 = Xm.to_dense()
+    nb = n // 32
+    norms = _block_norms(X32)
+    terms = (norms[:, :, None] * norms[None, :, :]).ravel()
+    assert not np.any(np.abs(terms[terms > 0] / tau_s - 1.0) <= 1e-9)   # no near-ties
+    c2, c1, c0 = -1.44, 2.4, 0.0
+    (rp, ci, va), sums, _ = snf.step_bsr(*_dev_bsr(Xm), n, c2, c1, c0, trunc_tau=0.0,
+                                          screen_tau=tau_s)
+    Y = _to_dense(rp, ci, va, n)
+    Ps = dense.screened_square(X32, 32, tau_s)
+    Yref = c2 * Ps + c1 * X32 + c0 * np.eye(n)
+    Yfull = c2 * (X32 @ X32) + c1 * X32 + c0 * np.eye(n)
+    pat = (norms > 0).astype(int)
+    assert np.array_equal(_block_norms(Y) > 0, ((pat @ pat) > 0) | np.eye(nb, dtype=bool))
+    bound = (n + 2) * 2.0 ** -24 * (np.abs(X32) @ np.abs(X32)) * abs(c2) + 1e-6 \
+        + 2.0 ** -23 * np.abs(Yref)
+    assert np.all(np.abs(Y - Yref) <= bound)
+    assert np.max(np.abs(Yfull - Yref) / bound) > 4.0        # the screening is visible
+    e2 = np.sum((Ps - X32) ** 2)
+    assert abs(sums[0] - e2) <= 1e-4 * e2
+    assert np.array_equal(Y, Y.T)
+
+
+@pytest.mark.parametrize("scheme", ["snf_varmu", "tc2"])
+def test_purify_bsr_screened_vs_oracle(snf, scheme):
+    """Whole solves with truncation (tau = 1e-6) and norm screening (1e-8) on the 8x8x8-site
+    lattice against the oracle with the same truncation rule and the same screening of its
+    FP64 iterates: identical decisions, D as close as for truncation alone."""
+    tau, tau_s = 1e-6, 1e-8
+    m, h = H.lattice_bsr((8, 8, 8), seed=3)
+    n = m.n
+    kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
+              lumo=h.lumo, tol=1e-9, max_iter=60)
+    (rp, ci, va), r = snf.purify_bsr(*_dev_bsr(m), n, scheme, trunc_tau=tau,
+                                      screen_tau=tau_s, **kw)
+    assert r["status"] in ("ok", "ok_floor"), r["status"]
+    Dg = _to_dense(rp, ci, va, n)
+    Fd = m.to_dense()
+    okw = dict(kw)
+    okw.update(tol=0.0, max_iter=r["iterations"])
+    o = dense.purify(Fd, scheme, mask=dense.block_truncation_mask(32, tau),
+                     screen=(32, tau_s), **okw)
+    assert r["branches"] == o["branches"]
+    err = float(np.linalg.norm(Dg - o["D"]))
+    print(f"\nBSR screened {scheme}: status {r['status']} products {r['products']} "
+          f"e={r['idem_err']:.2e} |D-D_oracle|_F={err:.2e} tr err {r['trace_err']:.2e}")
+    assert err <= 1e-3 * math.sqrt(n)
+    assert abs(r["trace_err"]) <= 1e-2 and r["idem_err"] <= 1e-3
+    assert np.array_equal(Dg, Dg.T)
+    with pytest.raises(RuntimeError):
+        snf.purify_bsr(*_dev_bsr(m), n, scheme, trunc_tau=tau, screen_tau=-1.0, **kw)
+
 def test_step_full_lattice_65536_sampled(snf):
     """Two steps at the size of the block-sparse workload (32x32x32 sites, n = 65536, 2048
     block rows), no truncation: X_1 = X_0^2 from the trace scheme's X_0, then a fold-type

@@ -47,7 +47,7 @@ def test_host_only_entry_points(lib):
 def test_binding_structs_match_header():
     """Field layout of the ctypes mirrors against the sizes the header implies."""
     from paper_1101_0265_amd import snf
-    assert ctypes.sizeof(snf.Params) == 6 * 8 + 8 + 8 + 4 + 4 + 8 + 8 + 4 + 4
+    assert ctypes.sizeof(snf.Params) == 6 * 8 + 8 + 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8
     assert ctypes.sizeof(snf.LogRec) == 4 * 4 + 6 * 8
     assert ctypes.sizeof(snf.Result) == 6 * 4 + 8 * 8 + snf.LOG_MAX + 8 + 8
 

@@ -1,0 +1,126 @@
+"""Pins of the norm-screened block product in the CPU oracle (no GPU).
+
+Screening leaves the block product X_IK X_KJ out of (X.X)_IJ when ||X_IK||_F ||X_KJ||_F is
+below a threshold (the block-sparse path's use of the decay of the blocks next to
+truncation; the paper only says that the schemes combine with such approximations, the rule
+is a reading).  Pinned against: the library matrix product when nothing is screened, a
+brute-force loop over block triples on tiny inputs, the norm bound on what is left out, the
+empty product above every norm product, and the unscreened iteration, which a threshold
+below every term reproduces.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dense
+from paper_1101_0265_amd import hamiltonians as H
+
+
+def _graded(nb, b, seed):
+    """Symmetric matrix whose blocks have norms spread over many decades."""
+    rng = np.random.default_rng(seed)
+    n = nb * b
+    X = rng.standard_normal((n, n))
+    scale = 10.0 ** rng.uniform(-9, 0, size=(nb, nb))
+    scale = np.sqrt(scale * scale.T)
+    X = X * np.kron(scale, np.ones((b, b)))
+    return 0.5 * (X + X.T)
+
+
+def test_threshold_zero_is_the_matrix_product():
+    X = _graded(6, 8, 1)
+    P = dense.screened_square(X, 8, 0.0)
+    assert np.allclose(P, X @ X, rtol=0, atol=1e-13 * np.abs(X).max() ** 2 * X.shape[0])
+
+
+@pytest.mark.parametrize("tau_s", [1e-8, 1e-5, 1e-3])
+def test_brute_force_block_triples(tau_s):
+    nb, b = 3, 4
+    X = _graded(nb, b, 7)
+    blk = lambda I, J: X[I * b:(I + 1) * b, J * b:(J + 1) * b]  # noqa: E731
+    P = np.zeros_like(X)
+    skipped = 0
+    for I in range(nb):
+        for J in range(nb):
+            acc = np.zeros((b, b))
+            for K in range(nb):
+                if np.linalg.norm(blk(I, K)) * np.linalg.norm(blk(K, J)) >= tau_s:
+                    acc += blk(I, K) @ blk(K, J)
+                else:
+                    skipped += 1
+            P[I * b:(I + 1) * b, J * b:(J + 1) * b] = acc
+    assert np.allclose(dense.screened_square(X, b, tau_s), P, rtol=1e-13, atol=1e-300)
+    assert 0 < skipped < nb ** 3          # the threshold falls inside the norm range
+
+
+@pytest.mark.parametrize("tau_s", [1e-7, 1e-4, 1e-2])
+def test_left_out_part_within_the_norm_bound(tau_s):
+    nb, b = 8, 6
+    X = _graded(nb, b, 3)
+    blocks = X.reshape(nb, b, nb, b)
+    norms = np.sqrt(np.einsum("ibjc,ibjc->ij", blocks, blocks))
+    D = (dense.screened_square(X, b, tau_s) - X @ X).reshape(nb, b, nb, b)
+    err = np.sqrt(np.einsum("ibjc,ibjc->ij", D, D))
+    for I in range(nb):
+        for J in range(nb):
+            terms = norms[I, :] * norms[:, J]
+            bound = terms[terms < tau_s].sum()
+            assert err[I, J] <= bound * (1 + 1e-12) + 1e-15 * norms.max() ** 2
+            assert bound <= (terms < tau_s).sum() * tau_s
+
+
+def test_threshold_above_every_term_leaves_nothing():
+    X = _graded(4, 5, 11)
+    assert not dense.screened_square(X, 5, 1e3 * np.abs(X).max() ** 2 * X.shape[0]).any()
+
+
+def test_expanded_step_equals_the_printed_maps():
+    X = _graded(4, 5, 2)
+    X = X / np.abs(np.linalg.eigvalsh(X)).max()
+    I = np.eye(X.shape[0])
+    for alpha in (0.0, 0.3, 0.9):
+        sq = dense.step_expanded(X, X @ X, "S", alpha)
+        fo = dense.step_expanded(X, X @ X, "F", alpha)
+        Y = (1 + alpha) * X - alpha * I
+        assert np.allclose(sq, Y @ Y, atol=1e-13)
+        assert np.allclose(fo, 2 * (1 + alpha) * X - (1 + alpha) ** 2 * (X @ X), atol=1e-13)
+
+
+@pytest.mark.parametrize("scheme", ["snf_varmu", "tc2", "sp2"])
+def test_tiny_threshold_reproduces_the_unscreened_iteration(scheme):
+    m, h = H.lattice_bsr((4, 4, 4), seed=3, dtype=np.float64)
+    F = m.to_dense()
+    kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
+              lumo=h.lumo, tol=1e-10, max_iter=60)
+    a = dense.purify(F, scheme, **kw)
+    b = dense.purify(F, scheme, screen=(32, 1e-300), **kw)
+    assert a["status"] == b["status"] == "ok"
+    assert a["branches"] == b["branches"] and a["products"] == b["products"]
+    assert np.linalg.norm(a["D"] - b["D"]) <= 1e-11 * math.sqrt(F.shape[0])
+
+
+def test_screened_iteration_error_grows_with_the_threshold():
+    """On the lattice the screened solve stays close to the unscreened one at small
+    thresholds and moves away as the threshold grows (the left-out terms act as a
+    perturbation of each product)."""
+    m, h = H.lattice_bsr((4, 4, 4), seed=3, dtype=np.float64)
+    F = m.to_dense()
+    kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
+              lumo=h.lumo, tol=1e-7, max_iter=60)
+    ref = dense.purify(F, "snf_varmu", **kw)
+    errs = []
+    for tau_s in (1e-9, 1e-6, 1e-3):
+        r = dense.purify(F, "snf_varmu", screen=(32, tau_s), tol=0.0,
+                         max_iter=ref["iterations"],
+                         **{k: v for k, v in kw.items() if k not in ("tol", "max_iter")})
+        errs.append(float(np.linalg.norm(r["D"] - ref["D"])))
+    assert errs[0] <= 1e-7
+    assert errs[0] <= errs[1] <= errs[2]
+
+
+def test_screening_rejects_multi_product_schemes():
+    F = np.diag(np.linspace(-1, 1, 64))
+    with pytest.raises(ValueError):
+        dense.purify(F, "snf_fixmu", lambda_min=-1, lambda_max=1, mu=0.0, xi=0.1,
+                     screen=(32, 1e-6))
