@@ -199,6 +199,7 @@ __global__ __launch_bounds__(256) void bsr_block_norms_kernel(const float* __res
 
 constexpr int kBsrLdsW = 128 + 16;   // LDS row stride (floats), as the dense f32 kernel
 constexpr int kChunkWords = 8;      // bitmap words per k-stage list chunk (256 columns)
+static_assert(kChunkWords * 32 <= 256, "a chunk's stages must fit waves 0-3 (compaction)");
 
 __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __restrict__ st,
                                                              BsrProductArgs g) {
@@ -213,6 +214,7 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
   // per k-stage: the block pairs (A block a, B block b) the stage multiplies, bit 4 a + b
   // (both present and, with screening, norm product at or above the threshold)
   __shared__ uint16_t kmask[kChunkWords * 32];
+  __shared__ int wkeep[4];             // stages kept per wave (screening)
   __shared__ uint32_t sw[kChunkWords];
   __shared__ int offs[kChunkWords + 1];
   __shared__ uint32_t spres[2];
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
       }
     }
     __syncthreads();
-    const int nk = offs[kChunkWords];
+    int nk = offs[kChunkWords];
     for (int t = tid; t < nk; t += 512) {
       const int K = klist[t];
       const int rp = g.X.row_ptr[K];
@@ -364,6 +366,35 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
       kmask[t] = (uint16_t)m;
     }
     __syncthreads();
+    if (g.screen2 > 0.0) {
+      // drop the stages whose every pair is screened out, keeping the order of the rest
+      // (nk <= kChunkWords * 32 = 256: thread t < nk holds stage t)
+      const bool keep = tid < nk && kmask[tid] != 0;
+      const unsigned long long bal = __ballot(keep);
+      if (lane == 0 && wid < 4) wkeep[wid] = __popcll(bal);
+      uint32_t ewa = 0u, ewb = 0u;
+      int epa = 0, epb = 0;
+      uint16_t em = 0;
+      if (keep) {
+        ewa = kwa[tid];
+        ewb = kwb[tid];
+        epa = kpa[tid];
+        epb = kpb[tid];
+        em = kmask[tid];
+      }
+      __syncthreads();                     // every entry read before any is overwritten
+      if (keep) {
+        int pos = __popcll(bal & ((1ull << lane) - 1ull));
+        for (int v = 0; v < wid; ++v) pos += wkeep[v];
+        kwa[pos] = ewa;
+        kwb[pos] = ewb;
+        kpa[pos] = epa;
+        kpb[pos] = epb;
+        kmask[pos] = em;
+      }
+      nk = wkeep[0] + wkeep[1] + wkeep[2] + wkeep[3];
+      __syncthreads();
+    }
     if (nk == 0) continue;
     // two stages in flight in registers: stage s in LDS buffer s & 1, s + 1 loaded into
     // registers, s + 2 being loaded
