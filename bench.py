@@ -558,6 +558,28 @@ def run_bsr(args):
                            blocks_per_row_by_iterate=[round(x["phase"] / m.nb, 1)
                                                       for x in r["log"]],
                            branches=r["branches"])
+        res[scheme]["commutator"] = _bsr_commutator((rp, ci, va), D, m.n)
+        del D
+    # the same solves with the block products norm-screened at 1e-8 (100x below the
+    # truncation threshold): time, and accuracy through ||[F, D]||_F against the unscreened
+    screened = {}
+    for scheme in (() if args.no_screened else ("snf_varmu", "sp2")):
+        tau_s = 1e-8
+        snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=1e-6, screen_tau=tau_s,
+                       want_log=False, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = max(1, args.steps)
+        for _ in range(steps):
+            D, r = snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=1e-6, screen_tau=tau_s,
+                                  want_log=False, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        screened[scheme] = dict(screen_tau=tau_s, ms=round(ms, 1), products=r["products"],
+                                status=r["status"], idem_err=r["idem_err"],
+                                trace_err=r["trace_err"],
+                                commutator=_bsr_commutator((rp, ci, va), D, m.n),
+                                speedup_vs_unscreened=round(res[scheme]["ms"] / ms, 3))
         del D
     s = res["snf_varmu"]
     line = _base_line("time-to-solution ms at the truncation floor (block-sparse), SnF vs SP2",
@@ -568,6 +590,7 @@ def run_bsr(args):
     line["ms_per_step"] = s["ms"]
     line["schemes"] = res
     line["speedup_vs_sp2"] = round(res["sp2"]["ms"] / s["ms"], 3)
+    line["norm_screened"] = screened
     line["roofline"] = dict(bound="mfma", achieved=s["useful_tflops"], peak=157.3,
                             unit="TFLOP/s", frac=round(s["useful_tflops"] / 157.3, 4),
                             traffic=None, kernel="bsr_product_kernel (f32 MFMA super-tiles)",
@@ -731,6 +754,9 @@ def main():
                          "the sweep, one JSON line each")
     ap.add_argument("--serve-slots", type=int, default=256,
                     help="serving workload: requests in flight at most")
+    ap.add_argument("--no-screened", action="store_true",
+                    help="block-sparse workload: only the unscreened solves (for counter runs "
+                         "whose per-launch figures belong to the headline solves)")
     ap.add_argument("--bsr-screen", action="store_true",
                     help="block-sparse workload: also run norm-screened products at several "
                          "thresholds, with ||[F, D]||_F estimates")
