@@ -818,8 +818,20 @@ ProductGrid make_product_grid(int64_t np, int64_t n, int sym, int num_cus, doubl
   // every slice needs at least one k-stage of the deepest stage that may run (f64 16,
   // f32 32, bf16 64 values of k per stage)
   const int kt_min = (int)(np / stage_depth);
-  if (rem == 0 || rem > num_cus / 2) return g;
-  int s = num_cus / rem;
+  if (rem == 0) return g;
+  int s;
+  if (rem <= num_cus / 2) {
+    s = num_cus / rem;            // a short tail: one slice per compute unit
+  } else if (tiles == rem) {
+    // a single wave of more than half as many tiles as compute units: whole tiles would
+    // run one workgroup per compute unit; three or more slices per tile fill both
+    // workgroup slots of every unit (n = 2048: 136 tiles, 3 slices each).  A lone workgroup
+    // already gets about half the unit's rate, so two slices per tile gain nothing.
+    s = 2 * num_cus / rem;
+    if (s < 3) return g;
+  } else {
+    return g;                     // a long tail behind full waves: whole tiles
+  }
   if (s > kt_min) s = kt_min;
   if (s > kMaxSplit) s = kMaxSplit;
   if (s < 2 || rem * s > split_cap) return g;

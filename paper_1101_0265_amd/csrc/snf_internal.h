@@ -124,7 +124,8 @@ struct ProductGrid {
 };
 
 // Split the last (tiles mod num_cus) tiles into k-slices when that tail would leave most
-// compute units idle; split_cap = slices the split buffer holds.
+// compute units idle, or a single wave of fewer tiles than compute units would hold one
+// workgroup per unit; split_cap = slices the split buffer holds.
 ProductGrid make_product_grid(int64_t np, int64_t n, int sym, int num_cus, double* partials,
                               double* split_buf, int split_cap, int stage_depth);
 // k values per stage of the deepest product variant a precision mode may run

@@ -147,6 +147,15 @@ def test_ragged_sizes_parity(snf, n, n_occ, scheme):
     _compare_to_oracle(snf, h, scheme)
 
 
+@pytest.mark.parametrize("scheme", ["snf_varmu", "sp2", "snf_fixmu"])
+def test_single_wave_split_parity(snf, scheme):
+    """n = 2100 pads to 2176: 153 tiles, more than half the compute units and fewer than
+    all, so every tile is cut into 3 k-slices summed by the fix-up (both workgroup slots of
+    every unit busy)."""
+    h = H.random_spectrum_hamiltonian(2100, 1000, -1.0, -0.03, 0.03, 1.0, seed=2100)
+    _compare_to_oracle(snf, h, scheme)
+
+
 @pytest.mark.parametrize("scheme", ["sp2", "tc2", "snf_varmu", "mcweeny", "snf_fixmu"])
 def test_single_level(snf, scheme):
     F = np.array([[0.3]])

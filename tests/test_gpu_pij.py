@@ -98,11 +98,11 @@ def test_ragged_sizes_parity(snf, n, n_occ, pij):
     _compare(snf, h, "snf_pij", pij)
 
 
-def test_whole_tile_epilogue_2048(snf):
-    """n = 2048: 136 upper-triangle tiles, more than half the compute units, so no tile is
-    split and the second output comes from the product kernel's own epilogue (smaller orders
-    route the tail tiles through the split fix-up)."""
-    h = _off_centre(n=2048, seed=7, mu=-0.4, gap=0.04)
+def test_whole_tile_and_split_epilogues_2944(snf):
+    """n = 2944: 276 upper-triangle tiles, 256 of them computed whole (the second output from
+    the product kernel's own epilogue) and 20 split into k-slices (the second output from the
+    fix-up's epilogue); smaller orders split every tile."""
+    h = _off_centre(n=2944, seed=7, mu=-0.4, gap=0.04)
     _compare(snf, h, "snf_pij", (3, 1))
 
 
