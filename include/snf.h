@@ -188,7 +188,8 @@ typedef struct {
   uint8_t branch[SNF_LOG_MAX]; /* SNF_BRANCH_* of iteration i                            */
   double flops;           /* algorithmic flops of all products: n^2 (n+1) each (only the
                              upper triangle of a symmetric product is needed); block-sparse:
-                             2 b^3 per block triple (I,K,J), I <= J, of stored blocks      */
+                             2 b^3 per block triple (I,K,J), I <= J, of stored blocks
+                             (screened triples included: the count is the pattern's)    */
   int64_t blocks;         /* block-sparse: stored blocks of D (0 for dense)             */
 } snf_result;
 
