@@ -127,10 +127,8 @@ def products_to_accuracy(scheme: str, mu01: float, xi: float, acc: float = 1e-9,
     The unscaled trace scheme ("sp2") is not covered: its choice needs the whole spectrum.
     """
     homo, lumo = mu01 - 0.5 * xi, mu01 + 0.5 * xi
+    # (Algorithm 1 maps mu onto 0.5; the level nearest 0.5 is xi/2 away in F-space)
     kw = dict(lambda_min=0.0, lambda_max=1.0, homo=homo, lumo=lumo, mu=mu01, xi=xi)
-    if scheme in ("mcweeny", "snf_fixmu"):
-        # Algorithm 1 maps mu onto 0.5; the level nearest 0.5 is xi/2 away in F-space.
-        pass
     st = sch.SchemeState(scheme, **kw)
     per_it = products_per_iteration(scheme)
     prods = 0
