@@ -138,8 +138,9 @@ typedef enum {
  *             its beta-bar is 1 - a' (the bounds of the two parts above).
  *  screen_tau: snf_purify_bsr only: norm screening of the block products, >= 0 (0 = off);
  *             see snf_step_bsr.  Its error is not part of the budget of
- *             SNF_FLAG_TRUNC_ERROR_CONTROL; screen_tau <= trunc_tau / 100 left the accuracy
- *             of the lattice solves unchanged.  Ignored by the dense paths.
+ *             SNF_FLAG_TRUNC_ERROR_CONTROL; with a fixed threshold,
+ *             screen_tau <= trunc_tau / 100 left the accuracy of the lattice solves
+ *             unchanged.  Ignored by the dense paths.
  */
 typedef struct {
   double lambda_min, lambda_max;
