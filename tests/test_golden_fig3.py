@@ -1,7 +1,9 @@
 """The setting of Fig. 3 as a stored table (tests/golden/fig3_counts.txt, written from the
 oracle by tests/golden/make_fig3_counts.py; the paper plots these counts and prints none).
 
-* CPU: the oracle reproduces the table exactly, and the table shows what the paper states
+* CPU: the oracle reproduces the table exactly; the table equals an independent
+  recomputation of the same recurrences in 50-digit decimal arithmetic (the anchor: the table
+  is not only the oracle agreeing with itself); and the table shows what the paper states
   about Fig. 3: the scaled schemes need about half the multiplications of the regular ones
   at every chemical potential, and the counts grow like ln(1/xi).
 * GPU: on diagonal test Hamiltonians with both gap edges in the spectrum (the matrices
@@ -11,6 +13,7 @@ oracle by tests/golden/make_fig3_counts.py; the paper plots these counts and pri
 import math
 import os
 import sys
+from decimal import Decimal, getcontext
 
 import numpy as np
 import pytest
@@ -41,6 +44,57 @@ def test_oracle_reproduces_the_table():
     for g, s in zip(got, stored):
         assert g[0] == s[0] and g[1] == pytest.approx(s[1]) and g[2] == pytest.approx(s[2])
         assert tuple(g[3:]) == tuple(s[3:])
+
+
+def _counts_high_precision(mu, xi, acc=Decimal("1e-9")):
+    """Multiplications to max(beta, 1 - beta-bar) <= acc for the four schemes of the table,
+    recomputed from the algorithms in 50-digit decimal arithmetic, independently of the
+    oracle's FP64 code: spectrum [0, 1], gap of width xi centred at mu, exact bounds.
+
+    Algorithm 2 and its alpha = 0 form: f_0 maps lambda to 1 - lambda, so beta = 1 - lumo and
+    beta-bar = 1 - homo; square if beta + beta-bar > 1 (alpha = beta / (2 - beta)), else fold
+    (alpha = (1 - beta-bar) / (1 + beta-bar)); one product per iteration.  Algorithm 1 and its
+    alpha = 1 form (McWeeny): gamma = 2 max(1 - mu, mu), beta = (1 - xi / gamma) / 2,
+    alpha = 3 / sqrt(12 beta^2 - 18 beta + 9), beta_s = alpha (beta - 1/2) + 1/2,
+    beta <- 3 beta_s^2 - 2 beta_s^3; two products per iteration; the bound is beta (the
+    scheme is symmetric about 1/2)."""
+    one, two, half = Decimal(1), Decimal(2), Decimal("0.5")
+    mu, xi = Decimal(repr(mu)), Decimal(repr(xi))
+    out = []
+    for scaled in (False, True):                       # McWeeny, Algorithm 1
+        gamma = two * max(one - mu, mu)
+        beta = half * (one - xi / gamma)
+        k = 0
+        while beta > acc:
+            a = Decimal(3) / (12 * beta * beta - 18 * beta + 9).sqrt() if scaled else one
+            bs = a * (beta - half) + half
+            beta = 3 * bs * bs - 2 * bs * bs * bs
+            k += 2
+        out.append(k)
+    for scaled in (False, True):                       # alpha = 0 form, Algorithm 2
+        beta, betabar = one - (mu + xi / 2), one - (mu - xi / 2)
+        k = 0
+        while max(beta, one - betabar) > acc:
+            if beta + betabar > one:
+                a = beta / (two - beta) if scaled else Decimal(0)
+                beta = ((one + a) * beta - a) ** 2
+                betabar = ((one + a) * betabar - a) ** 2
+            else:
+                a = (one - betabar) / (one + betabar) if scaled else Decimal(0)
+                beta = two * (one + a) * beta - (one + a) ** 2 * beta ** 2
+                betabar = two * (one + a) * betabar - (one + a) ** 2 * betabar ** 2
+            k += 1
+        out.append(k)
+    return tuple(out)
+
+
+def test_table_equals_high_precision_recomputation():
+    """The stored counts (the oracle's, FP64) equal the same recurrences run in 50-digit
+    decimal arithmetic by code that shares nothing with the oracle: a wrong constant, sign or
+    branch rule in either would change some count of the 17 settings."""
+    getcontext().prec = 50
+    for row in _table():
+        assert _counts_high_precision(row[1], row[2]) == tuple(row[3:]), row
 
 
 def test_table_shows_the_claims_of_the_figure():
