@@ -12,7 +12,12 @@ Prints one JSON line.  Extra keys:
                 algorithmic flops n^2 (n + 1) per product (the symmetric product needs only
                 the upper triangle), average product-kernel duration from HIP events recorded
                 on the library's stream over the timed solves;
-  cpu_baseline  the FP64 CPU oracle (numpy) on the same workload, one solve, host cores.
+  cpu_baseline  the FP64 CPU oracle (numpy) on the same workload, one solve, host cores;
+  workloads     compact objects for the other four workloads, each with its own value,
+                roofline and cpu_baseline: n = 256 with a 0.05 gap (latency), n = 8192 with a
+                1e-3 gap (FP64 against FP32/BF16 products with FP64 refinement), the
+                block-sparse lattice n = 65536, and the 512-request serving trace.  Their own
+                --workload lines give the full detail.
 """
 import argparse
 import hashlib
@@ -207,6 +212,10 @@ def run_precision(args):
             ("snf_varmu", "fp32_ref64", 0.0), ("snf_varmu", "fp32_ref64", 0.5),
             ("snf_varmu", "fp32_ref64", 0.9), ("snf_varmu", "bf16_ref64", 0.5),
             ("snf_varmu", "bf16_ref64", 0.9), ("snf_varmu", "fp32", 0.0)]
+    if getattr(args, "compact", False):
+        runs = [("snf_varmu", "fp64", 0.0), ("sp2", "fp64", 0.0), ("snf_fixmu", "fp64", 0.0),
+                ("snf_varmu", "fp32_ref64", 0.0), ("snf_varmu", "fp32_ref64", 0.5),
+                ("snf_varmu", "bf16_ref64", 0.5)]
     out = {}
     for scheme, prec, gsw in runs:
         snf.purify_dense(F, scheme, prec, out=D, want_log=False, gap_switch=gsw, **kw)
@@ -224,10 +233,22 @@ def run_precision(args):
             products_fp64=r["products_fp64"], products_lowp=r["products_lowp"],
             idem_err=r["idem_err"], trace_err=r["trace_err"], dist_to_exact_D=err,
             commutator=comm)
+    flops_one = float(n) * n * (n + 1)
+    # FP64 product kernel: every product of the FP64 scale-and-fold solve timed
+    _, r64 = snf.purify_dense(F, "snf_varmu", "fp64", out=D, want_log=False,
+                              flags=snf.FLAG_TIME_PRODUCTS, **kw)
+    f64_tflops = r64["products"] * flops_one / r64["product_ms"] / 1e9
     # FP32 product kernel alone: the FP32-only mode from the start, every product timed
     _, rf = snf.purify_dense(F, "snf_varmu", "fp32", out=D, want_log=False, gap_switch=0.0,
                              flags=snf.FLAG_TIME_PRODUCTS, **kw)
-    f32_tflops = rf["products"] * float(n) * n * (n + 1) / rf["product_ms"] / 1e9
+    f32_tflops = rf["products"] * flops_one / rf["product_ms"] / 1e9
+    # BF16 product kernel: one step X.X on the FP64 solve's D (the stand-alone product)
+    bf_ms = []
+    for _ in range(4):
+        _, _, kms = snf.step_dense(D, D, 1.0, 0.0, 0.0, "bf16_ref64")
+        bf_ms.append(kms)
+    bf_ms = sorted(bf_ms)[len(bf_ms) // 2]
+    bf16_tflops = flops_one / bf_ms / 1e9
     base = out["snf_varmu/fp64/gsw0.0"]
     line = _base_line("time-to-solution ms at ‖X²−X‖≤1e-8 by precision mode (n=8192)",
                       base["ms"], "ms", args, False, "f64",
@@ -237,13 +258,25 @@ def run_precision(args):
     line["ms_per_step"] = base["ms"]
     line["runs"] = out
     line["speedup_vs_sp2"] = round(out["sp2/fp64/gsw0.0"]["ms"] / base["ms"], 3)
-    line["roofline"] = dict(bound="mfma", achieved=round(f32_tflops, 2), peak=157.3,
-                            unit="TFLOP/s", frac=round(f32_tflops / 157.3, 4), traffic=None,
-                            kernel="product_f32_kernel (f32 MFMA, 128x128 tiles, n=8192)",
-                            avg_launch_ms=round(rf["product_ms"] / rf["products"], 3),
+    line["roofline"] = dict(bound="mfma", achieved=round(f64_tflops, 2), peak=78.6,
+                            unit="TFLOP/s", frac=round(f64_tflops / 78.6, 4), traffic=None,
+                            kernel="product_f64_kernel (f64 MFMA, 128x128 tiles, n=8192)",
+                            avg_launch_ms=round(r64["product_ms"] / r64["products"], 3),
                             note="n^2 (n+1) flops per product over the HIP-event time of the "
-                                 "product launches of an FP32-only solve (the low-precision "
-                                 "products of the other modes run the same kernel)")
+                                 "product launches of the FP64 scale-and-fold solve")
+    line["roofline_fp32"] = dict(bound="mfma", achieved=round(f32_tflops, 2), peak=157.3,
+                                 unit="TFLOP/s", frac=round(f32_tflops / 157.3, 4),
+                                 kernel="product_f32_kernel (f32 MFMA, n=8192)",
+                                 avg_launch_ms=round(rf["product_ms"] / rf["products"], 3),
+                                 note="every product of an FP32-only solve timed (the FP32 "
+                                      "products of the refined modes run the same kernel)")
+    line["roofline_bf16"] = dict(bound="mfma", achieved=round(bf16_tflops, 1), peak=2500.0,
+                                 unit="TFLOP/s", frac=round(bf16_tflops / 2500.0, 4),
+                                 kernel="product_bf16_kernel (bf16 MFMA, f32 accumulation, "
+                                        "n=8192)",
+                                 avg_launch_ms=round(bf_ms, 3),
+                                 note="one stand-alone product X.X (snf_step_dense), median "
+                                      "of 4 HIP-event kernel times")
     line["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         # the oracle on the same F for its first two iterations, scaled per iteration to the
@@ -717,10 +750,10 @@ def run_serve(args):
                                  f"{flops32 / 1e12:.1f} in FP32; achieved over the closed-loop "
                                  f"wall time")
     line["statuses"] = {s_: statuses.count(s_) for s_ in set(statuses)}
-    # oracle on a bounded sample of the same trace: every 4th request, so the sample keeps
+    # oracle on a bounded sample of the same trace: every 8th request, so the sample keeps
     # the trace's mix of orders (the large ones dominate the time, as on the GPU)
     from oracle import dense
-    sample = [(mats[i], trace[i]) for i in range(0, count, 4)]
+    sample = [(mats[i], trace[i]) for i in range(0, count, 8)]
     sample_F = [h.F.cpu().numpy() for h, _ in sample]
     t0 = time.perf_counter()
     for (h, _), F in zip(sample, sample_F):
@@ -729,10 +762,39 @@ def run_serve(args):
     ns = [r.n for _, r in sample]
     line["cpu_baseline"] = dict(value=round(len(sample) / cpu_s, 2), unit="solves/s",
                                 cores=int(_blas_threads()), kind="oracle",
-                                sample=f"every 4th request of the trace ({len(sample)} "
+                                sample=f"every 8th request of the trace ({len(sample)} "
                                        f"requests, n {min(ns)}..{max(ns)}; FP64 numpy, one "
                                        f"after another): {cpu_s:.1f} s")
     return line
+
+
+SUB_KEYS = ("metric", "value", "unit", "ms_per_step", "higher_is_better", "dtype", "config",
+            "speedup_vs_sp2", "latency_ms", "closed_loop_solves_per_s", "roofline",
+            "roofline_fp32", "roofline_bf16", "hbm", "cpu_baseline", "norm_screened", "runs",
+            "schemes")
+
+
+def other_workloads(args):
+    """The other four workloads, each as a compact object with its own roofline and CPU
+    baseline (fewer timed repetitions than their own --workload lines)."""
+    import types
+    import torch
+    sub_args = types.SimpleNamespace(**vars(args))
+    sub_args.steps = max(1, min(args.steps, 2))
+    sub_args.warmup = 1
+    sub_args.compact = True
+    out = {}
+    for name, fn in (("n256_gap0.05", run_small), ("n8192_gap1e-3", run_precision),
+                     ("bsr_lattice_n65536", run_bsr), ("serve_512", run_serve)):
+        t0 = time.perf_counter()
+        line = fn(sub_args)
+        torch.cuda.synchronize()
+        sub = {k: line[k] for k in SUB_KEYS if k in line}
+        sub["wall_s"] = round(time.perf_counter() - t0, 1)
+        out[name] = sub
+        print(f"# {name}: {sub['value']} {sub['unit']} ({sub['wall_s']} s)", file=sys.stderr,
+              flush=True)
+    return out
 
 
 def main():
@@ -763,6 +825,9 @@ def main():
     ap.add_argument("--bsr-ec", action="store_true",
                     help="block-sparse workload: also run fixed-threshold and error-controlled "
                          "truncation at several budgets, with ||[F, D]||_F estimates")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="default workload: leave out the compact objects of the other four "
+                         "workloads")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for hardware-counter runs: a plain 512 MiB device copy (counter "
                          "calibration), then three FP64 products of the workload's X_0")
@@ -895,6 +960,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(h, kw)
+    if not args.no_other_workloads:
+        del F, D
+        torch.cuda.empty_cache()
+        line["workloads"] = other_workloads(args)
     print(json.dumps(line), flush=True)
 
 

@@ -213,13 +213,18 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
 /*
  * snf_step_dense -- one purification step on a dense symmetric X, the unit of work of the
  * loop above (rows a2+a3 of the method: product and fused combination).
- *   Computes P = A.B (A, B symmetric n x n FP64, row stride ld, device) and
+ *   Computes P = A.B (A, B symmetric n x n FP64, row stride ld, device; they need not
+ *   commute) and
  *     Y = c2 P + c1 A + c0 I            (written to Y_dev, row stride ld)
  *   and, in FP64, sums[0] = ||P - A||_F^2, sums[1] = tr Y, sums[2] = ||Y||_F^2
- *   (host array of 3 doubles).  With A == B this is one f_i of Eqs. 4-5 and the
- *   idempotency check of A.  precision: SNF_P_FP64 (f64 MFMA), SNF_P_FP32 (f32 MFMA on
- *   FP32-rounded copies of A and B), SNF_P_BF16_REF64 (bf16 MFMA with FP32 accumulation on
- *   BF16-rounded copies).  Y_dev must not alias A_dev or B_dev.  Synchronous.
+ *   (host array of 3 doubles).  With A == B (the same pointer) this is one f_i of Eqs. 4-5
+ *   and the idempotency check of A; P is then symmetric, only its upper triangle of tiles is
+ *   computed and Y is exactly symmetric.  With A != B every tile is computed (twice the
+ *   work) and Y is in general not symmetric.  Only the upper triangles of A and B are
+ *   assumed to define them in neither case: both must be stored in full.
+ *   precision: SNF_P_FP64 (f64 MFMA), SNF_P_FP32 (f32 MFMA on FP32-rounded copies of A and
+ *   B), SNF_P_BF16_REF64 (bf16 MFMA with FP32 accumulation on BF16-rounded copies).  Y_dev
+ *   must not alias A_dev or B_dev.  Synchronous.
  *   kernel_ms (optional, may be NULL): duration of the product kernel (HIP events).
  */
 int snf_step_dense(const double* A_dev, const double* B_dev, int64_t n, int64_t ld,
@@ -341,6 +346,14 @@ int snf_serve_poll(snf_server* server, uint64_t ticket, snf_result* out);
    (admit -> done), ms[2] total (submit -> done).  SNF_PENDING until done. */
 int snf_serve_timing(snf_server* server, uint64_t ticket, double* ms);
 
+/* Per-request timeline in milliseconds since snf_serve_create: t[0] submitted, t[1] admitted
+ * (slot and arena memory taken), t[2] finished (the scheduler saw the stop flag of the
+ * request's last step, which has completed on the device; from here its memory may be given
+ * to a queued request, whose device work is stream-ordered behind this one's copy-out),
+ * t[3] done (the result is complete and visible to snf_serve_poll).  t: host array of 4
+ * doubles.  SNF_PENDING until done, SNF_EINVAL for an unknown ticket. */
+int snf_serve_timeline(snf_server* server, uint64_t ticket, double* t);
+
 /* Finish every queued and running request, stop the scheduler, release the arena. */
 int snf_serve_destroy(snf_server* server);
 
@@ -385,6 +398,15 @@ size_t snf_workspace_bytes(int64_t n, snf_precision precision);
 
 /* Release the calling device's cached workspace (it is re-created on the next call). */
 int snf_release_workspace(void);
+
+/* Release every per-device workspace the library holds, on every device it has used:
+ * device buffers, pinned host memory, HIP events (snf_release_workspace frees only the
+ * calling device's dense buffers).  Call it while the HIP runtime is still up, before the
+ * process exits (the Python binding registers it with atexit), so that no allocation of the
+ * library is left to the runtime's own teardown.  Destroy servers first; the call must not
+ * overlap other calls into the library.  The library stays usable: the next call on a device
+ * sets its workspace up again.  Returns SNF_OK. */
+int snf_shutdown(void);
 
 /* Human-readable text of a status code (static storage; SNF_EDEVICE includes the last
    HIP error string seen by this thread). */

@@ -60,12 +60,16 @@ products_per_iteration = sch.products_per_iteration
 def purify_spectrum(eigvals: np.ndarray, scheme: str, *, lambda_min: float,
                     lambda_max: float, n_occ: int = None, homo: float = None,
                     lumo: float = None, mu: float = None, xi: float = None,
-                    tol: float = 1e-10, max_iter: int = 200, poly_ij=None) -> dict:
+                    tol: float = 1e-10, max_iter: int = 200, poly_ij=None,
+                    force_branches: str = None) -> dict:
     """Run ``scheme`` on the spectrum; returns the final eigenvalues of D and the log.
 
     Returned keys: status ("ok" | "noconv" | "nonfinite"), p (eigenvalues of D), iterations,
     products, branches (string of S/F/M), log (list of per-iteration dicts with i, branch,
-    alpha, beta, betabar, e, t1, t2 of X_{i-1} before the step), e_final, trace.
+    alpha, beta, betabar, e, t1, t2 of X_{i-1} before the step, and for the trace scheme the
+    margin of its choice), e_final, trace.  ``force_branches`` replays a given branch string
+    for the trace scheme (an FP64 near-tie of the trace rule resolved the other way by another
+    implementation).
     """
     st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi,
                          poly_ij=poly_ij)
@@ -92,7 +96,10 @@ def purify_spectrum(eigvals: np.ndarray, scheme: str, *, lambda_min: float,
             log.append(rec)
             break
         branch, alpha = st.choose(t1, t2, n_occ)
-        rec.update(branch=branch, alpha=alpha)
+        if force_branches is not None and it < len(force_branches):
+            branch = force_branches[it]
+        rec.update(branch=branch, alpha=alpha,
+                   margin=(sch.trace_margin(t1, t2, n_occ) if scheme == "sp2" else None))
         log.append(rec)
         branches.append(branch)
         p = apply_branch(p, branch, alpha, st)

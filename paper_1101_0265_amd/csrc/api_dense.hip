@@ -81,6 +81,56 @@ static void free_buffers(Workspace* w) {
   w->lp_bytes = 0;
 }
 
+// Every resource of a workspace: device buffers, pinned host memory, events.  The object
+// itself stays (another thread may be waiting on its mutex) and is set up again on its next
+// use.  Called with w->mu held and the workspace's device current.
+static void release_all(Workspace* w) {
+  free_buffers(w);
+  if (w->x[3]) (void)hipFree(w->x[3]);
+  w->x[3] = nullptr;
+  if (w->partials) (void)hipFree(w->partials);
+  w->partials = nullptr;
+  w->partial_cap = 0;
+  if (w->split_buf) (void)hipFree(w->split_buf);
+  w->split_buf = nullptr;
+  if (w->state) (void)hipFree(w->state);
+  w->state = nullptr;
+  if (w->bufs_dev) (void)hipFree(w->bufs_dev);
+  w->bufs_dev = nullptr;
+  if (w->sums_dev) (void)hipFree(w->sums_dev);
+  w->sums_dev = nullptr;
+  if (w->state_host) (void)hipHostFree(w->state_host);
+  w->state_host = nullptr;
+  if (w->flags_host) (void)hipHostFree(w->flags_host);
+  w->flags_host = nullptr;
+  if (w->sums_host) (void)hipHostFree(w->sums_host);
+  w->sums_host = nullptr;
+  for (int i = 0; i < 4; ++i) {
+    if (w->ev[i]) (void)hipEventDestroy(w->ev[i]);
+    w->ev[i] = nullptr;
+  }
+  for (hipEvent_t e : w->prod_ev) (void)hipEventDestroy(e);
+  w->prod_ev.clear();
+  w->num_cus = 0;
+}
+
+void dense_release_all_devices() {
+  int prev = 0;
+  const bool restore = hipGetDevice(&prev) == hipSuccess;
+  for (int dev = 0; dev < 64; ++dev) {
+    Workspace* w = nullptr;
+    {
+      std::lock_guard<std::mutex> g(g_ws_mu);
+      w = g_ws[dev];
+    }
+    if (!w || hipSetDevice(dev) != hipSuccess) continue;
+    std::lock_guard<std::mutex> g(w->mu);
+    (void)hipDeviceSynchronize();
+    release_all(w);
+  }
+  if (restore) (void)hipSetDevice(prev);
+}
+
 // nbuf: FP64 n_pad x n_pad buffers the call needs (3, or 4 for the P_{m,m} and P_{i,j}
 // schemes).
 static int ensure_workspace(Workspace* w, int64_t np, int lp_bytes, int partial_need,
@@ -353,11 +403,13 @@ int snf_release_workspace(void) {
   return SNF_OK;
 }
 
-int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_params* params,
-                     snf_scheme scheme, snf_precision precision, double* D_dev,
-                     snf_result* out, snf_log_rec* log, int32_t log_cap, void* stream) {
-  if (!out) return SNF_EINVAL;
-  memset(out, 0, sizeof(*out));
+}  // extern "C"
+
+namespace snf {
+static int purify_dense_body(const double* F_dev, int64_t n, int64_t ld,
+                             const snf_params* params, snf_scheme scheme,
+                             snf_precision precision, double* D_dev, snf_result* out,
+                             snf_log_rec* log, int32_t log_cap, void* stream) {
   int rc = validate(n, params, scheme, precision);
   if (rc == SNF_OK && (!F_dev || !D_dev || ld < n || (const void*)F_dev == (const void*)D_dev))
     rc = SNF_EINVAL;
@@ -493,6 +545,28 @@ int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_param
   }
   return status;
 }
+}  // namespace snf
+
+extern "C" {
+
+int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_params* params,
+                     snf_scheme scheme, snf_precision precision, double* D_dev,
+                     snf_result* out, snf_log_rec* log, int32_t log_cap, void* stream) {
+  if (!out) return SNF_EINVAL;
+  memset(out, 0, sizeof(*out));
+  // every return path, HIP errors included, leaves its code in out->status
+  const int rc = purify_dense_body(F_dev, n, ld, params, scheme, precision, D_dev, out, log,
+                                   log_cap, stream);
+  out->status = rc;
+  return rc;
+}
+
+int snf_shutdown(void) {
+  dense_release_all_devices();
+  bsr_release_all_devices();
+  bounds_release_all_devices();
+  return SNF_OK;
+}
 
 int snf_step_dense(const double* A_dev, const double* B_dev, int64_t n, int64_t ld, double c2,
                    double c1, double c0, snf_precision precision, double* Y_dev, double* sums,
@@ -509,7 +583,9 @@ int snf_step_dense(const double* A_dev, const double* B_dev, int64_t n, int64_t 
   if (!w) return SNF_EDEVICE;
   std::lock_guard<std::mutex> guard(w->mu);
   const int64_t np = round_up(n, kTile);
-  const int sym = 1;
+  // A.A is symmetric: the upper triangle of tiles, mirrored.  A.B of two symmetric operands
+  // that need not commute is not: every tile, no mirror.
+  const int sym = (const void*)A_dev == (const void*)B_dev ? 1 : 0;
   const int tiles = num_product_tiles(np, sym);
   int rc = ensure_workspace(w, np, lowp_bytes_for(precision), tiles + 16 * kSplitCap);
   if (rc != SNF_OK) return rc;

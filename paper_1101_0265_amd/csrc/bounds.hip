@@ -444,6 +444,27 @@ static int run_lanczos(BoundsWorkspace* w, int64_t n, int64_t np, int nv, int st
 }
 
 }  // namespace
+
+void bounds_release_all_devices() {
+  int prev = 0;
+  const bool restore = hipGetDevice(&prev) == hipSuccess;
+  for (int dev = 0; dev < 64; ++dev) {
+    BoundsWorkspace* w = nullptr;
+    {
+      std::lock_guard<std::mutex> g(g_bd_mu);
+      w = g_bd[dev];
+    }
+    if (!w || hipSetDevice(dev) != hipSuccess) continue;
+    std::lock_guard<std::mutex> g(w->mu);
+    (void)hipDeviceSynchronize();
+    release(w);
+    if (w->host) (void)hipHostFree(w->host);
+    w->host = nullptr;
+    w->host_cap = 0;
+  }
+  if (restore) (void)hipSetDevice(prev);
+}
+
 }  // namespace snf
 
 using namespace snf;

@@ -742,6 +742,46 @@ static BsrWorkspace* bsr_workspace() {
   return g_bsr_ws[dev];
 }
 
+void bsr_release_all_devices() {
+  int prev = 0;
+  const bool restore = hipGetDevice(&prev) == hipSuccess;
+  for (int dev = 0; dev < 64; ++dev) {
+    BsrWorkspace* w = nullptr;
+    {
+      std::lock_guard<std::mutex> g(g_bsr_mu);
+      w = g_bsr_ws[dev];
+    }
+    if (!w || hipSetDevice(dev) != hipSuccess) continue;
+    std::lock_guard<std::mutex> g(w->mu);
+    (void)hipDeviceSynchronize();
+    for (BsrBuf* b : {&w->X[0], &w->X[1], &w->P, &w->Fl}) b->release();
+    w->normP.release();
+    w->partials.release();
+    w->sums.release();
+    w->nrmX.release();
+    w->cnt.release();
+    w->rank.release();
+    w->tiles.release();
+    w->triples.release();
+    w->flags.release();
+    w->hist.release();
+    if (w->state) (void)hipFree(w->state);
+    w->state = nullptr;
+    if (w->state_host) (void)hipHostFree(w->state_host);
+    w->state_host = nullptr;
+    if (w->pinned) (void)hipHostFree(w->pinned);
+    w->pinned = nullptr;
+    w->pinned_cap = 0;
+    if (w->hist_host) (void)hipHostFree(w->hist_host);
+    w->hist_host = nullptr;
+    for (int i = 0; i < 4; ++i) {
+      if (w->ev[i]) (void)hipEventDestroy(w->ev[i]);
+      w->ev[i] = nullptr;
+    }
+  }
+  if (restore) (void)hipSetDevice(prev);
+}
+
 static int ensure_pinned(BsrWorkspace* w, size_t bytes) {
   if (bytes <= w->pinned_cap) return SNF_OK;
   if (w->pinned) (void)hipHostFree(w->pinned);
@@ -1057,12 +1097,10 @@ static double error_control_eps(const SnfState* sh, double eps, int n_pred) {
 }
 }  // namespace snf
 
-int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme,
-                   double trunc_tau, snf_bsr** D_out, snf_result* out, snf_log_rec* log,
-                   int32_t log_cap, void* stream) {
-  if (!out) return SNF_EINVAL;
-  memset(out, 0, sizeof(*out));
-  if (D_out) *D_out = nullptr;
+namespace snf {
+static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_scheme scheme,
+                           double trunc_tau, snf_bsr** D_out, snf_result* out,
+                           snf_log_rec* log, int32_t log_cap, void* stream) {
   auto fail = [&](int rc) {
     out->status = rc;
     return rc;
@@ -1184,6 +1222,19 @@ int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme
   out->flops = flops;
   out->blocks = w->X[cur].nnzb;
   return status;
+}
+}  // namespace snf
+
+int snf_purify_bsr(const snf_bsr* F, const snf_params* params, snf_scheme scheme,
+                   double trunc_tau, snf_bsr** D_out, snf_result* out, snf_log_rec* log,
+                   int32_t log_cap, void* stream) {
+  if (!out) return SNF_EINVAL;
+  memset(out, 0, sizeof(*out));
+  if (D_out) *D_out = nullptr;
+  // every return path, HIP errors included, leaves its code in out->status
+  const int rc = purify_bsr_body(F, params, scheme, trunc_tau, D_out, out, log, log_cap, stream);
+  out->status = rc;
+  return rc;
 }
 
 int snf_step_bsr(const snf_bsr* Xin, double c2, double c1, double c0, double trunc_tau,

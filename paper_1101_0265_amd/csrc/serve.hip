@@ -91,7 +91,9 @@ struct ServeRequest {
   double* F_pin = nullptr;
   double* D_pin = nullptr;
   SnfState* st_pin = nullptr;
-  Clock::time_point t_submit, t_admit, t_done;
+  // submitted; admitted (slot and memory taken); finished (the scheduler read the stop flag
+  // of its last step); done (result complete on the host)
+  Clock::time_point t_submit, t_admit, t_finish, t_done;
   int slot = -1;
   size_t off = 0, bytes = 0;
   hipEvent_t ev = nullptr;
@@ -179,6 +181,7 @@ struct snf_server {
   uint64_t next_ticket = 1;
   bool stopping = false, sched_done = false;
   int sticky_error = SNF_OK;
+  Clock::time_point t_create;      // origin of snf_serve_timeline
 };
 
 namespace snf {
@@ -189,6 +192,7 @@ static void fail_all_locked(snf_server* sv, int rc) {
     r->status = rc;
     r->result.status = rc;
     r->t_done = Clock::now();
+    if (r->t_finish < r->t_admit) r->t_finish = r->t_done;
   };
   for (ServeRequest* r : sv->slot_req)
     if (r) fail(r);
@@ -465,6 +469,7 @@ static void scheduler(snf_server* sv) {
           if (!sv->stop_stage[a]) continue;
           ServeRequest* r = sv->slot_req[active[a]];
           r->finished = true;
+          r->t_finish = Clock::now();
           finished.push_back(r);
         }
       }
@@ -531,6 +536,7 @@ int snf_serve_create(size_t hbm_budget_bytes, int32_t max_slots, snf_server** ou
   snf_server* sv = new snf_server();
   sv->budget = hbm_budget_bytes;
   sv->max_slots = max_slots;
+  sv->t_create = Clock::now();
   sv->slot_req.assign(max_slots, nullptr);
   size_t pin = hbm_budget_bytes / 4;
   if (pin < ((size_t)64 << 20)) pin = (size_t)64 << 20;
@@ -652,6 +658,21 @@ int snf_serve_timing(snf_server* sv, uint64_t ticket, double* ms) {
   ms[0] = ms_t(r->t_admit - r->t_submit).count();
   ms[1] = ms_t(r->t_done - r->t_admit).count();
   ms[2] = ms_t(r->t_done - r->t_submit).count();
+  return SNF_OK;
+}
+
+int snf_serve_timeline(snf_server* sv, uint64_t ticket, double* t) {
+  if (!sv || !t) return SNF_EINVAL;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->by_ticket.find(ticket);
+  if (it == sv->by_ticket.end()) return SNF_EINVAL;
+  ServeRequest* r = it->second;
+  if (r->status == SNF_PENDING) return SNF_PENDING;
+  using ms_t = std::chrono::duration<double, std::milli>;
+  t[0] = ms_t(r->t_submit - sv->t_create).count();
+  t[1] = ms_t(r->t_admit - sv->t_create).count();
+  t[2] = ms_t(r->t_finish - sv->t_create).count();
+  t[3] = ms_t(r->t_done - sv->t_create).count();
   return SNF_OK;
 }
 

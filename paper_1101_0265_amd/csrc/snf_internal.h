@@ -172,6 +172,13 @@ void launch_sum_partials(const double* partials, int count, double* out3, hipStr
 
 int num_product_tiles(int64_t np, int sym);
 
+// Release every per-device workspace of one translation unit (device buffers, pinned host
+// memory, events), each with its device current; the workspaces are set up again on their
+// next use.  snf_shutdown calls all three.
+void dense_release_all_devices();
+void bsr_release_all_devices();
+void bounds_release_all_devices();
+
 // Host helpers of the dense driver, shared with the serving loop (api_dense.hip).
 int validate(int64_t n, const snf_params* p, snf_scheme scheme, snf_precision prec);
 void init_state(SnfState* s, int64_t n, const snf_params* p, snf_scheme scheme,

@@ -7,6 +7,7 @@ fallback implementation.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from typing import Optional
@@ -114,6 +115,10 @@ def lib() -> ctypes.CDLL:
     L.snf_serve_poll.restype = ctypes.c_int
     L.snf_serve_timing.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
     L.snf_serve_timing.restype = ctypes.c_int
+    L.snf_serve_timeline.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+    L.snf_serve_timeline.restype = ctypes.c_int
+    L.snf_shutdown.argtypes = []
+    L.snf_shutdown.restype = ctypes.c_int
     L.snf_serve_destroy.argtypes = [vp]
     L.snf_serve_destroy.restype = ctypes.c_int
     L.snf_workspace_bytes.argtypes = [i64, i32]
@@ -129,6 +134,9 @@ def lib() -> ctypes.CDLL:
     L.snf_version.argtypes = []
     L.snf_version.restype = ctypes.c_char_p
     _lib = L
+    # free the library's device and pinned memory while the HIP runtime is still up: Python
+    # runs atexit handlers before the C runtime's exit handlers, where HIP tears down
+    atexit.register(L.snf_shutdown)
     return L
 
 
@@ -418,6 +426,14 @@ class Server:
         if rc != OK:
             raise RuntimeError(f"snf_serve_timing: {strerror(rc)} ({rc})")
         return ms[0], ms[1], ms[2]
+
+    def timeline(self, ticket: int) -> tuple:
+        """(submitted, admitted, finished, done) in ms since the server was created."""
+        t = (ctypes.c_double * 4)()
+        rc = lib().snf_serve_timeline(self._h, ticket, t)
+        if rc != OK:
+            raise RuntimeError(f"snf_serve_timeline: {strerror(rc)} ({rc})")
+        return t[0], t[1], t[2], t[3]
 
     def wait(self, ticket: int, timeout_s: float = 120.0, sleep_s: float = 2e-4):
         import time

@@ -3,8 +3,10 @@
 * a request's D is bitwise the same alone and in a mix of requests of other sizes, schemes
   and precisions submitted before, with and after it;
 * results match the FP64 oracle (decisions, products, D within 1e-8 sqrt(n) in FP64 mode);
-* admission respects the memory budget: with room for one request at a time the run
-  intervals do not overlap; a request larger than the budget fails at submit.
+* admission respects the memory budget: with room for one request at a time, a request is
+  admitted only after the previous one has finished (the scheduler has seen the stop flag of
+  its last step), so their runs on the device do not overlap; a request larger than the budget
+  fails at submit.
 """
 import math
 
@@ -98,9 +100,16 @@ def test_budget_serialises_admission(snf):
             o = dense.purify(h.F, "snf_varmu", **_kw(h))
             assert np.linalg.norm(D - o["D"]) <= 1e-8 * math.sqrt(n)
         times = [sv.timing(t) for t in tickets]
+        line = [sv.timeline(t) for t in tickets]
         with pytest.raises(RuntimeError):                  # larger than the whole budget
             sv.submit(_req(900, 400, seed=9).F, "snf_varmu", "fp64",
                       **_kw(_req(900, 400, seed=9)))
+    for sub, adm, fin, done in line:
+        assert sub <= adm <= fin <= done
+    # the runs [admitted, finished] follow one another: each request was admitted only after
+    # the previous one finished
+    for k in range(len(line) - 1):
+        assert line[k + 1][1] >= line[k][2], (k, line[k], line[k + 1])
     # queued time grows along the FIFO: each request waited for the previous one
     q = [t[0] for t in times]
     assert q[1] > 0 and q[3] > q[1]
