@@ -76,6 +76,7 @@ extern "C" {
 #define SNF_ENONFINITE -4   /* a non-finite value appeared in X (bad input or bounds)         */
 #define SNF_EMIXED     -5   /* converged, but |tr D - n_occ| >= 0.5: states were mixed        */
 #define SNF_EDEVICE    -6   /* a HIP runtime call failed                                      */
+#define SNF_ESIZE      -7   /* snf_purify_dense_noalloc: order above SNF_NOALLOC_MAX_N         */
 
 /* ---- schemes and precision modes ------------------------------------------------------- */
 typedef enum {
@@ -209,6 +210,31 @@ typedef struct {
 int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_params* params,
                      snf_scheme scheme, snf_precision precision, double* D_dev,
                      snf_result* out, snf_log_rec* log, int32_t log_cap, void* stream);
+
+/*
+ * snf_purify_dense_noalloc -- snf_purify_dense for callers that cannot allocate: code under
+ * HIP stream capture, tight serving loops, harnesses that forbid hipMalloc.  The call makes
+ * no allocation at all (no hipMalloc / hipHostMalloc / hipFree, no events, nothing from
+ * torch): all device memory beyond F and D comes from a fixed array of
+ * SNF_NOALLOC_SCRATCH_BYTES that the library's code object holds on every device it is loaded
+ * on, until the process ends.  Same arguments, results and errors as snf_purify_dense, bit
+ * for bit (the same kernels on the same decomposition), restricted to:
+ *   - precision SNF_P_FP64 and the schemes other than SNF_SNF_FIXMU_PIJ / SNF_PIJ
+ *     (SNF_EINVAL otherwise);
+ *   - n rounded up to a multiple of 128 at most SNF_NOALLOC_MAX_N (SNF_ESIZE otherwise).
+ * The first call on a device looks up the array's device address (hipGetSymbolAddress).
+ * Calls on one device share the array: the library serialises them with a per-device lock
+ * within the process; work enqueued by such a call must not overlap another one's (it does
+ * not: the call is synchronous).  Nothing carries over between calls (every buffer is written
+ * before it is read).  snf_result.device_ms comes from the device's wall clock; the
+ * SNF_FLAG_TIME_PRODUCTS flag is ignored (product_ms = 0).
+ */
+#define SNF_NOALLOC_MAX_N 896
+#define SNF_NOALLOC_SCRATCH_BYTES (26u << 20)
+int snf_purify_dense_noalloc(const double* F_dev, int64_t n, int64_t ld,
+                             const snf_params* params, snf_scheme scheme,
+                             snf_precision precision, double* D_dev, snf_result* out,
+                             snf_log_rec* log, int32_t log_cap, void* stream);
 
 /*
  * snf_step_dense -- one purification step on a dense symmetric X, the unit of work of the

@@ -29,6 +29,8 @@ static int dev_error(hipError_t e, const char* what) {
   return SNF_EDEVICE;
 }
 
+int record_hip_error(hipError_t e, const char* what) { return dev_error(e, what); }
+
 #define SNF_HIP(call)                                  \
   do {                                                 \
     hipError_t _e = (call);                            \
@@ -379,6 +381,7 @@ const char* snf_strerror(int status) {
     case SNF_ENONFINITE: return "non-finite value in the iteration";
     case SNF_EMIXED: return "converged to a projector with the wrong occupation";
     case SNF_EDEVICE: return g_err_text[0] ? g_err_text : "HIP runtime error";
+    case SNF_ESIZE: return "order above the no-allocation entry point's maximum";
     default: return "unknown status";
   }
 }

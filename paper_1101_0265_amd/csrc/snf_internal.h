@@ -172,6 +172,9 @@ void launch_sum_partials(const double* partials, int count, double* out3, hipStr
 
 int num_product_tiles(int64_t np, int sym);
 
+// Keep the text of a failed HIP call for snf_strerror(SNF_EDEVICE); returns SNF_EDEVICE.
+int record_hip_error(hipError_t e, const char* what);
+
 // Release every per-device workspace of one translation unit (device buffers, pinned host
 // memory, events), each with its device current; the workspaces are set up again on their
 // next use.  snf_shutdown calls all three.

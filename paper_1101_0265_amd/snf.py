@@ -17,10 +17,11 @@ LIB_PATH = os.path.join(PKG, "libsnf.so")
 
 # ---- status codes, schemes, precisions (mirror include/snf.h) ----------------------------
 OK, PENDING, OK_FLOOR = 0, 1, 2
-EINVAL, ENOMEM, ENOCONV, ENONFINITE, EMIXED, EDEVICE = -1, -2, -3, -4, -5, -6
+EINVAL, ENOMEM, ENOCONV, ENONFINITE, EMIXED, EDEVICE, ESIZE = -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {OK: "ok", PENDING: "pending", OK_FLOOR: "ok_floor", EINVAL: "einval",
                 ENOMEM: "enomem", ENOCONV: "noconv", ENONFINITE: "nonfinite", EMIXED: "mixed",
-                EDEVICE: "edevice"}
+                EDEVICE: "edevice", ESIZE: "esize"}
+NOALLOC_MAX_N = 896
 
 SCHEMES = {"sp2": 0, "tc2": 1, "snf_varmu": 2, "mcweeny": 3, "snf_fixmu": 4,
            "snf_fixmu3": 5, "snf_fixmu5": 6, "pmm3": 7, "pmm5": 8, "snf_pij": 9, "pij": 10}
@@ -84,6 +85,8 @@ def lib() -> ctypes.CDLL:
     L.snf_purify_dense.argtypes = [vp, i64, i64, ctypes.POINTER(Params), i32, i32, vp,
                                    ctypes.POINTER(Result), ctypes.POINTER(LogRec), i32, vp]
     L.snf_purify_dense.restype = ctypes.c_int
+    L.snf_purify_dense_noalloc.argtypes = L.snf_purify_dense.argtypes
+    L.snf_purify_dense_noalloc.restype = ctypes.c_int
     L.snf_step_dense.argtypes = [vp, vp, i64, i64, dbl, dbl, dbl, i32, vp,
                                  ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double), vp]
