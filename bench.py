@@ -830,7 +830,11 @@ def main():
                          "workloads")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for hardware-counter runs: a plain 512 MiB device copy (counter "
-                         "calibration), then three FP64 products of the workload's X_0")
+                         "calibration), then three stand-alone products X.X: the workload's "
+                         "X_0 at n=4096, or a seeded symmetric matrix of order --probe-n")
+    ap.add_argument("--probe-n", type=int, default=4096)
+    ap.add_argument("--probe-precision", default="fp64",
+                    choices=["fp64", "fp32", "bf16_ref64"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the method's "
@@ -866,13 +870,25 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        lmax, lmin = h.lambda_max, h.lambda_min
-        X0 = (lmax * torch.eye(n, dtype=torch.float64, device=dev) - F) / (lmax - lmin)
+        if args.probe_n == n:
+            lmax, lmin = h.lambda_max, h.lambda_min
+            X0 = (lmax * torch.eye(n, dtype=torch.float64, device=dev) - F) / (lmax - lmin)
+        else:   # a seeded symmetric matrix of the requested order (timing does not depend on
+                # the values)
+            g = torch.Generator(device=dev)
+            g.manual_seed(8)
+            Z = torch.randn(args.probe_n, args.probe_n, generator=g, device=dev,
+                            dtype=torch.float64)
+            X0 = (Z + Z.T) / (2.0 * math.sqrt(args.probe_n))
+            del Z
+        kms = []
         for _ in range(3):
-            snf.step_dense(X0, X0, 1.0, 0.0, 0.0, "fp64")
+            kms.append(snf.step_dense(X0, X0, 1.0, 0.0, 0.0, args.probe_precision)[2])
         torch.cuda.synchronize()
         print(json.dumps({"traffic_probe": True, "copy_bytes": src.numel() * 8,
-                          "n": n, "kernel_source_hash": kernel_source_hash()}), flush=True)
+                          "n": args.probe_n, "precision": args.probe_precision,
+                          "kernel_ms": kms, "kernel_source_hash": kernel_source_hash()}),
+              flush=True)
         return
 
     def solve(scheme, flags=0):
