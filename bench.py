@@ -216,23 +216,30 @@ def run_precision(args):
         runs = [("snf_varmu", "fp64", 0.0), ("sp2", "fp64", 0.0), ("snf_fixmu", "fp64", 0.0),
                 ("snf_varmu", "fp32_ref64", 0.0), ("snf_varmu", "fp32_ref64", 0.5),
                 ("snf_varmu", "bf16_ref64", 0.5)]
+    # the FP32 and BF16 modes again with the subspace correction (one Newton step that
+    # re-references F, then FP64 refinement)
+    runs = [(sc, pr, g, 0) for sc, pr, g in runs] + [
+        ("snf_varmu", "fp32_ref64", 0.0, snf.FLAG_SUBSPACE_NEWTON),
+        ("snf_varmu", "fp32_ref64", 0.5, snf.FLAG_SUBSPACE_NEWTON),
+        ("snf_varmu", "bf16_ref64", 0.5, snf.FLAG_SUBSPACE_NEWTON)]
     out = {}
-    for scheme, prec, gsw in runs:
-        snf.purify_dense(F, scheme, prec, out=D, want_log=False, gap_switch=gsw, **kw)
+    for scheme, prec, gsw, fl in runs:
+        snf.purify_dense(F, scheme, prec, out=D, want_log=False, gap_switch=gsw, flags=fl, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         steps = max(1, args.steps)
         for _ in range(steps):
-            _, r = snf.purify_dense(F, scheme, prec, out=D, want_log=False, gap_switch=gsw, **kw)
+            _, r = snf.purify_dense(F, scheme, prec, out=D, want_log=False, gap_switch=gsw,
+                                    flags=fl, **kw)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
         err = float(torch.linalg.norm(D - D_exact))
         comm = float(torch.linalg.norm(F @ D - D @ F))
-        out[f"{scheme}/{prec}/gsw{gsw}"] = dict(
+        out[f"{scheme}/{prec}/gsw{gsw}" + ("/newton" if fl else "")] = dict(
             ms=round(ms, 2), status=r["status"], products=r["products"],
             products_fp64=r["products_fp64"], products_lowp=r["products_lowp"],
-            idem_err=r["idem_err"], trace_err=r["trace_err"], dist_to_exact_D=err,
-            commutator=comm)
+            products_newton=r["products_newton"], idem_err=r["idem_err"],
+            trace_err=r["trace_err"], dist_to_exact_D=err, commutator=comm)
     flops_one = float(n) * n * (n + 1)
     # FP64 product kernel: every product of the FP64 scale-and-fold solve timed
     _, r64 = snf.purify_dense(F, "snf_varmu", "fp64", out=D, want_log=False,

@@ -113,6 +113,9 @@ typedef enum {
                                      their summed duration in snf_result.product_ms         */
 #define SNF_FLAG_TRUNC_ERROR_CONTROL 2  /* snf_purify_bsr: trunc_tau is an error budget for
                                      ||D - D_exact||_F, not a per-block threshold (below)   */
+#define SNF_FLAG_SUBSPACE_NEWTON 4  /* snf_purify_dense: after the solve, one Newton step on
+                                     the occupied subspace that re-references F, then FP64
+                                     refinement (see snf_purify_dense)                      */
 
 /*
  * Inputs of a purification (Algorithm 1 and the P_{m,m} schemes need lambda_min, lambda_max,
@@ -180,7 +183,7 @@ typedef struct {
   int32_t products;       /* matrix-matrix products, the certifying one included        */
   int32_t products_fp64;  /* ... of which FP64                                          */
   int32_t products_lowp;  /* ... of which FP32 or BF16                                  */
-  int32_t reserved;
+  int32_t products_newton;/* ... of which the subspace correction and its refinement    */
   double idem_err;        /* ||D^2 - D||_F (from the certifying product)                */
   double trace;           /* tr D                                                       */
   double trace_err;       /* tr D - n_occ (0 if n_occ unknown)                          */
@@ -206,6 +209,20 @@ typedef struct {
  *           snf_log_rec records.
  *   out:    host struct, filled on return (required).
  * Synchronous: returns after D and the result are complete.
+ *
+ * SNF_FLAG_SUBSPACE_NEWTON (not in the paper, for the precision modes): low-precision
+ * products leave the occupied subspace slightly rotated, and refinement by purification,
+ * being a function of the iterate alone, cannot see it.  With the flag, the solve's result
+ * D~ gets one Newton step that re-references F: with G = f_0(F) of Algorithm 2, W = G D~ and
+ * M = D~ G D~ (FP64 products), G splits into G - V, which commutes with D~ and has D~ as its
+ * projector, and the coupling V = W + W^T - 2 M; the first-order change of the projector along
+ * V comes from running Algorithm 2's polynomial sequence (from the gap-edge bounds, until
+ * max(beta, 1 - beta-bar) <= 1e-10) on G - V while carrying its derivative along
+ * (X1 <- c2 (X X1 + X1 X) + c1 X1, one product X X1 per step, in FP32 unless precision is
+ * SNF_P_FP64); D~ + X1 is then refined by trace-correcting FP64 steps to tol.  The error left
+ * is of second order in the rotation.  Needs n_occ >= 0 and gap edges (homo/lumo, or
+ * mu -/+ xi/2); SNF_EINVAL otherwise.  out: the solve's decisions and log; products and flops
+ * include the correction; idem_err, trace and status are the refinement's.
  */
 int snf_purify_dense(const double* F_dev, int64_t n, int64_t ld, const snf_params* params,
                      snf_scheme scheme, snf_precision precision, double* D_dev,

@@ -14,6 +14,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -57,6 +58,15 @@ struct Workspace {
   double* sums_host = nullptr;       // pinned
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> prod_ev;
+  // subspace correction: five FP64 buffers of order nnp, FP32 copies of four of them, the
+  // Buffers tables and the planned product sequence on the device
+  int64_t nnp = 0;
+  bool nlp_on = false;
+  double* nx[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  float* nlp[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  Buffers* nbufs_dev = nullptr;      // [4] tables
+  NewtonOp* nops_dev = nullptr;
+  int nops_cap = 0;
   std::mutex mu;
 };
 
@@ -86,8 +96,25 @@ static void free_buffers(Workspace* w) {
 // Every resource of a workspace: device buffers, pinned host memory, events.  The object
 // itself stays (another thread may be waiting on its mutex) and is set up again on its next
 // use.  Called with w->mu held and the workspace's device current.
+static void free_newton(Workspace* w) {
+  for (int i = 0; i < 5; ++i) {
+    if (w->nx[i]) (void)hipFree(w->nx[i]);
+    if (w->nlp[i]) (void)hipFree(w->nlp[i]);
+    w->nx[i] = nullptr;
+    w->nlp[i] = nullptr;
+  }
+  w->nnp = 0;
+  w->nlp_on = false;
+}
+
 static void release_all(Workspace* w) {
   free_buffers(w);
+  free_newton(w);
+  if (w->nbufs_dev) (void)hipFree(w->nbufs_dev);
+  w->nbufs_dev = nullptr;
+  if (w->nops_dev) (void)hipFree(w->nops_dev);
+  w->nops_dev = nullptr;
+  w->nops_cap = 0;
   if (w->x[3]) (void)hipFree(w->x[3]);
   w->x[3] = nullptr;
   if (w->partials) (void)hipFree(w->partials);
@@ -277,6 +304,15 @@ int validate(int64_t n, const snf_params* p, snf_scheme scheme, snf_precision pr
       if (!(p->xi < sched::alg1_gamma(p->lambda_min, p->lambda_max, p->mu))) return SNF_EINVAL;
       break;
   }
+  if (p->flags & SNF_FLAG_SUBSPACE_NEWTON) {
+    // the correction follows Algorithm 2's sequence between gap edges and refines by the
+    // trace rule
+    const bool edges = (gap_edges) ||
+                       (finite(p->mu) && finite(p->xi) && p->xi > 0.0 &&
+                        p->lambda_min <= p->mu - 0.5 * p->xi &&
+                        p->mu + 0.5 * p->xi <= p->lambda_max);
+    if (!edges || p->n_occ < 0) return SNF_EINVAL;
+  }
   if (prec != SNF_P_FP64) {
     if (!finite(p->gap_switch) || p->gap_switch < 0.0 || p->gap_switch > 1.0) return SNF_EINVAL;
     if (!finite(p->lowp_floor) || p->lowp_floor < 0.0 || p->lowp_floor >= 0.5) return SNF_EINVAL;
@@ -400,6 +436,7 @@ int snf_release_workspace(void) {
   if (!w) return SNF_EDEVICE;
   std::lock_guard<std::mutex> g(w->mu);
   free_buffers(w);
+  free_newton(w);
   if (w->partials) (void)hipFree(w->partials);
   w->partials = nullptr;
   w->partial_cap = 0;
@@ -409,6 +446,191 @@ int snf_release_workspace(void) {
 }  // extern "C"
 
 namespace snf {
+// ---- subspace correction ------------------------------------------------------------------
+// After a solve, one Newton step on the occupied subspace of its result D~ that re-references
+// F (not in the paper: a low-precision solve followed by refinement by purification leaves a
+// rotation of the subspace that no function of the iterate can see).  With G = f_0(F) (the
+// map of Algorithm 2) split with respect to D~ into the part that commutes with D~ and the
+// coupling V = W + W^T - 2 M (W = G D~, M = D~ G D~), D~ is the projector of G - V, and the
+// first-order change of the projector along V is obtained by running Algorithm 2's polynomial
+// sequence on X_0 = G - V while carrying its derivative X1 along (X1_0 = V,
+// X1 <- c2 (X X1 + X1 X) + c1 X1, X X1 from one product whose transpose is X1 X).  Then
+// D = D~ + X1 is refined by trace-correcting FP64 steps to tol.  W, M and the refinement run in
+// FP64; the response products in FP32 unless the solve was FP64 (their relative error only
+// enters at second order).
+constexpr int kNewtonMaxIter = 120;     // steps of the response recurrence at most
+constexpr double kNewtonEps = 1e-10;    // ... until max(beta, 1 - beta-bar) <= this
+
+struct NewtonStats {
+  int products_f64 = 0, products_lowp = 0, launches = 0;
+  double flops = 0.0;
+};
+
+static int ensure_newton(Workspace* w, int64_t np, bool lp, int nops) {
+  if (np > w->nnp || (lp && !w->nlp_on)) {
+    free_newton(w);
+    const size_t elems = (size_t)np * (size_t)np;
+    for (int i = 0; i < 5; ++i) {
+      if (hipMalloc(&w->nx[i], elems * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        free_newton(w);
+        return SNF_ENOMEM;
+      }
+      if (lp && i != 1 && hipMalloc(&w->nlp[i], elems * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        free_newton(w);
+        return SNF_ENOMEM;
+      }
+    }
+    w->nnp = np;
+    w->nlp_on = lp;
+  }
+  if (!w->nbufs_dev) SNF_HIP(hipMalloc(&w->nbufs_dev, 4 * sizeof(Buffers)));
+  if (nops > w->nops_cap) {
+    if (w->nops_dev) (void)hipFree(w->nops_dev);
+    w->nops_dev = nullptr;
+    w->nops_cap = 0;
+    SNF_HIP(hipMalloc(&w->nops_dev, (size_t)nops * sizeof(NewtonOp)));
+    w->nops_cap = nops;
+  }
+  return SNF_OK;
+}
+
+// Gap edges of the correction's polynomial sequence: the given bounds, else mu -/+ xi / 2.
+static bool newton_edges(const snf_params* p, double* homo, double* lumo) {
+  if (isfinite(p->homo) && isfinite(p->lumo) && p->homo < p->lumo) {
+    *homo = p->homo;
+    *lumo = p->lumo;
+  } else if (isfinite(p->mu) && isfinite(p->xi) && p->xi > 0.0) {
+    *homo = p->mu - 0.5 * p->xi;
+    *lumo = p->mu + 0.5 * p->xi;
+  } else {
+    return false;
+  }
+  return p->lambda_min <= *homo && *lumo <= p->lambda_max;
+}
+
+// (c2, c1, c0) of Algorithm 2's steps until max(beta, 1 - beta-bar) <= eps (the same FP64
+// recurrence as the device schedule).
+static void newton_steps(double lmin, double lmax, double homo, double lumo, double eps,
+                         std::vector<double>& c) {
+#pragma clang fp contract(off)
+  double beta = sched::alg2_f0(lumo, lmin, lmax), betabar = sched::alg2_f0(homo, lmin, lmax);
+  for (int it = 0; it < kNewtonMaxIter; ++it) {
+    const double bound = beta > 1.0 - betabar ? beta : 1.0 - betabar;
+    if (bound <= eps) break;
+    const bool sq = sched::alg2_square(beta, betabar);
+    const double a = sq ? sched::alg2_square_alpha(beta) : sched::alg2_fold_alpha(betabar);
+    if (sq) {
+      c.push_back((1.0 + a) * (1.0 + a));
+      c.push_back(-2.0 * a * (1.0 + a));
+      c.push_back(a * a);
+      beta = sched::alg2_square_map(beta, a);
+      betabar = sched::alg2_square_map(betabar, a);
+    } else {
+      c.push_back(-((1.0 + a) * (1.0 + a)));
+      c.push_back(2.0 * (1.0 + a));
+      c.push_back(0.0);
+      beta = sched::alg2_fold_map(beta, a);
+      betabar = sched::alg2_fold_map(betabar, a);
+    }
+  }
+}
+
+// Runs the correction on the solve's result (buffer x[cur] of the workspace) and leaves in
+// w->state the state of the refinement that follows, ready for its step loop (the caller's),
+// with the corrected, not yet refined D in buffer x[target], target 0 or 1 and != cur.
+static int newton_correct(Workspace* w, const double* F_dev, int64_t n, int64_t ld, int64_t np,
+                          const snf_params* p, snf_precision prec, int cur, int target,
+                          hipStream_t s, NewtonStats* ns) {
+  if ((target != 0 && target != 1) || target == cur) return SNF_EINVAL;
+  double homo = 0.0, lumo = 0.0;
+  if (!newton_edges(p, &homo, &lumo)) return SNF_EINVAL;
+  std::vector<double> c;
+  newton_steps(p->lambda_min, p->lambda_max, homo, lumo, kNewtonEps, c);
+  const int N = (int)(c.size() / 3);
+  const int cp = prec == SNF_P_FP64 ? kPrecF64 : kPrecF32;
+  const bool lp = cp == kPrecF32;
+  int rc = ensure_newton(w, np, lp, 2 + 2 * N);
+  if (rc != SNF_OK) return rc;
+  double* const* X = w->nx;
+  float* const* L = w->nlp;
+  // Buffers tables: 0 f_0 -> G; 1 W = G D~, M = D~ W; 2 / 3 the even / odd iterations
+  Buffers t[4];
+  memset(t, 0, sizeof(t));
+  t[0].x[0] = X[0];
+  t[1].x[0] = X[0];
+  t[1].x[1] = w->x[cur];
+  t[1].x[2] = X[1];
+  t[1].x[3] = X[2];
+  const int xa[2] = {3, 0}, x1a[2] = {4, 2};       // X and X1 of an even / odd iteration
+  for (int par = 0; par < 2; ++par) {
+    Buffers& b = t[2 + par];
+    b.x[0] = X[xa[par]];
+    b.x[1] = X[x1a[par]];
+    b.x[2] = X[1];                                   // Z = X X1
+    b.x[3] = X[xa[1 - par]];                         // the next X
+    b.lp[0] = L[xa[par]];
+    b.lp[1] = L[x1a[par]];
+    b.lp[3] = L[xa[1 - par]];
+  }
+  std::vector<NewtonOp> ops;
+  ops.push_back(NewtonOp{0, 1, 0, 2, kPrecF64, 0, 1.0, 0.0, 0.0});     // W = G D~
+  ops.push_back(NewtonOp{1, 2, 1, 3, kPrecF64, 0, 1.0, 0.0, 0.0});     // M = D~ W
+  for (int i = 0; i < N; ++i) {
+    ops.push_back(NewtonOp{0, 1, 0, 2, cp, 0, 1.0, 0.0, 0.0});         // Z = X X1
+    ops.push_back(NewtonOp{0, 0, 0, 3, cp, lp ? 1 : 0, c[3 * i], c[3 * i + 1], c[3 * i + 2]});
+  }
+  SNF_HIP(hipMemcpyAsync(w->nbufs_dev, t, sizeof(t), hipMemcpyHostToDevice, s));
+  SNF_HIP(hipMemcpyAsync(w->nops_dev, ops.data(), ops.size() * sizeof(NewtonOp),
+                         hipMemcpyHostToDevice, s));
+  // the product kernels read the state: Algorithm 2's f_0 map, FP32 copies as FP32
+  SnfState* sh = w->state_host;
+  init_state(sh, n, p, SNF_SNF_VARMU, SNF_P_FP32_REF64);
+  sh->homo = homo;
+  sh->lumo = lumo;
+  sh->cur = 0;
+  SNF_HIP(hipMemcpyAsync(w->state, sh, sizeof(SnfState), hipMemcpyHostToDevice, s));
+  SNF_HIP(hipStreamSynchronize(s));                  // the host staging is reused below
+
+  const ProductGrid g0 = make_product_grid(np, n, 0, w->num_cus, w->partials, w->split_buf,
+                                           kSplitCap, stage_depth_for(prec));
+  const ProductGrid g1 = make_product_grid(np, n, 1, w->num_cus, w->partials, w->split_buf,
+                                           kSplitCap, stage_depth_for(prec));
+  const double nd = (double)n, full = 2.0 * nd * nd * nd, half = nd * nd * (nd + 1.0);
+  auto product = [&](int k, int tab, const ProductGrid& g) {
+    launch_newton_set(w->state, w->nops_dev, k, s);
+    launch_product(ops[k].prec, w->state, w->nbufs_dev + tab, g, s);
+    launch_split_fixup(w->state, w->nbufs_dev + tab, g, s);
+    if (ops[k].prec == kPrecF64) ns->products_f64 += 1; else ns->products_lowp += 1;
+    ns->launches += 1;
+  };
+  launch_f0(F_dev, n, ld, np, w->state, w->nbufs_dev + 0, -1, w->partials, s);
+  product(0, 1, g0);
+  product(1, 1, g1);
+  ns->flops += full + half;
+  launch_newton_split(X[0], X[1], X[2], n, np, X[3], L[3], X[4], L[4], s);
+  for (int i = 0; i < N; ++i) {
+    const int par = i & 1;
+    product(2 + 2 * i, 2 + par, g0);
+    launch_newton_sym(X[1], X[x1a[par]], c[3 * i], c[3 * i + 1], n, np, X[x1a[1 - par]],
+                      L[x1a[1 - par]], s);
+    product(3 + 2 * i, 2 + par, g1);
+    ns->flops += full + half;
+  }
+  SNF_HIP(hipGetLastError());
+  // D = D~ + X1 into the refinement's buffer, with its trace sums; then the refinement state
+  launch_newton_add(w->x[cur], X[x1a[N & 1]], n, np, w->x[target], w->partials, s);
+  init_state(sh, n, p, p->n_occ >= 0 ? SNF_SP2_TRACE : SNF_MCWEENY, SNF_P_FP32_REF64);
+  sh->phase = kPhaseRefine;
+  sh->cur = target;
+  SNF_HIP(hipMemcpyAsync(w->state, sh, sizeof(SnfState), hipMemcpyHostToDevice, s));
+  launch_schedule(w->state, w->partials, kF0Blocks, 1, s);
+  SNF_HIP(hipGetLastError());
+  SNF_HIP(hipStreamSynchronize(s));
+  return SNF_OK;
+}
+
 static int purify_dense_body(const double* F_dev, int64_t n, int64_t ld,
                              const snf_params* params, snf_scheme scheme,
                              snf_precision precision, double* D_dev, snf_result* out,
@@ -431,7 +653,10 @@ static int purify_dense_body(const double* F_dev, int64_t n, int64_t ld,
   const int64_t np = round_up(n, kTile);
   const int sym = 1;
   const int tiles = num_product_tiles(np, sym);
-  rc = ensure_workspace(w, np, lowp_bytes_for(precision), tiles + 16 * kSplitCap,
+  // (the subspace correction's full-grid products need a partial slot per tile of the grid)
+  const int slot_tiles = (params->flags & SNF_FLAG_SUBSPACE_NEWTON) ? num_product_tiles(np, 0)
+                                                                     : tiles;
+  rc = ensure_workspace(w, np, lowp_bytes_for(precision), slot_tiles + 16 * kSplitCap,
                         (scheme_pmm_m(scheme) || scheme_is_pij(scheme)) ? 4 : 3);
   if (rc != SNF_OK) {
     out->status = rc;
@@ -517,15 +742,59 @@ static int purify_dense_body(const double* F_dev, int64_t n, int64_t ld,
     stopped = flags[checked & 1] != 0;
     ++checked;
   }
+  // subspace correction of the solve's result, then its FP64 refinement
+  std::unique_ptr<SnfState> main_st;
+  NewtonStats ns;
+  if (params->flags & SNF_FLAG_SUBSPACE_NEWTON) {
+    SNF_HIP(hipMemcpyAsync(w->state_host, w->state, sizeof(SnfState), hipMemcpyDeviceToHost, s));
+    SNF_HIP(hipStreamSynchronize(s));
+    const int st0 = w->state_host->stop ? w->state_host->status : SNF_ENOCONV;
+    if (st0 == SNF_OK || st0 == SNF_OK_FLOOR) {
+      main_st.reset(new SnfState(*w->state_host));
+      // the refinement ping-pongs between buffers 0 and 1 (its steps write buffer 1 - cur), so
+      // the corrected D goes to the one of them that does not hold the solve's result
+      const int target = main_st->cur == 0 ? 1 : 0;
+      rc = newton_correct(w, F_dev, n, ld, np, params, precision, main_st->cur, target, s, &ns);
+      if (rc != SNF_OK) return rc;
+      bool rstop = false;
+      for (int renq = 0; !rstop && renq < params->max_iter + 1;) {
+        for (int k = 0; k < chunk && renq < params->max_iter + 1; ++k, ++renq) {
+          launch_product(kPrecF64, w->state, w->bufs_dev, grid, s);
+          launch_split_fixup(w->state, w->bufs_dev, grid, s);
+          launch_schedule(w->state, w->partials, grid.partial_count, 0, s);
+        }
+        SNF_HIP(hipGetLastError());
+        SNF_HIP(hipMemcpyAsync((void*)flags, &w->state->stop, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+        SNF_HIP(hipStreamSynchronize(s));
+        rstop = flags[0] != 0;
+      }
+    }
+  }
   launch_copy_out(w->state, w->bufs_dev, n, np, D_dev, ld, s);
   SNF_HIP(hipGetLastError());
   SNF_HIP(hipEventRecord(w->ev[1], s));
   SNF_HIP(hipMemcpyAsync(w->state_host, w->state, sizeof(SnfState), hipMemcpyDeviceToHost, s));
   SNF_HIP(hipStreamSynchronize(s));
 
-  const SnfState* st = w->state_host;
+  const SnfState* st = main_st ? main_st.get() : w->state_host;
   int status = st->stop ? st->status : SNF_ENOCONV;
   fill_result(st, out, log, log_cap);
+  if (main_st) {
+    // decisions and log are the solve's; counts add the correction and the refinement; the
+    // idempotency, trace and status are the refinement's
+    const SnfState* r = w->state_host;
+    status = r->stop ? r->status : SNF_ENOCONV;
+    const double nd = (double)n;
+    out->products += ns.launches + r->products;
+    out->products_fp64 += ns.products_f64 + r->products_f64;
+    out->products_lowp += ns.products_lowp + r->products_lowp;
+    out->products_newton = ns.launches + r->products;
+    out->idem_err = r->e_last;
+    out->trace = r->t1;
+    out->trace_err = r->has_nocc ? r->t1 - (double)r->n_occ : 0.0;
+    out->flops += ns.flops + (double)r->products * nd * nd * (nd + 1.0);
+  }
   out->status = status;
   float ms = 0.f;
   SNF_HIP(hipEventElapsedTime(&ms, w->ev[0], w->ev[1]));

@@ -326,6 +326,55 @@ __device__ __forceinline__ int acc_row(int lane, int v) {
   return ROWS_INTERLEAVED ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
 }
 
+// Off-diagonal tile of a symmetric product in the f32 / bf16 accumulator layout: the lane's
+// four values are rows r0 .. r0 + 3 of column c, so their mirror entries Y[c][r0 .. r0 + 3] are
+// contiguous and go out as two 16-byte stores (and one 16- or 8-byte store of the
+// low-precision copy) instead of four scattered 8-byte ones.  Same values as epi_elem.
+template <typename Acc4>
+__device__ __forceinline__ void epi_quad_mirrored(const Acc4& acc4, int64_t r0, int64_t c,
+                                                  int64_t n, int64_t np, const EpiArgs& ea,
+                                                  double& e2, double& t2) {
+  double y[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t r = r0 + v;
+    const double p = (double)acc4[v];
+    const double x = ea.Xt[r * np + c];
+    if (ea.want_e) {
+      const double d = p - x;
+      e2 += 2.0 * (d * d);
+    }
+    double yv = ea.c2 * p + ea.c1 * x;      // r != c in an off-diagonal tile
+    if (r >= n || c >= n) yv = 0.0;
+    t2 += 2.0 * (yv * yv);
+    ea.Y[r * np + c] = yv;
+    y[v] = yv;
+  }
+  double* ym = ea.Y + c * np + r0;
+  *(double2*)(ym) = double2{y[0], y[1]};
+  *(double2*)(ym + 2) = double2{y[2], y[3]};
+  if (ea.lowp_kind == kPrecF32) {
+    float* lp = (float*)ea.LPY;
+    float f[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      f[v] = (float)y[v];
+      lp[(r0 + v) * np + c] = f[v];
+    }
+    *(float4*)(lp + c * np + r0) = float4{f[0], f[1], f[2], f[3]};
+  } else if (ea.lowp_kind == kPrecBF16) {
+    unsigned short* lp = (unsigned short*)ea.LPY;
+    unsigned short b[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      b[v] = f32_to_bf16_rne((float)y[v]);
+      lp[(r0 + v) * np + c] = b[v];
+    }
+    *(uint2*)(lp + c * np + r0) = uint2{(unsigned)b[0] | ((unsigned)b[1] << 16),
+                                        (unsigned)b[2] | ((unsigned)b[3] << 16)};
+  }
+}
+
 // One 16x16 MFMA block (m, q) of the wave tile: acc4 holds its four values of this lane.
 template <bool ROWS_INTERLEAVED, bool DUAL, typename Acc4>
 __device__ __forceinline__ void epilogue_block(const Acc4& acc4, int m, int q, int gi0, int gj0,
@@ -334,6 +383,10 @@ __device__ __forceinline__ void epilogue_block(const Acc4& acc4, int m, int q, i
                                                double& t2) {
   const int lane = threadIdx.x & 63;
   const int64_t c = gj0 + q * 16 + (lane & 15);
+  if (!ROWS_INTERLEAVED && !DUAL && sym && !diag) {
+    epi_quad_mirrored(acc4, gi0 + m * 16 + acc_row<false>(lane, 0), c, n, np, ea, e2, t2);
+    return;
+  }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int64_t r = gi0 + m * 16 + acc_row<ROWS_INTERLEAVED>(lane, v);
@@ -1335,6 +1388,143 @@ __global__ void sum_partials_kernel(const double* __restrict__ partials, int cou
 void launch_sum_partials(const double* partials, int count, double* out3, hipStream_t s) {
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kReduceThreads), 0, s, partials, count,
                      out3);
+}
+
+// ---------------------------------------------------------------------------------------
+// Subspace correction (one Newton step on the occupied subspace that re-references F): the
+// elementwise parts.  Every kernel walks 32 x 32 tiles of the padded order with a grid-stride
+// loop; a tile's transposed partner is staged through LDS so that both reads are coalesced.
+// Entries outside the true order n are written as 0, like every other padded buffer.
+// ---------------------------------------------------------------------------------------
+// V = W + W^T - 2 M (the coupling of G between the subspace of D~ and its complement, with
+// W = G D~ and M = D~ G D~), X1 = V, Xbd = G - V (G's part that commutes with D~).
+__global__ __launch_bounds__(256) void newton_split_kernel(const double* __restrict__ G,
+                                                           const double* __restrict__ W,
+                                                           const double* __restrict__ M,
+                                                           int64_t n, int64_t np,
+                                                           double* __restrict__ Xbd,
+                                                           float* __restrict__ Xbd_lp,
+                                                           double* __restrict__ X1,
+                                                           float* __restrict__ X1_lp) {
+  __shared__ double wt[32][33];
+  const int64_t nt = np / 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int64_t t = blockIdx.x; t < nt * nt; t += gridDim.x) {
+    const int64_t bi = t / nt, bj = t % nt;
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) wt[r][tx] = W[(bj * 32 + r) * np + bi * 32 + tx];
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+      const int64_t gr = bi * 32 + r, gc = bj * 32 + tx;
+      const int64_t idx = gr * np + gc;
+      double v = (W[idx] + wt[tx][r]) - 2.0 * M[idx];
+      double xb = G[idx] - v;
+      if (gr >= n || gc >= n) v = xb = 0.0;
+      X1[idx] = v;
+      Xbd[idx] = xb;
+      if (X1_lp) X1_lp[idx] = (float)v;
+      if (Xbd_lp) Xbd_lp[idx] = (float)xb;
+    }
+  }
+}
+
+// X1_new = c2 (Z + Z^T) + c1 X1: the derivative of the step X <- c2 X^2 + c1 X + c0 I along
+// X1, with Z = X X1 (so Z^T = X1 X for symmetric X and X1).  Exactly symmetric.
+__global__ __launch_bounds__(256) void newton_sym_kernel(const double* __restrict__ Z,
+                                                         const double* __restrict__ X1,
+                                                         double c2, double c1, int64_t n,
+                                                         int64_t np, double* __restrict__ out,
+                                                         float* __restrict__ out_lp) {
+  __shared__ double zt[32][33];
+  const int64_t nt = np / 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int64_t t = blockIdx.x; t < nt * nt; t += gridDim.x) {
+    const int64_t bi = t / nt, bj = t % nt;
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) zt[r][tx] = Z[(bj * 32 + r) * np + bi * 32 + tx];
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+      const int64_t gr = bi * 32 + r, gc = bj * 32 + tx;
+      const int64_t idx = gr * np + gc;
+      double y = c2 * (Z[idx] + zt[tx][r]) + c1 * X1[idx];
+      if (gr >= n || gc >= n) y = 0.0;
+      out[idx] = y;
+      if (out_lp) out_lp[idx] = (float)y;
+    }
+  }
+}
+
+// out = D~ + X1 (the first-order corrected projector) and per-block FP64 sums of its trace
+// and squared Frobenius norm, in the partial-sum layout of f0_kernel (the refinement's
+// schedule starts from them).
+__global__ __launch_bounds__(256) void newton_add_kernel(const double* __restrict__ Dt,
+                                                         const double* __restrict__ X1,
+                                                         int64_t n, int64_t np,
+                                                         double* __restrict__ out,
+                                                         double* __restrict__ partials) {
+  __shared__ double red[24];
+  double t1 = 0.0, t2 = 0.0;
+  const int64_t total = np * np;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / np, c = idx % np;
+    double y = Dt[idx] + X1[idx];
+    if (r >= n || c >= n) y = 0.0;
+    out[idx] = y;
+    if (r == c) t1 += y;
+    t2 += y * y;
+  }
+  double e0 = 0.0;
+  block_sum3(e0, t1, t2, red);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 4 + 0] = 0.0;
+    partials[blockIdx.x * 4 + 1] = t1;
+    partials[blockIdx.x * 4 + 2] = t2;
+    partials[blockIdx.x * 4 + 3] = 0.0;
+  }
+}
+
+// Write the operand / output indices, precision and epilogue coefficients of the next product
+// of a host-planned sequence into the state the product kernels read.
+__global__ void newton_set_kernel(SnfState* __restrict__ st, const NewtonOp* __restrict__ ops,
+                                  int k) {
+  if (threadIdx.x != 0) return;
+  const NewtonOp o = ops[k];
+  st->ia = o.ia;
+  st->ib = o.ib;
+  st->ix = o.ix;
+  st->io = o.io;
+  st->prec = o.prec;
+  st->write_lowp = o.write_lowp;
+  st->c2 = o.c2;
+  st->c1 = o.c1;
+  st->c0 = o.c0;
+  st->want_e = 0;
+  st->dual = 0;
+  st->stop = 0;
+}
+
+void launch_newton_split(const double* G, const double* W, const double* M, int64_t n,
+                         int64_t np, double* Xbd, float* Xbd_lp, double* X1, float* X1_lp,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(newton_split_kernel, dim3(kF0Blocks), dim3(256), 0, s, G, W, M, n, np, Xbd,
+                     Xbd_lp, X1, X1_lp);
+}
+
+void launch_newton_sym(const double* Z, const double* X1, double c2, double c1, int64_t n,
+                       int64_t np, double* out, float* out_lp, hipStream_t s) {
+  hipLaunchKernelGGL(newton_sym_kernel, dim3(kF0Blocks), dim3(256), 0, s, Z, X1, c2, c1, n, np,
+                     out, out_lp);
+}
+
+void launch_newton_add(const double* Dt, const double* X1, int64_t n, int64_t np, double* out,
+                       double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(newton_add_kernel, dim3(kF0Blocks), dim3(256), 0, s, Dt, X1, n, np, out,
+                     partials);
+}
+
+void launch_newton_set(SnfState* st, const NewtonOp* ops, int k, hipStream_t s) {
+  hipLaunchKernelGGL(newton_set_kernel, dim3(1), dim3(64), 0, s, st, ops, k);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -172,6 +172,23 @@ void launch_sum_partials(const double* partials, int count, double* out3, hipStr
 
 int num_product_tiles(int64_t np, int sym);
 
+// ---- subspace correction (kernels_dense.hip; driven by snf_purify_dense) ----------------
+// One product of the host-planned correction sequence: buffer indices into the Buffers
+// table the launch uses, the product's precision, whether the epilogue writes the FP32 copy,
+// and the epilogue coefficients Y = c2 P + c1 X[ix] + c0 I.
+struct NewtonOp {
+  int32_t ia, ib, ix, io, prec, write_lowp;
+  double c2, c1, c0;
+};
+void launch_newton_set(SnfState* st, const NewtonOp* ops, int k, hipStream_t s);
+void launch_newton_split(const double* G, const double* W, const double* M, int64_t n,
+                         int64_t np, double* Xbd, float* Xbd_lp, double* X1, float* X1_lp,
+                         hipStream_t s);
+void launch_newton_sym(const double* Z, const double* X1, double c2, double c1, int64_t n,
+                       int64_t np, double* out, float* out_lp, hipStream_t s);
+void launch_newton_add(const double* Dt, const double* X1, int64_t n, int64_t np, double* out,
+                       double* partials, hipStream_t s);
+
 // Keep the text of a failed HIP call for snf_strerror(SNF_EDEVICE); returns SNF_EDEVICE.
 int record_hip_error(hipError_t e, const char* what);
 

@@ -30,6 +30,7 @@ BRANCH_LETTERS = {0: "S", 1: "F", 2: "M", 3: "3", 4: "5", 5: "P"}
 LOG_MAX = 256
 FLAG_TIME_PRODUCTS = 1
 FLAG_TRUNC_ERROR_CONTROL = 2
+FLAG_SUBSPACE_NEWTON = 4
 
 
 class Params(ctypes.Structure):
@@ -54,7 +55,7 @@ class LogRec(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("products", ctypes.c_int32), ("products_fp64", ctypes.c_int32),
-                ("products_lowp", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("products_lowp", ctypes.c_int32), ("products_newton", ctypes.c_int32),
                 ("idem_err", ctypes.c_double), ("trace", ctypes.c_double),
                 ("trace_err", ctypes.c_double), ("alpha_last", ctypes.c_double),
                 ("beta_last", ctypes.c_double), ("betabar_last", ctypes.c_double),
@@ -182,7 +183,7 @@ def result_dict(res: Result, log_arr=None) -> dict:
     d = dict(status=STATUS_NAMES.get(res.status, str(res.status)), code=res.status,
              iterations=res.iterations, products=res.products,
              products_fp64=res.products_fp64, products_lowp=res.products_lowp,
-             idem_err=res.idem_err, trace=res.trace, trace_err=res.trace_err,
+             products_newton=res.products_newton, idem_err=res.idem_err, trace=res.trace, trace_err=res.trace_err,
              alpha_last=res.alpha_last, beta_last=res.beta_last,
              betabar_last=res.betabar_last, device_ms=res.device_ms,
              product_ms=res.product_ms, flops=res.flops, blocks=res.blocks,
