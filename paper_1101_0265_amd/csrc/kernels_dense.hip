@@ -696,13 +696,16 @@ void launch_product_small(SnfState* st, const Buffers* bufs_dev, const SmallGrid
 //   Here the LDS tiles are 'row panels' with k contiguous: sA[i][k] = A[i0+i][k0+k] and
 //   sB[j][k] = B[j0+j][k0+k] (B[k][j] = B[j][k] by symmetry), because a lane's MFMA operand
 //   is 8 consecutive k values of one row / column: lane l holds row (l % 16),
-//   k = 8 (l / 16) .. 8 (l / 16) + 7.
+//   k = 8 (l / 16) .. 8 (l / 16) + 7.  Rows are 128 bytes (eight 16-byte chunks) without
+//   padding; chunk c of row r is stored at position c ^ ((r >> 1) & 7), so that both the
+//   stores (two rows of eight chunks per 16 lanes) and the operand reads (16 rows, one chunk
+//   each) hit every bank once.
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ void product_bf16_body(const SnfState* __restrict__ st,
                                                   const Buffers* __restrict__ bufs,
                                                   const ProductGrid& g, const WorkItem& wi) {
   constexpr int BK = 64;                 // bf16 per LDS row per stage = 128 B
-  constexpr int LDS_W = BK + 8;          // row stride 144 B
+  constexpr int LDS_W = BK;              // row stride 128 B, chunks swizzled
   constexpr int VPR = BK / 8;            // 16-byte vectors per row = 8
   constexpr int RPP = kThreads / VPR;    // 32 rows per pass
   constexpr int PASSES = kTile / RPP;    // 4
@@ -739,8 +742,9 @@ __device__ __forceinline__ void product_bf16_body(const SnfState* __restrict__ s
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int p = 0; p < PASSES; ++p) {
-      *(u32x4*)(&sA[buf][p * RPP + lrow][lvec * 8]) = ra[p];
-      *(u32x4*)(&sB[buf][p * RPP + lrow][lvec * 8]) = rb[p];
+      const int rr = p * RPP + lrow, pc = (lvec ^ ((rr >> 1) & 7)) * 8;
+      *(u32x4*)(&sA[buf][rr][pc]) = ra[p];
+      *(u32x4*)(&sB[buf][rr][pc]) = rb[p];
     }
   };
 
@@ -756,11 +760,15 @@ __device__ __forceinline__ void product_bf16_body(const SnfState* __restrict__ s
     for (int kk = 0; kk < BK; kk += 32) {
       bf16x8 a[4], b[4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
-        a[m] = *(const bf16x8*)(&sA[buf][wr * 64 + m * 16 + fr][kk + fk]);
+      for (int m = 0; m < 4; ++m) {
+        const int rr = wr * 64 + m * 16 + fr;
+        a[m] = *(const bf16x8*)(&sA[buf][rr][(((kk + fk) >> 3) ^ ((rr >> 1) & 7)) * 8]);
+      }
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        b[q] = *(const bf16x8*)(&sB[buf][wc * 64 + q * 16 + fr][kk + fk]);
+      for (int q = 0; q < 4; ++q) {
+        const int rr = wc * 64 + q * 16 + fr;
+        b[q] = *(const bf16x8*)(&sB[buf][rr][(((kk + fk) >> 3) ^ ((rr >> 1) & 7)) * 8]);
+      }
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
