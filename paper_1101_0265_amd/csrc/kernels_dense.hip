@@ -277,19 +277,20 @@ __device__ __forceinline__ EpiArgs epi_args(const SnfState* st, const Buffers* b
   return e;
 }
 
-// Epilogue of one product entry p at global (r, c): Y = c2 p + c1 X + c0 [r == c], the FP64
-// sums, the mirror write.  In symmetric mode a diagonal tile keeps its upper half and
-// mirrors it, so the result is exactly symmetric; every off-diagonal entry then stands for
-// two.  With DUAL the second output Y2 is written too (compiled only into the kernel variants
-// that need it, so the others keep their register budget).
+// Epilogue of one product entry p at global (r, c), x = X[r][c] (loaded by the caller, ahead
+// of the stores, so that the loads of many entries are in flight together: the compiler may not
+// move a load of X above a store to Y, which it cannot tell apart): Y = c2 p + c1 X +
+// c0 [r == c], the FP64 sums, the mirror write.  In symmetric mode a diagonal tile keeps its
+// upper half and mirrors it, so the result is exactly symmetric; every off-diagonal entry then
+// stands for two.  With DUAL the second output Y2 is written too (compiled only into the
+// kernel variants that need it, so the others keep their register budget).
 template <bool DUAL = false>
-__device__ __forceinline__ void epi_elem(double p, int64_t r, int64_t c, int sym, int diag,
-                                         int64_t n, int64_t np, const EpiArgs& ea, double& e2,
-                                         double& t1, double& t2) {
+__device__ __forceinline__ void epi_elem(double p, double x, int64_t r, int64_t c, int sym,
+                                         int diag, int64_t n, int64_t np, const EpiArgs& ea,
+                                         double& e2, double& t1, double& t2) {
   if (diag && sym && r > c) return;
   const bool mirror = sym && r != c;
   const double w = mirror ? 2.0 : 1.0;
-  const double x = ea.Xt[r * np + c];
   if (ea.want_e) {
     const double d = p - x;
     e2 += w * (d * d);
@@ -331,15 +332,15 @@ __device__ __forceinline__ int acc_row(int lane, int v) {
 // contiguous and go out as two 16-byte stores (and one 16- or 8-byte store of the
 // low-precision copy) instead of four scattered 8-byte ones.  Same values as epi_elem.
 template <typename Acc4>
-__device__ __forceinline__ void epi_quad_mirrored(const Acc4& acc4, int64_t r0, int64_t c,
-                                                  int64_t n, int64_t np, const EpiArgs& ea,
-                                                  double& e2, double& t2) {
+__device__ __forceinline__ void epi_quad_mirrored(const Acc4& acc4, const double (&x4)[4],
+                                                  int64_t r0, int64_t c, int64_t n, int64_t np,
+                                                  const EpiArgs& ea, double& e2, double& t2) {
   double y[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int64_t r = r0 + v;
     const double p = (double)acc4[v];
-    const double x = ea.Xt[r * np + c];
+    const double x = x4[v];
     if (ea.want_e) {
       const double d = p - x;
       e2 += 2.0 * (d * d);
@@ -375,35 +376,93 @@ __device__ __forceinline__ void epi_quad_mirrored(const Acc4& acc4, int64_t r0, 
   }
 }
 
-// One 16x16 MFMA block (m, q) of the wave tile: acc4 holds its four values of this lane.
+// X[r][c] of the four entries of MFMA block (m, q) held by this lane.
+template <bool ROWS_INTERLEAVED>
+__device__ __forceinline__ void load_x_block(double (&x4)[4], int m, int q, int gi0, int gj0,
+                                             int64_t np, const EpiArgs& ea) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = gj0 + q * 16 + (lane & 15);
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    x4[v] = ea.Xt[(gi0 + m * 16 + acc_row<ROWS_INTERLEAVED>(lane, v)) * np + c];
+}
+
+// One 16x16 MFMA block (m, q) of the wave tile: acc4 holds its four values of this lane, x4
+// the matching entries of X.
 template <bool ROWS_INTERLEAVED, bool DUAL, typename Acc4>
-__device__ __forceinline__ void epilogue_block(const Acc4& acc4, int m, int q, int gi0, int gj0,
-                                               int sym, int diag, int64_t n, int64_t np,
-                                               const EpiArgs& ea, double& e2, double& t1,
-                                               double& t2) {
+__device__ __forceinline__ void epilogue_block(const Acc4& acc4, const double (&x4)[4], int m,
+                                               int q, int gi0, int gj0, int sym, int diag,
+                                               int64_t n, int64_t np, const EpiArgs& ea,
+                                               double& e2, double& t1, double& t2) {
   const int lane = threadIdx.x & 63;
   const int64_t c = gj0 + q * 16 + (lane & 15);
   if (!ROWS_INTERLEAVED && !DUAL && sym && !diag) {
-    epi_quad_mirrored(acc4, gi0 + m * 16 + acc_row<false>(lane, 0), c, n, np, ea, e2, t2);
+    epi_quad_mirrored(acc4, x4, gi0 + m * 16 + acc_row<false>(lane, 0), c, n, np, ea, e2, t2);
     return;
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int64_t r = gi0 + m * 16 + acc_row<ROWS_INTERLEAVED>(lane, v);
-    epi_elem<DUAL>((double)acc4[v], r, c, sym, diag, n, np, ea, e2, t1, t2);
+    epi_elem<DUAL>((double)acc4[v], x4[v], r, c, sym, diag, n, np, ea, e2, t1, t2);
   }
 }
 
-template <bool ROWS_INTERLEAVED, bool DUAL, int MT, int QT, typename AccT>
+// The wave tile's epilogue.  X values are loaded in batches ahead of the stores: BATCH -1
+// loads each value just before its entry's stores, 0 the four values of one MFMA block before
+// that block's stores, 1 those of a row of blocks before the row's stores, 2 also the next
+// row's before the current row's stores (more registers each: the FP64 kernels, at 4 waves per
+// SIMD, have room only for -1).
+template <bool ROWS_INTERLEAVED, bool DUAL, int BATCH = 0, int MT, int QT, typename AccT>
 __device__ __forceinline__ void epilogue(const AccT (&acc)[MT][QT], int gi0, int gj0, int sym,
                                          int diag, int64_t n, int64_t np, const EpiArgs& ea,
                                          double& e2, double& t1, double& t2) {
+  if constexpr (BATCH < 0) {
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int m = 0; m < MT; ++m)
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-    for (int q = 0; q < QT; ++q)
-      epilogue_block<ROWS_INTERLEAVED, DUAL>(acc[m][q], m, q, gi0, gj0, sym, diag, n, np, ea,
-                                             e2, t1, t2);
+      for (int q = 0; q < QT; ++q) {
+        const int64_t c = gj0 + q * 16 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t r = gi0 + m * 16 + acc_row<ROWS_INTERLEAVED>(lane, v);
+          if (diag && sym && r > c) continue;   // (the entry's mirror is written instead)
+          epi_elem<DUAL>((double)acc[m][q][v], ea.Xt[r * np + c], r, c, sym, diag, n, np, ea,
+                         e2, t1, t2);
+        }
+      }
+  } else if constexpr (BATCH == 0) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int q = 0; q < QT; ++q) {
+        double x4[4];
+        load_x_block<ROWS_INTERLEAVED>(x4, m, q, gi0, gj0, np, ea);
+        epilogue_block<ROWS_INTERLEAVED, DUAL>(acc[m][q], x4, m, q, gi0, gj0, sym, diag, n, np,
+                                               ea, e2, t1, t2);
+      }
+  } else {
+    constexpr int NB = BATCH == 2 ? 2 : 1;
+    double xs[NB][QT][4];
+    if (BATCH == 2) {
+#pragma unroll
+      for (int q = 0; q < QT; ++q)
+        load_x_block<ROWS_INTERLEAVED>(xs[0][q], 0, q, gi0, gj0, np, ea);
+    }
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int nm = BATCH == 2 ? m + 1 : m;
+      if (nm < MT) {
+#pragma unroll
+        for (int q = 0; q < QT; ++q)
+          load_x_block<ROWS_INTERLEAVED>(xs[nm % NB][q], nm, q, gi0, gj0, np, ea);
+      }
+#pragma unroll
+      for (int q = 0; q < QT; ++q)
+        epilogue_block<ROWS_INTERLEAVED, DUAL>(acc[m][q], xs[m % NB][q], m, q, gi0, gj0, sym,
+                                               diag, n, np, ea, e2, t1, t2);
+    }
+  }
 }
 
 __device__ __forceinline__ void write_partials(double e2, double t1, double t2,
@@ -562,7 +621,8 @@ __device__ __forceinline__ void product_body(const SnfState* __restrict__ st,
   }
   const EpiArgs ea = epi_args(st, bufs);
   double e2 = 0.0, t1 = 0.0, t2 = 0.0;
-  epilogue<PREC == kPrecF64, DUAL>(acc, (int)(i0 + wr * TR), (int)(j0 + wc * TC), g.sym,
+  epilogue<PREC == kPrecF64, DUAL, PREC == kPrecF64 ? -1 : 0>(acc, (int)(i0 + wr * TR),
+                                                             (int)(j0 + wc * TC), g.sym,
                                    bi == bj, g.n, np, ea, e2, t1, t2);
   write_partials(e2, t1, t2, g.partials, wi.tile);
 }
@@ -657,12 +717,18 @@ __device__ __forceinline__ void small_tile_product(const SnfState* __restrict__ 
   __syncthreads();
   const EpiArgs ea = epi_args(st, bufs);
   double e2 = 0.0, t1 = 0.0, t2 = 0.0;
+  double xs[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int idx = e * kSmallThreads + tid;
+    xs[e] = ea.Xt[(i0 + idx / kSmallTile) * np + j0 + idx % kSmallTile];
+  }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int idx = e * kSmallThreads + tid;
     const int r = idx / kSmallTile, c = idx % kSmallTile;
     const double p = ((part[0][r][c] + part[1][r][c]) + part[2][r][c]) + part[3][r][c];
-    epi_elem(p, i0 + r, j0 + c, 1, bi == bj, g.n, np, ea, e2, t1, t2);
+    epi_elem(p, xs[e], i0 + r, j0 + c, 1, bi == bj, g.n, np, ea, e2, t1, t2);
   }
   write_partials(e2, t1, t2, partials, tile);
 }
@@ -785,7 +851,8 @@ __device__ __forceinline__ void product_bf16_body(const SnfState* __restrict__ s
   }
   const EpiArgs ea = epi_args(st, bufs);
   double e2 = 0.0, t1 = 0.0, t2 = 0.0;
-  epilogue<false, false>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), g.sym, bi == bj, g.n,
+  epilogue<false, false, 2>(acc, (int)(i0 + wr * 64), (int)(j0 + wc * 64), g.sym, bi == bj,
+                            g.n,
                          np, ea, e2, t1, t2);
   write_partials(e2, t1, t2, g.partials, wi.tile);
 }
@@ -854,10 +921,13 @@ __global__ __launch_bounds__(256) void split_fixup_kernel(const SnfState* __rest
   const EpiArgs ea = epi_args(st, bufs);
   double e2 = 0.0, t1 = 0.0, t2 = 0.0;
   const int64_t gr = (int64_t)bi * kTile + r;
+  double xs[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) xs[v] = ea.Xt[gr * g.np + (int64_t)bj * kTile + c0 + v];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
-    epi_elem<true>(sum[v], gr, (int64_t)bj * kTile + c0 + v, g.sym, bi == bj, g.n, g.np, ea,
-                   e2, t1, t2);
+    epi_elem<true>(sum[v], xs[v], gr, (int64_t)bj * kTile + c0 + v, g.sym, bi == bj, g.n, g.np,
+                   ea, e2, t1, t2);
   write_partials(e2, t1, t2, g.partials, g.dp_tiles + blockIdx.x);
 }
 
