@@ -28,52 +28,12 @@
 #include <unordered_map>
 #include <vector>
 
+#include "arena.h"
 #include "snf_internal.h"
 
 namespace snf {
 
 using Clock = std::chrono::steady_clock;
-
-// First-fit sub-allocator over [0, size) with coalescing of free neighbours.
-class Arena {
- public:
-  void init(size_t size) {
-    free_.clear();
-    free_[0] = size;
-  }
-  bool alloc(size_t bytes, size_t* off) {
-    bytes = (bytes + 255) & ~(size_t)255;
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        *off = it->first;
-        const size_t rest = it->second - bytes, start = it->first + bytes;
-        free_.erase(it);
-        if (rest) free_[start] = rest;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = (bytes + 255) & ~(size_t)255;
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-
- private:
-  std::map<size_t, size_t> free_;
-};
 
 struct ServeRequest {
   uint64_t ticket = 0;
