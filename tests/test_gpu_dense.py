@@ -113,6 +113,37 @@ def test_step_commuting_operands(snf):
     assert np.max(np.abs(Y.cpu().numpy() - A @ B)) <= 1e-13
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16_ref64"])
+def test_step_8192_lowp(snf, prec):
+    """The low-precision products at n = 8192, in the configuration the benchmark times (a
+    stand-alone step): Y against the FP64 product of the same rounded operand, entry by entry,
+    within the accumulation bound (n + 2) u32 |c2| (|A~| |A~|)."""
+    n = 8192
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(8)
+    Z = torch.randn(n, n, generator=g, device="cuda:0", dtype=torch.float64)
+    A = (Z + Z.T) / (2.0 * math.sqrt(n))
+    del Z
+    c2, c1, c0 = 0.7, -0.3, 0.25
+    Y, sums, _ = snf.step_dense(A, A, c2, c1, c0, prec)
+    Ar = A.float()
+    if prec == "bf16_ref64":
+        Ar = Ar.to(torch.bfloat16)
+    Ar = Ar.double()
+    P = Ar @ Ar
+    Yref = c2 * P + c1 * A
+    Yref.diagonal().add_(c0)
+    bound = abs(c2) * (n + 2) * 2.0 ** -24 * (Ar.abs() @ Ar.abs())
+    bound += 8 * U64 * (Yref.abs() + abs(c1) * A.abs())
+    err = (Y - Yref).abs()
+    print(f"\nn=8192 {prec}: max |Y - Yref| = {float(err.max()):.2e}, "
+          f"max ratio to the bound {float((err / bound).max()):.3f}")
+    assert bool((err <= bound).all())
+    assert torch.equal(Y, Y.T)
+    assert abs(sums[1] - float(torch.trace(Y))) <= 1e-10 * max(1.0, abs(float(torch.trace(Y))))
+    assert abs(sums[2] - float((Y * Y).sum())) <= 1e-10 * float((Y * Y).sum())
+
+
 @pytest.mark.parametrize("n", [17, 300, 1000])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16_ref64"])
 def test_step_non_commuting_operands(snf, n, prec):
