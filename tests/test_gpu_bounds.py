@@ -97,6 +97,41 @@ def test_bounds_drive_a_solve(snf):
           f"{r2['products']} products vs {ref['products']} with exact bounds")
 
 
+def test_bounds_lattice_4096(snf):
+    """The bound pipeline of the n = 4096 lattice workload at full size, with the benchmark's
+    40 Lanczos steps: spectral and gap bounds equal the oracle's for the same start vectors,
+    enclose the exact extreme levels and gap edges, and the scale-and-fold solve they drive
+    reaches the solve with exact bounds."""
+    h = H.lattice_hamiltonian((16, 16, 8), seed=2)
+    n, steps = h.n, 40
+    F = _dev(h.F)
+    v0 = np.random.default_rng(40).standard_normal(n)
+    v1 = np.random.default_rng(41).standard_normal(n)
+    width = h.lambda_max - h.lambda_min
+    lo, hi, _, _ = snf.spectral_bounds(F, steps, start=_dev(v0))
+    olo, ohi = bounds.spectral_bounds(h.F, v0, steps)
+    assert abs(lo - olo) <= 1e-9 * width and abs(hi - ohi) <= 1e-9 * width, (lo, olo, hi, ohi)
+    assert lo <= h.lambda_min and hi >= h.lambda_max
+    D1, r1 = snf.purify_dense(F, "sp2", lambda_min=lo, lambda_max=hi, n_occ=h.n_occ, tol=1e-8,
+                              max_iter=100)
+    assert r1["status"] == "ok"
+    homo, lumo = snf.gap_bounds(F, D1, lo, hi, steps, start=_dev(v1))
+    ohomo, olumo = bounds.gap_bounds(h.F, D1.cpu().numpy(), lo, hi, v1, steps)
+    assert abs(homo - ohomo) <= 1e-9 * width and abs(lumo - olumo) <= 1e-9 * width
+    assert homo <= h.homo and lumo >= h.lumo
+    D2, r2 = snf.purify_dense(F, "snf_varmu", lambda_min=lo, lambda_max=hi, homo=homo,
+                              lumo=lumo, n_occ=h.n_occ, tol=1e-8, max_iter=100)
+    Dx, rx = snf.purify_dense(F, "snf_varmu", lambda_min=h.lambda_min,
+                              lambda_max=h.lambda_max, homo=h.homo, lumo=h.lumo,
+                              n_occ=h.n_occ, tol=1e-8, max_iter=100)
+    assert r2["status"] == "ok" and rx["status"] == "ok"
+    assert float(torch.linalg.norm(D2 - Dx)) <= 1e-7 * math.sqrt(n)
+    assert r2["products"] <= rx["products"] + 2
+    print(f"\nn=4096 lattice: bounds [{lo:.6f}, {hi:.6f}] gap [{homo:.6f}, {lumo:.6f}] "
+          f"(exact [{h.lambda_min:.6f}, {h.lambda_max:.6f}] [{h.homo:.6f}, {h.lumo:.6f}]); "
+          f"{r2['products']} products vs {rx['products']} with exact bounds")
+
+
 def test_bounds_invalid_arguments(snf):
     F = _dev(np.eye(4))
     with pytest.raises(RuntimeError):
