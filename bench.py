@@ -533,6 +533,26 @@ def run_bsr(args):
                                   blocks_per_row=round(r["blocks"] / m.nb, 1),
                                   peak_blocks_per_row=round(peak, 1))), flush=True)
             del D
+    if args.bsr_fixmu:
+        # Algorithm 1 (two products per iteration, truncation after the second) beside
+        # Algorithm 2 and the trace scheme, tau = 1e-6; accuracy from ||[F, D]||_F
+        kw1 = dict(kw, mu=h.mu, xi=h.xi)
+        for scheme in ("snf_fixmu", "snf_varmu", "sp2"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            D, r = snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=1e-6, **kw1)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            comm = _bsr_commutator((rp, ci, va), D, m.n)
+            peak = max(x["phase"] for x in r["log"]) / m.nb
+            print(json.dumps(dict(scheme=scheme, tau=1e-6, ms=round(ms, 1),
+                                  products=r["products"], iterations=r["iterations"],
+                                  status=r["status"], e=r["idem_err"],
+                                  trace_err=r["trace_err"], commutator=comm,
+                                  product_ms=round(r["product_ms"], 1),
+                                  blocks_per_row=round(r["blocks"] / m.nb, 1),
+                                  peak_blocks_per_row=round(peak, 1))), flush=True)
+            del D
     if args.bsr_ec:
         # fixed threshold against error-controlled truncation at several budgets; accuracy
         # from ||[F, D]||_F (no exact D at this size)
@@ -829,6 +849,8 @@ def main():
     ap.add_argument("--bsr-screen", action="store_true",
                     help="block-sparse workload: also run norm-screened products at several "
                          "thresholds, with ||[F, D]||_F estimates")
+    ap.add_argument("--bsr-fixmu", action="store_true",
+                    help="block-sparse workload: Algorithm 1 beside Algorithm 2 and SP2")
     ap.add_argument("--bsr-ec", action="store_true",
                     help="block-sparse workload: also run fixed-threshold and error-controlled "
                          "truncation at several budgets, with ||[F, D]||_F estimates")

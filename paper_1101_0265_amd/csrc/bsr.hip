@@ -86,8 +86,11 @@ __global__ __launch_bounds__(64) void bsr_bitmap_kernel(const int32_t* __restric
 }
 
 // ---- 2. symbolic ------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void bsr_symbolic_kernel(const int32_t* __restrict__ row_ptr,
-                                                          const int32_t* __restrict__ col_idx,
+// Pattern of A.B (both symmetric patterns): row I is the OR of the bitmaps of B's block rows
+// K over the blocks (I, K) of A.
+__global__ __launch_bounds__(64) void bsr_symbolic_kernel(const int32_t* __restrict__ row_ptrA,
+                                                          const int32_t* __restrict__ colA,
+                                                          const int32_t* __restrict__ row_ptrB,
                                                           const uint32_t* __restrict__ bm, int W,
                                                           const int32_t* __restrict__ pre,
                                                           uint32_t* __restrict__ bmP,
@@ -98,13 +101,13 @@ __global__ __launch_bounds__(64) void bsr_symbolic_kernel(const int32_t* __restr
   const int I = blockIdx.x;
   for (int w = threadIdx.x; w < W; w += blockDim.x) acc[w] = 0u;
   int64_t tri = 0;   // block triples (I, K, J), J >= I: the useful work of row I
-  for (int p = row_ptr[I]; p < row_ptr[I + 1]; ++p) {
-    const int K = col_idx[p];
+  for (int p = row_ptrA[I]; p < row_ptrA[I + 1]; ++p) {
+    const int K = colA[p];
     for (int w = threadIdx.x; w < W; w += blockDim.x) acc[w] |= bm[(size_t)K * W + w];
     if (threadIdx.x == 0) {
       const uint32_t word = bm[(size_t)K * W + (I >> 5)];
       const int below = pre[(size_t)K * W + (I >> 5)] + __popc(word & ((1u << (I & 31)) - 1u));
-      tri += (row_ptr[K + 1] - row_ptr[K]) - below;
+      tri += (row_ptrB[K + 1] - row_ptrB[K]) - below;
     }
   }
   if (threadIdx.x == 0) triples[I] = tri;
@@ -163,7 +166,10 @@ struct BsrMat {                    // device view of one BSR matrix with its loo
 };
 
 struct BsrProductArgs {
-  BsrMat X;            // operand (both sides) and linear term
+  BsrMat X;            // left operand A (A_IK = A_KI is read from block row K)
+  BsrMat Y;            // right operand B (the same matrix as X for a square)
+  BsrMat L;            // linear term of the epilogue (X for a square; S2 for Algorithm 1's
+                       // second product)
   BsrMat P;            // candidate pattern of the output, values written here
   double* normP;       // squared Frobenius norm per candidate block
   const int32_t* tiles;  // (TI << 16) | TJ
@@ -241,6 +247,7 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
   // Threads 0-255 move the A panel, 256-511 the B panel: one 16-byte piece of each of the 4
   // blocks of their side, block row k = t / 8, columns 4 (t % 8) .. +3 (t = tid mod 256).
   const int side = tid >> 8, lk = (tid & 255) >> 3, lc = (tid & 7) * 4;
+  const float* valS = side ? g.Y.val : g.X.val;   // this thread's operand
   u32x4 rA[kSup], rB[kSup];
   uint32_t pA = 0, pB = 0;   // block pairs of the stage (kmask)
   auto gload = [&](int s, u32x4 (&rv)[kSup], uint32_t& pres) {
@@ -257,7 +264,7 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
     for (int a = 0; a < kSup; ++a) {
       const uint32_t bit = 1u << ((c0v + a) & 31);
       rv[a] = ((need >> a) & 1u)
-                  ? bsr_gload16(g.X.val + (size_t)(p0 + __popc(wv & (bit - 1u))) * kBB +
+                  ? bsr_gload16(valS + (size_t)(p0 + __popc(wv & (bit - 1u))) * kBB +
                                 lk * kB + lc)
                   : u32x4{0, 0, 0, 0};
     }
@@ -307,7 +314,7 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
       if (w < W) {
         for (int a = 0; a < kSup; ++a) {
           if (ci0 + a < nb) ua |= g.X.bm[(size_t)(ci0 + a) * W + w];
-          if (cj0 + a < nb) ub |= g.X.bm[(size_t)(cj0 + a) * W + w];
+          if (cj0 + a < nb) ub |= g.Y.bm[(size_t)(cj0 + a) * W + w];
         }
       }
       sw[tid] = ua & ub;
@@ -335,11 +342,10 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
     int nk = offs[kChunkWords];
     for (int t = tid; t < nk; t += 512) {
       const int K = klist[t];
-      const int rp = g.X.row_ptr[K];
       const uint32_t wa = g.X.bm[(size_t)K * W + (ci0 >> 5)];
-      const uint32_t wb = g.X.bm[(size_t)K * W + (cj0 >> 5)];
-      const int pa0 = rp + g.X.pre[(size_t)K * W + (ci0 >> 5)];
-      const int pb0 = rp + g.X.pre[(size_t)K * W + (cj0 >> 5)];
+      const uint32_t wb = g.Y.bm[(size_t)K * W + (cj0 >> 5)];
+      const int pa0 = g.X.row_ptr[K] + g.X.pre[(size_t)K * W + (ci0 >> 5)];
+      const int pb0 = g.Y.row_ptr[K] + g.Y.pre[(size_t)K * W + (cj0 >> 5)];
       kwa[t] = wa;
       kwb[t] = wb;
       kpa[t] = pa0;
@@ -349,7 +355,7 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
 #pragma unroll
       for (int a = 0; a < kSup; ++a)
         if ((ba >> a) & 1u) m |= bb << (4 * a);
-      if (g.screen2 > 0.0 && m) {
+      if (g.screen2 > 0.0 && m) {          // (squares only: both sides index nrmX)
         double na[kSup], nbv[kSup];
 #pragma unroll
         for (int a = 0; a < kSup; ++a) {
@@ -430,10 +436,10 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
       const int pp = bsr_find(g.P.row_ptr, g.P.bm, g.P.pre, W, I, J);
       if (pp < 0) continue;                      // no candidate: nothing contributes
       const int ppT = (I == J) ? pp : bsr_find(g.P.row_ptr, g.P.bm, g.P.pre, W, J, I);
-      const int px = bsr_find(g.X.row_ptr, g.X.bm, g.X.pre, W, I, J);
+      const int px = bsr_find(g.L.row_ptr, g.L.bm, g.L.pre, W, I, J);
       float* Y = g.P.val + (size_t)pp * kBB;
       float* YT = g.P.val + (size_t)ppT * kBB;
-      const float* Xb = px >= 0 ? g.X.val + (size_t)px * kBB : nullptr;
+      const float* Xb = px >= 0 ? g.L.val + (size_t)px * kBB : nullptr;
       double nrm2 = 0.0;
 #pragma unroll
       for (int mm = 0; mm < 2; ++mm) {
@@ -613,6 +619,9 @@ __global__ __launch_bounds__(256) void bsr_f0_kernel(const int32_t* __restrict__
                                                      double* __restrict__ partials, int nbrows) {
   __shared__ double red[12];
   const double lmin = st->lambda_min, lmax = st->lambda_max;
+  // Algorithm 1 and McWeeny: X_0 = (mu I - F) / gamma + I / 2; else Algorithm 2's map
+  const bool alg1 = st->scheme == SNF_SNF_FIXMU || st->scheme == SNF_MCWEENY;
+  const double mu = st->mu, gamma = st->gamma;
   double t1 = 0.0, t2 = 0.0;
   // grid-stride over block rows; every thread handles 4 values of each block
   for (int I = blockIdx.x; I < nbrows; I += gridDim.x) {
@@ -626,7 +635,8 @@ __global__ __launch_bounds__(256) void bsr_f0_kernel(const int32_t* __restrict__
         else if (I > J) fv = valF[(size_t)src * kBB + c * kB + r];
         else fv = (r <= c) ? valF[(size_t)src * kBB + r * kB + c] : valF[(size_t)src * kBB + c * kB + r];
         const bool d = (I == J && r == c);
-        const double x = ((d ? lmax : 0.0) - (double)fv) / (lmax - lmin);
+        const double x = alg1 ? ((d ? mu : 0.0) - (double)fv) / gamma + (d ? 0.5 : 0.0)
+                              : ((d ? lmax : 0.0) - (double)fv) / (lmax - lmin);
         const float xf = (float)x;
         valX[(size_t)p * kBB + e] = xf;
         if (d) t1 += (double)xf;
@@ -714,6 +724,7 @@ struct BsrBuf {                 // one BSR matrix owned by the library, with loo
 
 struct BsrWorkspace {
   BsrBuf X[2], P, Fl;           // current / next X, candidate product, F's lookup tables
+  BsrBuf S;                     // Algorithm 1: S2 = Xs^2, the left operand of R = S2.X
   DevArr<double> normP, partials, sums;
   DevArr<double> nrmX;          // norm screening: squared norms of the operand's blocks
   DevArr<int32_t> cnt, rank, tiles;
@@ -754,7 +765,7 @@ void bsr_release_all_devices() {
     if (!w || hipSetDevice(dev) != hipSuccess) continue;
     std::lock_guard<std::mutex> g(w->mu);
     (void)hipDeviceSynchronize();
-    for (BsrBuf* b : {&w->X[0], &w->X[1], &w->P, &w->Fl}) b->release();
+    for (BsrBuf* b : {&w->X[0], &w->X[1], &w->P, &w->Fl, &w->S}) b->release();
     w->normP.release();
     w->partials.release();
     w->sums.release();
@@ -859,18 +870,19 @@ static int scan_counts(BsrWorkspace* w, const int32_t* cnt_dev, int nb, DevArr<i
   return SNF_OK;
 }
 
-// One step on w->X[cur] (lookup tables built): candidate pattern, numeric product (reads
-// the coefficients in the state), truncation, compaction into w->X[1 - cur].  Partial sums
+// One product Y = c2 A.B + c1 L + c0 I (lookup tables of A, B and L built; coefficients from
+// the state) into N: candidate pattern of A.B, numeric product, truncation, compaction.  A
+// square has A = B = L = X; Algorithm 1's second product has A = L = S2, B = X (S2 and X are
+// polynomials in the same matrix, so S2.X is symmetric and its pattern too).  Partial sums
 // land in slots [0, tiles) (product) and [tiles, tiles + nb) (kept norms); *slots = total.
 // eps_i >= 0 selects the error-controlled rule (tau2 is then derived from the block-norm
 // histogram of this product); eps_i < 0 keeps the fixed threshold tau2.
-static int bsr_step(BsrWorkspace* w, int cur, int nb, int W, double tau2, int* slots,
-                    hipEvent_t ev_a, hipEvent_t ev_b, hipStream_t s, double eps_i = -1.0,
-                    double screen2 = 0.0) {
-  BsrBuf& X = w->X[cur];
-  BsrBuf& N = w->X[1 - cur];
+static int bsr_step(BsrWorkspace* w, BsrBuf& X, BsrBuf& B, BsrBuf& L, BsrBuf& N, int nb,
+                    int W, double tau2, int* slots, hipEvent_t ev_a, hipEvent_t ev_b,
+                    hipStream_t s, double eps_i = -1.0, double screen2 = 0.0) {
   BsrBuf& P = w->P;
   int rc;
+  if (&B != &X) screen2 = 0.0;           // screening indexes one operand's norms
   // 1b. operand block norms for the screening
   if (screen2 > 0.0 && X.nnzb > 0) {
     if ((rc = w->nrmX.reserve(X.nnzb))) return rc;
@@ -884,8 +896,8 @@ static int bsr_step(BsrWorkspace* w, int cur, int nb, int W, double tau2, int* s
     return rc;
   if ((rc = w->triples.reserve(nb))) return rc;
   hipLaunchKernelGGL(bsr_symbolic_kernel, dim3(nb), dim3(64), W * sizeof(uint32_t), s,
-                     X.row_ptr.p, X.col.p, X.bm.p, W, X.pre.p, P.bm.p, P.pre.p, w->cnt.p,
-                     w->triples.p);
+                     X.row_ptr.p, X.col.p, B.row_ptr.p, B.bm.p, W, B.pre.p, P.bm.p, P.pre.p,
+                     w->cnt.p, w->triples.p);
   BSR_HIP(hipGetLastError());
   int64_t nnzP = 0;
   if ((rc = scan_counts(w, w->cnt.p, nb, P.row_ptr, &nnzP, s))) return rc;
@@ -925,6 +937,8 @@ static int bsr_step(BsrWorkspace* w, int cur, int nb, int W, double tau2, int* s
   // 4. numeric
   BsrProductArgs args;
   args.X = X.view();
+  args.Y = B.view();
+  args.L = L.view();
   args.P = P.view();
   args.normP = w->normP.p;
   args.tiles = w->tiles.p;
@@ -1107,16 +1121,28 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
   };
   if (!F || !params || !D_out || !(trunc_tau >= 0.0) || !isfinite(trunc_tau)) return fail(SNF_EINVAL);
   if ((params->flags & SNF_FLAG_TRUNC_ERROR_CONTROL) && !(trunc_tau > 0.0)) return fail(SNF_EINVAL);
-  if (scheme != SNF_SP2_TRACE && scheme != SNF_TC2_BETA && scheme != SNF_SNF_VARMU)
+  // Algorithm 2 and its unscaled forms, and Algorithm 1 (with McWeeny, its alpha = 1 form):
+  // two products per iteration, S2 = Xs^2 and then S2.X, truncation after the second
+  const bool alg1 = scheme == SNF_SNF_FIXMU || scheme == SNF_MCWEENY;
+  if (scheme != SNF_SP2_TRACE && scheme != SNF_TC2_BETA && scheme != SNF_SNF_VARMU && !alg1)
     return fail(SNF_EINVAL);
   const snf_params& p = *params;
-  if (!isfinite(p.lambda_min) || !isfinite(p.lambda_max) || !(p.lambda_min < p.lambda_max) ||
-      !(p.tol > 0.0) || p.max_iter < 1 || p.max_iter >= SNF_LOG_MAX ||
-      !isfinite(p.homo) || !isfinite(p.lumo) || !(p.homo < p.lumo) ||
-      p.homo < p.lambda_min || p.lumo > p.lambda_max || p.lowp_floor < 0.0 ||
-      !(p.lowp_floor < 0.5) || (scheme == SNF_SP2_TRACE && p.n_occ < 0) ||
-      !(p.screen_tau >= 0.0) || !isfinite(p.screen_tau))
+  if (!(p.screen_tau >= 0.0) || !isfinite(p.screen_tau) || p.lowp_floor < 0.0 ||
+      !(p.lowp_floor < 0.5))
     return fail(SNF_EINVAL);
+  if (alg1) {
+    // the fixed-mu parameters as on the dense path; the error-control budget and the
+    // screening follow Algorithm 2's one-product steps and are not offered here
+    if (validate(F ? F->n : 0, params, scheme, SNF_P_FP32) != SNF_OK ||
+        (p.flags & SNF_FLAG_TRUNC_ERROR_CONTROL) || p.screen_tau > 0.0)
+      return fail(SNF_EINVAL);
+  } else if (!isfinite(p.lambda_min) || !isfinite(p.lambda_max) ||
+             !(p.lambda_min < p.lambda_max) || !(p.tol > 0.0) || p.max_iter < 1 ||
+             p.max_iter >= SNF_LOG_MAX || !isfinite(p.homo) || !isfinite(p.lumo) ||
+             !(p.homo < p.lumo) || p.homo < p.lambda_min || p.lumo > p.lambda_max ||
+             (scheme == SNF_SP2_TRACE && p.n_occ < 0)) {
+    return fail(SNF_EINVAL);
+  }
   hipStream_t s = (hipStream_t)stream;
   std::vector<int32_t> rp, ci;
   int rc = validate_pattern(F, rp, ci, s);
@@ -1130,25 +1156,29 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
 
   // scalar state: FP32 products, no refinement phase, stagnation stop at the floor
   SnfState* sh = w->state_host;
-  memset(sh, 0, sizeof(*sh));
-  sh->scheme = scheme;
-  sh->max_iter = p.max_iter;
-  sh->mode = SNF_P_FP32;
-  sh->has_nocc = p.n_occ >= 0;
-  sh->n = F->n;
-  sh->n_occ = p.n_occ;
-  sh->tol = p.tol;
-  sh->lambda_min = p.lambda_min;
-  sh->lambda_max = p.lambda_max;
-  sh->mu = p.mu;
-  sh->xi = p.xi;
-  sh->homo = p.homo;
-  sh->lumo = p.lumo;
+  if (alg1) {
+    init_state(sh, F->n, params, scheme, SNF_P_FP32);   // gamma, beta = beta-bar's mirror
+  } else {
+    memset(sh, 0, sizeof(*sh));
+    sh->scheme = scheme;
+    sh->max_iter = p.max_iter;
+    sh->mode = SNF_P_FP32;
+    sh->has_nocc = p.n_occ >= 0;
+    sh->n = F->n;
+    sh->n_occ = p.n_occ;
+    sh->tol = p.tol;
+    sh->lambda_min = p.lambda_min;
+    sh->lambda_max = p.lambda_max;
+    sh->mu = p.mu;
+    sh->xi = p.xi;
+    sh->homo = p.homo;
+    sh->lumo = p.lumo;
+    sh->beta = sched::alg2_f0(p.lumo, p.lambda_min, p.lambda_max);
+    sh->betabar = sched::alg2_f0(p.homo, p.lambda_min, p.lambda_max);
+    sh->e_hist[0] = sh->e_hist[1] = sh->e_hist[2] = INFINITY;
+  }
   sh->gap_switch = 0.0;
   sh->lowp_floor = p.lowp_floor > 0.0 ? p.lowp_floor : 1e-3;
-  sh->beta = sched::alg2_f0(p.lumo, p.lambda_min, p.lambda_max);
-  sh->betabar = sched::alg2_f0(p.homo, p.lambda_min, p.lambda_max);
-  sh->e_hist[0] = sh->e_hist[1] = sh->e_hist[2] = INFINITY;
   BSR_HIP(hipMemcpyAsync(w->state, sh, sizeof(SnfState), hipMemcpyHostToDevice, s));
   BSR_HIP(hipEventRecord(w->ev[0], s));
   if ((rc = bsr_init(w, F, W, s))) return fail(rc);
@@ -1158,20 +1188,33 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
   const bool ec = (p.flags & SNF_FLAG_TRUNC_ERROR_CONTROL) != 0;
   const double tau2 = ec ? 0.0 : trunc_tau * trunc_tau;
   const int n_pred = ec ? predicted_iterations(scheme, sh->beta, sh->betabar, trunc_tau) : 1;
-  if (ec) {   // the pending step's branch and alpha, for its truncation budget
-    BSR_HIP(hipMemcpyAsync(sh, w->state, sizeof(SnfState), hipMemcpyDeviceToHost, s));
-    BSR_HIP(hipStreamSynchronize(s));
-  }
+  // the pending product's kind, branch and alpha (which product runs next; the truncation
+  // budget of error control)
+  BSR_HIP(hipMemcpyAsync(sh, w->state, sizeof(SnfState), hipMemcpyDeviceToHost, s));
+  BSR_HIP(hipStreamSynchronize(s));
   const bool timing = (p.flags & SNF_FLAG_TIME_PRODUCTS) != 0;
   double prod_ms = 0.0, flops = 0.0;
   int cur = 0;
   std::vector<int64_t> blocks_of_iterate;   // stored blocks of X_i
   blocks_of_iterate.push_back(w->X[0].nnzb);
-  for (int it = 0; it <= p.max_iter; ++it) {
+  // one product per pass: a square of X (Algorithm 1's first product goes to S, untruncated,
+  // as the iteration's mask applies to X_new only), or Algorithm 1's second product S2.X
+  for (int pass = 0; pass <= 2 * p.max_iter + 1; ++pass) {
     int slots = 0;
+    const bool cube = sh->kind == kKindCube;
+    const bool first = !cube && sh->branch == SNF_BRANCH_P11;
     const double eps_i = ec ? error_control_eps(sh, trunc_tau, n_pred) : -1.0;
-    rc = bsr_step(w, cur, nb, W, tau2, &slots, timing ? w->ev[2] : nullptr,
-                  timing ? w->ev[3] : nullptr, s, eps_i, p.screen_tau * p.screen_tau);
+    BsrBuf& X = w->X[cur];
+    if (cube)
+      rc = bsr_step(w, w->S, X, w->S, w->X[1 - cur], nb, W, tau2, &slots,
+                    timing ? w->ev[2] : nullptr, timing ? w->ev[3] : nullptr, s);
+    else if (first)
+      rc = bsr_step(w, X, X, X, w->S, nb, W, 0.0, &slots, timing ? w->ev[2] : nullptr,
+                    timing ? w->ev[3] : nullptr, s);
+    else
+      rc = bsr_step(w, X, X, X, w->X[1 - cur], nb, W, tau2, &slots,
+                    timing ? w->ev[2] : nullptr, timing ? w->ev[3] : nullptr, s, eps_i,
+                    p.screen_tau * p.screen_tau);
     if (rc) return fail(rc);
     launch_schedule(w->state, w->partials.p, slots, 0, s);
     BSR_HIP(hipGetLastError());
@@ -1184,6 +1227,10 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
     }
     flops += 2.0 * kB * kB * kB * (double)w->last_triples;
     if (sh->stop) break;
+    if (first) {                         // S2 ready: the second product reads its tables
+      if ((rc = build_lookup(w->S, nb, W, s))) return fail(rc);
+      continue;
+    }
     cur = 1 - cur;
     blocks_of_iterate.push_back(w->X[cur].nnzb);
     if ((rc = build_lookup(w->X[cur], nb, W, s))) return fail(rc);
@@ -1270,8 +1317,8 @@ int snf_step_bsr(const snf_bsr* Xin, double c2, double c1, double c0, double tru
   BSR_HIP(hipMemcpyAsync(X.val.p, Xin->val, (size_t)Xin->nnzb * kBB * 4, hipMemcpyDeviceToDevice, s));
   if ((rc = build_lookup(X, nb, W, s))) return rc;
   int slots = 0;
-  if ((rc = bsr_step(w, 0, nb, W, trunc_tau * trunc_tau, &slots, w->ev[2], w->ev[3], s, -1.0,
-                     screen_tau * screen_tau)))
+  if ((rc = bsr_step(w, X, X, X, w->X[1], nb, W, trunc_tau * trunc_tau, &slots, w->ev[2],
+                     w->ev[3], s, -1.0, screen_tau * screen_tau)))
     return rc;
   if ((rc = ensure_pinned(w, 64)) || (rc = w->sums.reserve(4))) return rc;
   launch_sum_partials(w->partials.p, slots, w->sums.p, s);

@@ -81,13 +81,17 @@ def test_step_matches_masked_numpy(snf, L, tau):
 
 
 @pytest.mark.parametrize("L", [(8, 8, 4), (8, 8, 8), (16, 16, 8)])
-@pytest.mark.parametrize("scheme", ["snf_varmu", "sp2", "tc2"])
+@pytest.mark.parametrize("scheme", ["snf_varmu", "sp2", "tc2", "snf_fixmu", "mcweeny"])
 def test_purify_bsr_vs_masked_oracle(snf, L, scheme):
+    """Algorithm 1 and McWeeny run two products per iteration (S2 = Xs^2, then S2.X); the
+    truncation applies to the iteration's result, as the oracle's mask does."""
     tau = 1e-6
     m, h = H.lattice_bsr(L, seed=3)
     n = m.n
     kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
               lumo=h.lumo, tol=1e-9, max_iter=60)
+    if scheme in ("snf_fixmu", "mcweeny"):
+        kw.update(mu=h.mu, xi=h.xi)
     (rp, ci, va), r = snf.purify_bsr(*_dev_bsr(m), n, scheme, trunc_tau=tau, **kw)
     assert r["status"] in ("ok", "ok_floor"), r["status"]
     Dg = _to_dense(rp, ci, va, n)
@@ -105,6 +109,8 @@ def test_purify_bsr_vs_masked_oracle(snf, L, scheme):
     assert err <= 1e-3 * math.sqrt(n)
     assert abs(r["trace_err"]) <= 1e-2 and r["idem_err"] <= 1e-3
     assert np.array_equal(Dg, Dg.T)
+    if scheme in ("snf_fixmu", "mcweeny"):
+        assert r["products"] == 2 * r["iterations"] + 1      # two per iteration + certifying
 
 
 def test_bsr_no_truncation_matches_dense_oracle(snf):
@@ -118,6 +124,13 @@ def test_bsr_no_truncation_matches_dense_oracle(snf):
     assert r["status"] == o["status"] == "ok"
     assert r["branches"] == o["branches"] and r["products"] == o["products"]
     assert np.linalg.norm(_to_dense(rp, ci, va, n) - o["D"]) <= 1e-4 * math.sqrt(n)
+    # Algorithm 1: both products of every iteration without truncation
+    kw.update(mu=h.mu, xi=h.xi)
+    (rp, ci, va), r = snf.purify_bsr(*_dev_bsr(m), n, "snf_fixmu", trunc_tau=0.0, **kw)
+    o = dense.purify(m.to_dense(), "snf_fixmu", **kw)
+    assert r["status"] == o["status"] == "ok"
+    assert r["branches"] == o["branches"] and r["products"] == o["products"]
+    assert np.linalg.norm(_to_dense(rp, ci, va, n) - o["D"]) <= 1e-4 * math.sqrt(n)
 
 
 def test_bsr_invalid_inputs(snf):
@@ -126,8 +139,15 @@ def test_bsr_invalid_inputs(snf):
     kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
               lumo=h.lumo, tol=1e-6, max_iter=40)
     rp, ci, va = _dev_bsr(m)
-    with pytest.raises(RuntimeError):            # Algorithm 1 is not offered on BSR
-        snf.purify_bsr(rp, ci, va, n, "snf_fixmu", mu=h.mu, xi=h.xi, **kw)
+    with pytest.raises(RuntimeError):            # Algorithm 1 needs mu and xi
+        snf.purify_bsr(rp, ci, va, n, "snf_fixmu", **kw)
+    with pytest.raises(RuntimeError):            # no error-control budget for Algorithm 1
+        snf.purify_bsr(rp, ci, va, n, "snf_fixmu", mu=h.mu, xi=h.xi,
+                       flags=snf.FLAG_TRUNC_ERROR_CONTROL, **kw)
+    with pytest.raises(RuntimeError):            # nor norm screening
+        snf.purify_bsr(rp, ci, va, n, "snf_fixmu", mu=h.mu, xi=h.xi, screen_tau=1e-9, **kw)
+    with pytest.raises(RuntimeError):            # the higher-order schemes stay dense-only
+        snf.purify_bsr(rp, ci, va, n, "snf_fixmu3", mu=h.mu, xi=h.xi, **kw)
     # drop one off-diagonal block: the pattern is no longer symmetric
     keep = np.ones(m.nnzb, bool)
     off = next(p for p in range(m.nnzb) if m.col_idx[p] != 0)
