@@ -1,22 +1,25 @@
 // Block-sparse (BSR, 32x32 FP32 blocks) purification step and driver for gfx950.
 //
-// Per iteration, for the current X (symmetric pattern, every diagonal block present):
+// Per product, for operands A, B (symmetric patterns, every diagonal block present; A = B = X
+// for a square, A = S2 = Xs^2 and B = X for the second product of Algorithm 1):
 //   1. bsr_bitmap_kernel    per block row: bitmap of its block columns + prefix popcounts,
 //                           so block (K, c) is found at row_ptr[K] + rank_K(c) in O(1).
-//   2. bsr_symbolic_kernel  candidate pattern of X.X: row I = OR of the bitmaps of the rows
-//                           K in row I (integer work).
+//   2. bsr_symbolic_kernel  candidate pattern of A.B: row I = OR of the bitmaps of B's rows
+//                           K over the blocks (I, K) of A (integer work).
 //   3. bsr_tile_flags       128x128 super-tiles (4x4 blocks) of the upper triangle that hold
 //                           a candidate block.
 //   4. bsr_product_kernel   one workgroup per super-tile: the f32-MFMA 128x128 tile engine of
 //                           the dense path, whose k-stages are the block columns K present in
-//                           both row unions; stage K gathers blocks (K, I_a) and (K, J_b) of
-//                           block row K (X symmetric: X_{I,K} = X_{K,I}^T), zero when absent.
-//                           With norm screening (bsr_block_norms_kernel first), a block pair
-//                           whose norm product is below the threshold is left out as if absent.
-//                           Fused epilogue: Y = c2 P + c1 X + c0 I, FP64 sums, block norms;
+//                           both row unions; stage K gathers blocks (K, I_a) of A's block row
+//                           K (A symmetric: A_{I,K} = A_{K,I}^T) and (K, J_b) of B's, zero
+//                           when absent.  With norm screening (squares only;
+//                           bsr_block_norms_kernel first), a block pair whose norm product is
+//                           below the threshold is left out as if absent.  Fused epilogue:
+//                           Y = c2 P + c1 L + c0 I (L = X, or S2), FP64 sums, block norms;
 //                           upper blocks written with their transposed mirror.
-//   5. bsr_truncate_kernel  keep (I,J) and (J,I) iff ||Y_IJ||_F >= tau (diagonal always);
-//                           ranks in row order; per-row FP64 sum of kept squared norms.
+//   5. bsr_truncate_kernel  keep (I,J) and (J,I) iff ||Y_IJ||_F >= tau (diagonal always; tau
+//                           = 0 for Algorithm 1's intermediate S2); ranks in row order;
+//                           per-row FP64 sum of kept squared norms.
 //   6. bsr_compact_kernel   copy the kept blocks into the next X.
 //   7. the dense path's schedule kernel (same on-device scalar state machine).
 #include <hip/hip_runtime.h>
