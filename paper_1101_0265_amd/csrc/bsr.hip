@@ -622,8 +622,9 @@ __global__ __launch_bounds__(256) void bsr_f0_kernel(const int32_t* __restrict__
                                                      double* __restrict__ partials, int nbrows) {
   __shared__ double red[12];
   const double lmin = st->lambda_min, lmax = st->lambda_max;
-  // Algorithm 1 and McWeeny: X_0 = (mu I - F) / gamma + I / 2; else Algorithm 2's map
-  const bool alg1 = st->scheme == SNF_SNF_FIXMU || st->scheme == SNF_MCWEENY;
+  // fixed-mu schemes (Algorithm 1, McWeeny, P_{m,m}): X_0 = (mu I - F) / gamma + I / 2; else
+  // Algorithm 2's map
+  const bool alg1 = st->scheme == SNF_SNF_FIXMU || st->scheme == SNF_MCWEENY || st->pmm_m;
   const double mu = st->mu, gamma = st->gamma;
   double t1 = 0.0, t2 = 0.0;
   // grid-stride over block rows; every thread handles 4 values of each block
@@ -727,7 +728,10 @@ struct BsrBuf {                 // one BSR matrix owned by the library, with loo
 
 struct BsrWorkspace {
   BsrBuf X[2], P, Fl;           // current / next X, candidate product, F's lookup tables
-  BsrBuf S;                     // Algorithm 1: S2 = Xs^2, the left operand of R = S2.X
+  BsrBuf S, T;                  // the iteration's intermediates (Algorithm 1's S2 = Xs^2;
+                                // P_{m,m}'s W and Horner levels)
+  // the schedule's buffer indices 0..3 (operands, linear term and output of each product)
+  BsrBuf& buf(int i) { return i == 0 ? X[0] : i == 1 ? X[1] : i == 2 ? S : T; }
   DevArr<double> normP, partials, sums;
   DevArr<double> nrmX;          // norm screening: squared norms of the operand's blocks
   DevArr<int32_t> cnt, rank, tiles;
@@ -768,7 +772,7 @@ void bsr_release_all_devices() {
     if (!w || hipSetDevice(dev) != hipSuccess) continue;
     std::lock_guard<std::mutex> g(w->mu);
     (void)hipDeviceSynchronize();
-    for (BsrBuf* b : {&w->X[0], &w->X[1], &w->P, &w->Fl, &w->S}) b->release();
+    for (BsrBuf* b : {&w->X[0], &w->X[1], &w->P, &w->Fl, &w->S, &w->T}) b->release();
     w->normP.release();
     w->partials.release();
     w->sums.release();
@@ -1124,19 +1128,24 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
   };
   if (!F || !params || !D_out || !(trunc_tau >= 0.0) || !isfinite(trunc_tau)) return fail(SNF_EINVAL);
   if ((params->flags & SNF_FLAG_TRUNC_ERROR_CONTROL) && !(trunc_tau > 0.0)) return fail(SNF_EINVAL);
-  // Algorithm 2 and its unscaled forms, and Algorithm 1 (with McWeeny, its alpha = 1 form):
-  // two products per iteration, S2 = Xs^2 and then S2.X, truncation after the second
-  const bool alg1 = scheme == SNF_SNF_FIXMU || scheme == SNF_MCWEENY;
-  if (scheme != SNF_SP2_TRACE && scheme != SNF_TC2_BETA && scheme != SNF_SNF_VARMU && !alg1)
+  // Algorithm 2 and its unscaled forms (one product per iteration); Algorithm 1 with McWeeny
+  // (its alpha = 1 form) and the P_{m,m} schemes, scaled and not (a chain of products per
+  // iteration, truncation after the last).  The P_{i,j} schemes, whose first product has two
+  // outputs, stay on the dense path.
+  const bool fixmu = scheme == SNF_SNF_FIXMU || scheme == SNF_MCWEENY ||
+                     scheme_pmm_m(scheme) != 0;
+  if (scheme != SNF_SP2_TRACE && scheme != SNF_TC2_BETA && scheme != SNF_SNF_VARMU && !fixmu)
     return fail(SNF_EINVAL);
   const snf_params& p = *params;
   if (!(p.screen_tau >= 0.0) || !isfinite(p.screen_tau) || p.lowp_floor < 0.0 ||
       !(p.lowp_floor < 0.5))
     return fail(SNF_EINVAL);
-  if (alg1) {
-    // the fixed-mu parameters as on the dense path; the error-control budget and the
-    // screening follow Algorithm 2's one-product steps and are not offered here
-    if (validate(F ? F->n : 0, params, scheme, SNF_P_FP32) != SNF_OK ||
+  if (fixmu) {
+    // the fixed-mu parameters as on the dense path (checked as for FP64, where the dense
+    // path offers P_{m,m}; the block-sparse products are FP32 either way); the
+    // error-control budget and the screening follow Algorithm 2's one-product steps and are
+    // not offered here
+    if (validate(F ? F->n : 0, params, scheme, SNF_P_FP64) != SNF_OK ||
         (p.flags & SNF_FLAG_TRUNC_ERROR_CONTROL) || p.screen_tau > 0.0)
       return fail(SNF_EINVAL);
   } else if (!isfinite(p.lambda_min) || !isfinite(p.lambda_max) ||
@@ -1159,8 +1168,8 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
 
   // scalar state: FP32 products, no refinement phase, stagnation stop at the floor
   SnfState* sh = w->state_host;
-  if (alg1) {
-    init_state(sh, F->n, params, scheme, SNF_P_FP32);   // gamma, beta = beta-bar's mirror
+  if (fixmu) {
+    init_state(sh, F->n, params, scheme, SNF_P_FP32);   // gamma, beta, the P_{m,m} tables
   } else {
     memset(sh, 0, sizeof(*sh));
     sh->scheme = scheme;
@@ -1200,24 +1209,21 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
   int cur = 0;
   std::vector<int64_t> blocks_of_iterate;   // stored blocks of X_i
   blocks_of_iterate.push_back(w->X[0].nnzb);
-  // one product per pass: a square of X (Algorithm 1's first product goes to S, untruncated,
-  // as the iteration's mask applies to X_new only), or Algorithm 1's second product S2.X
-  for (int pass = 0; pass <= 2 * p.max_iter + 1; ++pass) {
+  // One product per pass, on the buffers the schedule names (operands ia and ib, linear term
+  // ix, output io; 0 and 1 hold X, 2 and 3 an iteration's intermediates).  Only the product
+  // that completes an iteration is truncated: the intermediates keep every candidate block,
+  // as the oracle's mask applies to each f_i's result.
+  for (int pass = 0; pass <= 8 * (p.max_iter + 1); ++pass) {
     int slots = 0;
-    const bool cube = sh->kind == kKindCube;
-    const bool first = !cube && sh->branch == SNF_BRANCH_P11;
+    const bool last = sh->kind == kKindCube || sh->kind == kKindFinal ||
+                      (sh->kind == kKindSquare && (sh->branch == SNF_BRANCH_SQUARE ||
+                                                   sh->branch == SNF_BRANCH_FOLD));
     const double eps_i = ec ? error_control_eps(sh, trunc_tau, n_pred) : -1.0;
-    BsrBuf& X = w->X[cur];
-    if (cube)
-      rc = bsr_step(w, w->S, X, w->S, w->X[1 - cur], nb, W, tau2, &slots,
-                    timing ? w->ev[2] : nullptr, timing ? w->ev[3] : nullptr, s);
-    else if (first)
-      rc = bsr_step(w, X, X, X, w->S, nb, W, 0.0, &slots, timing ? w->ev[2] : nullptr,
-                    timing ? w->ev[3] : nullptr, s);
-    else
-      rc = bsr_step(w, X, X, X, w->X[1 - cur], nb, W, tau2, &slots,
-                    timing ? w->ev[2] : nullptr, timing ? w->ev[3] : nullptr, s, eps_i,
-                    p.screen_tau * p.screen_tau);
+    BsrBuf& out = w->buf(sh->io);
+    rc = bsr_step(w, w->buf(sh->ia), w->buf(sh->ib), w->buf(sh->ix), out, nb, W,
+                  last ? tau2 : 0.0, &slots, timing ? w->ev[2] : nullptr,
+                  timing ? w->ev[3] : nullptr, s, last ? eps_i : -1.0,
+                  p.screen_tau * p.screen_tau);
     if (rc) return fail(rc);
     launch_schedule(w->state, w->partials.p, slots, 0, s);
     BSR_HIP(hipGetLastError());
@@ -1230,16 +1236,12 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
     }
     flops += 2.0 * kB * kB * kB * (double)w->last_triples;
     if (sh->stop) break;
-    if (first) {                         // S2 ready: the second product reads its tables
-      if ((rc = build_lookup(w->S, nb, W, s))) return fail(rc);
-      continue;
-    }
-    cur = 1 - cur;
-    blocks_of_iterate.push_back(w->X[cur].nnzb);
-    if ((rc = build_lookup(w->X[cur], nb, W, s))) return fail(rc);
+    if ((rc = build_lookup(out, nb, W, s))) return fail(rc);
+    if (last) blocks_of_iterate.push_back(out.nnzb);
   }
+  cur = sh->cur;
   // the result is the X whose idempotency was certified (the input of the last product)
-  rc = make_output(w->X[cur], F->n, nb, D_out, s);
+  rc = make_output(w->buf(cur), F->n, nb, D_out, s);
   if (rc) return fail(rc);
   BSR_HIP(hipEventRecord(w->ev[1], s));
   BSR_HIP(hipStreamSynchronize(s));
@@ -1270,7 +1272,7 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
   out->device_ms = ms;
   out->product_ms = prod_ms;
   out->flops = flops;
-  out->blocks = w->X[cur].nnzb;
+  out->blocks = w->buf(cur).nnzb;
   return status;
 }
 }  // namespace snf

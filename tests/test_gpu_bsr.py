@@ -113,6 +113,35 @@ def test_purify_bsr_vs_masked_oracle(snf, L, scheme):
         assert r["products"] == 2 * r["iterations"] + 1      # two per iteration + certifying
 
 
+@pytest.mark.parametrize("L,scheme", [((8, 8, 4), "snf_fixmu3"), ((8, 8, 8), "snf_fixmu3"),
+                                      ((8, 8, 4), "snf_fixmu5"), ((8, 8, 8), "snf_fixmu5"),
+                                      ((8, 8, 4), "pmm3")])
+def test_purify_bsr_higher_order_vs_masked_oracle(snf, L, scheme):
+    """P_{m,m}: W = (a (X - I/2))^2, Horner levels in W, then X.T: m + 1 products per
+    iteration on the schedule's buffers, truncation after the last."""
+    tau = 1e-6
+    m, h = H.lattice_bsr(L, seed=3)
+    n = m.n
+    kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, mu=h.mu,
+              xi=h.xi, tol=1e-9, max_iter=60)
+    (rp, ci, va), r = snf.purify_bsr(*_dev_bsr(m), n, scheme, trunc_tau=tau, **kw)
+    assert r["status"] in ("ok", "ok_floor"), r["status"]
+    Dg = _to_dense(rp, ci, va, n)
+    Fd = m.to_dense()
+    okw = dict(kw)
+    okw.update(tol=0.0, max_iter=r["iterations"])
+    o = dense.purify(Fd, scheme, mask=dense.block_truncation_mask(32, tau), **okw)
+    assert r["branches"] == o["branches"]
+    mm = 3 if scheme.endswith("3") else 5
+    assert r["products"] == (mm + 1) * r["iterations"] + 1
+    err = float(np.linalg.norm(Dg - o["D"]))
+    print(f"\nBSR {L} {scheme}: status {r['status']} products {r['products']} "
+          f"e={r['idem_err']:.2e} |D-D_oracle|_F={err:.2e} tr err {r['trace_err']:.2e}")
+    assert err <= 1e-3 * math.sqrt(n)
+    assert abs(r["trace_err"]) <= 1e-2 and r["idem_err"] <= 1e-3
+    assert np.array_equal(Dg, Dg.T)
+
+
 def test_bsr_no_truncation_matches_dense_oracle(snf):
     """tau = 0: the block-sparse product is a plain FP32 product of the full pattern."""
     m, h = H.lattice_bsr((8, 8, 4), seed=1)
@@ -146,8 +175,8 @@ def test_bsr_invalid_inputs(snf):
                        flags=snf.FLAG_TRUNC_ERROR_CONTROL, **kw)
     with pytest.raises(RuntimeError):            # nor norm screening
         snf.purify_bsr(rp, ci, va, n, "snf_fixmu", mu=h.mu, xi=h.xi, screen_tau=1e-9, **kw)
-    with pytest.raises(RuntimeError):            # the higher-order schemes stay dense-only
-        snf.purify_bsr(rp, ci, va, n, "snf_fixmu3", mu=h.mu, xi=h.xi, **kw)
+    with pytest.raises(RuntimeError):            # P_{i,j} (two outputs) stays dense-only
+        snf.purify_bsr(rp, ci, va, n, "snf_pij", mu=h.mu, xi=h.xi, poly_ij=(1, 3), **kw)
     # drop one off-diagonal block: the pattern is no longer symmetric
     keep = np.ones(m.nnzb, bool)
     off = next(p for p in range(m.nnzb) if m.col_idx[p] != 0)

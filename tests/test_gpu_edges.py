@@ -64,13 +64,17 @@ def _bsr_dense(snf, D, n):
                        val=va.cpu().numpy()).to_dense()
 
 
-@pytest.mark.parametrize("scheme", ["snf_varmu", "sp2", "tc2"])
+@pytest.mark.parametrize("scheme", ["snf_varmu", "sp2", "tc2", "snf_fixmu", "mcweeny",
+                                    "snf_fixmu3"])
 def test_bsr_single_block(snf, scheme):
-    """n = 32: the whole matrix is one block."""
+    """n = 32: the whole matrix is one block (for the fixed-mu schemes every product of an
+    iteration is that one block)."""
     h = H.random_spectrum_hamiltonian(32, 13, -1.0, -0.1, 0.1, 1.0, seed=4)
     m = H.dense_to_bsr(h.F, 32)
     kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
               lumo=h.lumo, tol=1e-5, max_iter=60)
+    if scheme in ("snf_fixmu", "mcweeny", "snf_fixmu3"):
+        kw.update(mu=h.mu, xi=h.xi)
     D, r = snf.purify_bsr(*_bsr_dev(m), 32, scheme, trunc_tau=0.0, **kw)
     assert r["status"] in ("ok", "ok_floor")
     D_ref = exact.projector(n_occ=h.n_occ, eigvals=h.eigvals, Q=h.Q)

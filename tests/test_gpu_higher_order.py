@@ -109,13 +109,7 @@ def test_higher_order_rejects_low_precision_and_other_paths(snf):
     F = torch.tensor(h.F, device="cuda:0")
     with pytest.raises(RuntimeError):
         snf.purify_dense(F, "snf_fixmu3", "fp32_ref64", **_kw(h))
-    m, hb = H.lattice_bsr((8, 8, 4), seed=1)
-    rp = torch.tensor(m.row_ptr, device="cuda:0")
-    ci = torch.tensor(m.col_idx, device="cuda:0")
-    va = torch.tensor(m.val, device="cuda:0")
-    with pytest.raises(RuntimeError):
-        snf.purify_bsr(rp, ci, va, m.n, "snf_fixmu5", lambda_min=hb.lambda_min,
-                       lambda_max=hb.lambda_max, mu=hb.mu, xi=hb.xi, tol=1e-6, max_iter=40)
+    # (the block-sparse path runs them: tests/test_gpu_bsr.py)
     srv = snf.Server(64 << 20, max_slots=4)
     try:
         with pytest.raises(RuntimeError):
