@@ -296,9 +296,10 @@ typedef struct {
  * SNF_SNF_VARMU (one product per iteration) and the fixed-mu SNF_SNF_FIXMU, SNF_MCWEENY
  * (Algorithm 1 and its alpha = 1 form: S2 = Xs^2, then S2.X, Xs = a (X - I/2) + I/2),
  * SNF_SNF_FIXMU3/5 and SNF_PMM3/5 (P_{m,m}: W = Xs'^2, Horner levels in W, then X.T; m + 1
- * products).  A fixed-mu iteration's intermediates keep every candidate block and the
- * truncation applies to its result; these schemes take neither
- * SNF_FLAG_TRUNC_ERROR_CONTROL nor screen_tau.  The P_{i,j} schemes return SNF_EINVAL.
+ * products), SNF_SNF_FIXMU_PIJ and SNF_PIJ (P_{i,j}: the first product writes W and the top
+ * Horner level, then the levels, then X.T; (i + j)/2 + 1 products).  A fixed-mu iteration's
+ * intermediates keep every candidate block and the truncation applies to its result; these
+ * schemes take neither SNF_FLAG_TRUNC_ERROR_CONTROL nor screen_tau.
  *   F:      caller-owned, device arrays; the pattern must be symmetric with every diagonal
  *           block present; only blocks (I,J) with I <= J (and the upper triangle of diagonal
  *           blocks) are read, the rest is taken as their transpose.

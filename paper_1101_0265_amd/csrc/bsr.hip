@@ -174,6 +174,8 @@ struct BsrProductArgs {
   BsrMat L;            // linear term of the epilogue (X for a square; S2 for Algorithm 1's
                        // second product)
   BsrMat P;            // candidate pattern of the output, values written here
+  float* val2;         // second output d2 P + d1 L + d0 I over the same candidate pattern
+                       // (the first product of a P_{i,j} iteration), or null
   double* normP;       // squared Frobenius norm per candidate block
   const int32_t* tiles;  // (TI << 16) | TJ
   double* partials;    // [tiles][4]
@@ -428,6 +430,7 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
   // accumulator of lane l, register v is row 4 (l / 16) + v, column l % 16 of its 16x16
   // piece (m, q): rows m 16 + ... of block row wr, block bj = q / 2.
   const double c2 = st->c2, c1 = st->c1, c0 = st->c0;
+  const double d2 = st->d2, d1 = st->d1, d0 = st->d0;
   const int want_e = st->want_e;
   double e2 = 0.0, t1 = 0.0;
   {
@@ -442,6 +445,8 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
       const int px = bsr_find(g.L.row_ptr, g.L.bm, g.L.pre, W, I, J);
       float* Y = g.P.val + (size_t)pp * kBB;
       float* YT = g.P.val + (size_t)ppT * kBB;
+      float* Y2 = g.val2 ? g.val2 + (size_t)pp * kBB : nullptr;
+      float* YT2 = g.val2 ? g.val2 + (size_t)ppT * kBB : nullptr;
       const float* Xb = px >= 0 ? g.L.val + (size_t)px * kBB : nullptr;
       double nrm2 = 0.0;
 #pragma unroll
@@ -468,6 +473,11 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
             nrm2 += (I == J ? w : 1.0) * ((double)yf * (double)yf);
             Y[r * kB + c] = yf;
             if (mirror) YT[c * kB + r] = yf;
+            if (Y2) {
+              const float y2 = (float)(d2 * p + d1 * x + ((I == J && r == c) ? d0 : 0.0));
+              Y2[r * kB + c] = y2;
+              if (mirror) YT2[c * kB + r] = y2;
+            }
           }
         }
       }
@@ -622,10 +632,11 @@ __global__ __launch_bounds__(256) void bsr_f0_kernel(const int32_t* __restrict__
                                                      double* __restrict__ partials, int nbrows) {
   __shared__ double red[12];
   const double lmin = st->lambda_min, lmax = st->lambda_max;
-  // fixed-mu schemes (Algorithm 1, McWeeny, P_{m,m}): X_0 = (mu I - F) / gamma + I / 2; else
-  // Algorithm 2's map
-  const bool alg1 = st->scheme == SNF_SNF_FIXMU || st->scheme == SNF_MCWEENY || st->pmm_m;
-  const double mu = st->mu, gamma = st->gamma;
+  // fixed-mu schemes (Algorithm 1, McWeeny, P_{m,m}, P_{i,j}): X_0 = (mu I - F) / gamma +
+  // x* I (x* = 1/2 but for P_{i,j}); else Algorithm 2's map
+  const bool alg1 = st->scheme == SNF_SNF_FIXMU || st->scheme == SNF_MCWEENY || st->pmm_m ||
+                    st->pij_i;
+  const double mu = st->mu, gamma = st->gamma, xs = st->xstar;
   double t1 = 0.0, t2 = 0.0;
   // grid-stride over block rows; every thread handles 4 values of each block
   for (int I = blockIdx.x; I < nbrows; I += gridDim.x) {
@@ -639,7 +650,7 @@ __global__ __launch_bounds__(256) void bsr_f0_kernel(const int32_t* __restrict__
         else if (I > J) fv = valF[(size_t)src * kBB + c * kB + r];
         else fv = (r <= c) ? valF[(size_t)src * kBB + r * kB + c] : valF[(size_t)src * kBB + c * kB + r];
         const bool d = (I == J && r == c);
-        const double x = alg1 ? ((d ? mu : 0.0) - (double)fv) / gamma + (d ? 0.5 : 0.0)
+        const double x = alg1 ? ((d ? mu : 0.0) - (double)fv) / gamma + (d ? xs : 0.0)
                               : ((d ? lmax : 0.0) - (double)fv) / (lmax - lmin);
         const float xf = (float)x;
         valX[(size_t)p * kBB + e] = xf;
@@ -729,7 +740,8 @@ struct BsrBuf {                 // one BSR matrix owned by the library, with loo
 struct BsrWorkspace {
   BsrBuf X[2], P, Fl;           // current / next X, candidate product, F's lookup tables
   BsrBuf S, T;                  // the iteration's intermediates (Algorithm 1's S2 = Xs^2;
-                                // P_{m,m}'s W and Horner levels)
+                                // P_{m,m}'s and P_{i,j}'s W and Horner levels)
+  DevArr<float> val2;           // second output of a dual product, candidate pattern
   // the schedule's buffer indices 0..3 (operands, linear term and output of each product)
   BsrBuf& buf(int i) { return i == 0 ? X[0] : i == 1 ? X[1] : i == 2 ? S : T; }
   DevArr<double> normP, partials, sums;
@@ -777,6 +789,7 @@ void bsr_release_all_devices() {
     w->partials.release();
     w->sums.release();
     w->nrmX.release();
+    w->val2.release();
     w->cnt.release();
     w->rank.release();
     w->tiles.release();
@@ -886,7 +899,8 @@ static int scan_counts(BsrWorkspace* w, const int32_t* cnt_dev, int nb, DevArr<i
 // histogram of this product); eps_i < 0 keeps the fixed threshold tau2.
 static int bsr_step(BsrWorkspace* w, BsrBuf& X, BsrBuf& B, BsrBuf& L, BsrBuf& N, int nb,
                     int W, double tau2, int* slots, hipEvent_t ev_a, hipEvent_t ev_b,
-                    hipStream_t s, double eps_i = -1.0, double screen2 = 0.0) {
+                    hipStream_t s, double eps_i = -1.0, double screen2 = 0.0,
+                    BsrBuf* N2 = nullptr) {
   BsrBuf& P = w->P;
   int rc;
   if (&B != &X) screen2 = 0.0;           // screening indexes one operand's norms
@@ -947,6 +961,11 @@ static int bsr_step(BsrWorkspace* w, BsrBuf& X, BsrBuf& B, BsrBuf& L, BsrBuf& N,
   args.Y = B.view();
   args.L = L.view();
   args.P = P.view();
+  args.val2 = nullptr;
+  if (N2) {                              // second output, same candidate pattern
+    if ((rc = w->val2.reserve((size_t)nnzP * kBB))) return rc;
+    args.val2 = w->val2.p;
+  }
   args.normP = w->normP.p;
   args.tiles = w->tiles.p;
   args.partials = w->partials.p;
@@ -983,6 +1002,17 @@ static int bsr_step(BsrWorkspace* w, BsrBuf& X, BsrBuf& B, BsrBuf& L, BsrBuf& N,
   hipLaunchKernelGGL(bsr_compact_kernel, dim3(nb), dim3(256), 0, s, P.row_ptr.p, P.col.p, P.val.p,
                      w->rank.p, N.row_ptr.p, N.col.p, N.val.p);
   BSR_HIP(hipGetLastError());
+  if (N2) {                              // the same kept blocks of the second output
+    if ((rc = N2->row_ptr.reserve(nb + 1)) || (rc = N2->col.reserve(nnzN)) ||
+        (rc = N2->val.reserve((size_t)nnzN * kBB)))
+      return rc;
+    N2->nnzb = nnzN;
+    BSR_HIP(hipMemcpyAsync(N2->row_ptr.p, N.row_ptr.p, (nb + 1) * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(bsr_compact_kernel, dim3(nb), dim3(256), 0, s, P.row_ptr.p, P.col.p,
+                       w->val2.p, w->rank.p, N2->row_ptr.p, N2->col.p, N2->val.p);
+    BSR_HIP(hipGetLastError());
+  }
   *slots = ntiles + nb;
   return SNF_OK;
 }
@@ -1129,11 +1159,11 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
   if (!F || !params || !D_out || !(trunc_tau >= 0.0) || !isfinite(trunc_tau)) return fail(SNF_EINVAL);
   if ((params->flags & SNF_FLAG_TRUNC_ERROR_CONTROL) && !(trunc_tau > 0.0)) return fail(SNF_EINVAL);
   // Algorithm 2 and its unscaled forms (one product per iteration); Algorithm 1 with McWeeny
-  // (its alpha = 1 form) and the P_{m,m} schemes, scaled and not (a chain of products per
-  // iteration, truncation after the last).  The P_{i,j} schemes, whose first product has two
-  // outputs, stay on the dense path.
+  // (its alpha = 1 form), the P_{m,m} and the P_{i,j} schemes, scaled and not (a chain of
+  // products per iteration, truncation after the last; P_{i,j}'s first product has two
+  // outputs over one candidate pattern).
   const bool fixmu = scheme == SNF_SNF_FIXMU || scheme == SNF_MCWEENY ||
-                     scheme_pmm_m(scheme) != 0;
+                     scheme_pmm_m(scheme) != 0 || scheme_is_pij(scheme);
   if (scheme != SNF_SP2_TRACE && scheme != SNF_TC2_BETA && scheme != SNF_SNF_VARMU && !fixmu)
     return fail(SNF_EINVAL);
   const snf_params& p = *params;
@@ -1220,10 +1250,11 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
                                                    sh->branch == SNF_BRANCH_FOLD));
     const double eps_i = ec ? error_control_eps(sh, trunc_tau, n_pred) : -1.0;
     BsrBuf& out = w->buf(sh->io);
+    BsrBuf* out2 = sh->dual ? &w->buf(sh->io2) : nullptr;
     rc = bsr_step(w, w->buf(sh->ia), w->buf(sh->ib), w->buf(sh->ix), out, nb, W,
                   last ? tau2 : 0.0, &slots, timing ? w->ev[2] : nullptr,
                   timing ? w->ev[3] : nullptr, s, last ? eps_i : -1.0,
-                  p.screen_tau * p.screen_tau);
+                  p.screen_tau * p.screen_tau, out2);
     if (rc) return fail(rc);
     launch_schedule(w->state, w->partials.p, slots, 0, s);
     BSR_HIP(hipGetLastError());
@@ -1237,6 +1268,7 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
     flops += 2.0 * kB * kB * kB * (double)w->last_triples;
     if (sh->stop) break;
     if ((rc = build_lookup(out, nb, W, s))) return fail(rc);
+    if (out2 && (rc = build_lookup(*out2, nb, W, s))) return fail(rc);
     if (last) blocks_of_iterate.push_back(out.nnzb);
   }
   cur = sh->cur;

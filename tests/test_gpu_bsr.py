@@ -113,17 +113,26 @@ def test_purify_bsr_vs_masked_oracle(snf, L, scheme):
         assert r["products"] == 2 * r["iterations"] + 1      # two per iteration + certifying
 
 
-@pytest.mark.parametrize("L,scheme", [((8, 8, 4), "snf_fixmu3"), ((8, 8, 8), "snf_fixmu3"),
-                                      ((8, 8, 4), "snf_fixmu5"), ((8, 8, 8), "snf_fixmu5"),
-                                      ((8, 8, 4), "pmm3")])
-def test_purify_bsr_higher_order_vs_masked_oracle(snf, L, scheme):
+@pytest.mark.parametrize("L,scheme,pij", [((8, 8, 4), "snf_fixmu3", None),
+                                          ((8, 8, 8), "snf_fixmu3", None),
+                                          ((8, 8, 4), "snf_fixmu5", None),
+                                          ((8, 8, 8), "snf_fixmu5", None),
+                                          ((8, 8, 4), "pmm3", None),
+                                          ((8, 8, 4), "snf_pij", (1, 3)),
+                                          ((8, 8, 8), "snf_pij", (3, 1)),
+                                          ((8, 8, 4), "pij", (1, 3))])
+def test_purify_bsr_higher_order_vs_masked_oracle(snf, L, scheme, pij):
     """P_{m,m}: W = (a (X - I/2))^2, Horner levels in W, then X.T: m + 1 products per
-    iteration on the schedule's buffers, truncation after the last."""
+    iteration on the schedule's buffers, truncation after the last.  P_{i,j}: the first
+    product writes W and the top Horner level (two outputs over one candidate pattern), then
+    the levels T.W, then X.T: (i + j)/2 + 1 products."""
     tau = 1e-6
     m, h = H.lattice_bsr(L, seed=3)
     n = m.n
     kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, mu=h.mu,
               xi=h.xi, tol=1e-9, max_iter=60)
+    if pij:
+        kw["poly_ij"] = pij
     (rp, ci, va), r = snf.purify_bsr(*_dev_bsr(m), n, scheme, trunc_tau=tau, **kw)
     assert r["status"] in ("ok", "ok_floor"), r["status"]
     Dg = _to_dense(rp, ci, va, n)
@@ -132,8 +141,8 @@ def test_purify_bsr_higher_order_vs_masked_oracle(snf, L, scheme):
     okw.update(tol=0.0, max_iter=r["iterations"])
     o = dense.purify(Fd, scheme, mask=dense.block_truncation_mask(32, tau), **okw)
     assert r["branches"] == o["branches"]
-    mm = 3 if scheme.endswith("3") else 5
-    assert r["products"] == (mm + 1) * r["iterations"] + 1
+    per_it = (pij[0] + pij[1]) // 2 + 1 if pij else (4 if scheme.endswith("3") else 6)
+    assert r["products"] == per_it * r["iterations"] + 1
     err = float(np.linalg.norm(Dg - o["D"]))
     print(f"\nBSR {L} {scheme}: status {r['status']} products {r['products']} "
           f"e={r['idem_err']:.2e} |D-D_oracle|_F={err:.2e} tr err {r['trace_err']:.2e}")
@@ -175,8 +184,8 @@ def test_bsr_invalid_inputs(snf):
                        flags=snf.FLAG_TRUNC_ERROR_CONTROL, **kw)
     with pytest.raises(RuntimeError):            # nor norm screening
         snf.purify_bsr(rp, ci, va, n, "snf_fixmu", mu=h.mu, xi=h.xi, screen_tau=1e-9, **kw)
-    with pytest.raises(RuntimeError):            # P_{i,j} (two outputs) stays dense-only
-        snf.purify_bsr(rp, ci, va, n, "snf_pij", mu=h.mu, xi=h.xi, poly_ij=(1, 3), **kw)
+    with pytest.raises(RuntimeError):            # P_{i,j} needs odd i, j
+        snf.purify_bsr(rp, ci, va, n, "snf_pij", mu=h.mu, xi=h.xi, poly_ij=(2, 3), **kw)
     # drop one off-diagonal block: the pattern is no longer symmetric
     keep = np.ones(m.nnzb, bool)
     off = next(p for p in range(m.nnzb) if m.col_idx[p] != 0)
