@@ -892,8 +892,10 @@ static int scan_counts(BsrWorkspace* w, const int32_t* cnt_dev, int nb, DevArr<i
 
 // One product Y = c2 A.B + c1 L + c0 I (lookup tables of A, B and L built; coefficients from
 // the state) into N: candidate pattern of A.B, numeric product, truncation, compaction.  A
-// square has A = B = L = X; Algorithm 1's second product has A = L = S2, B = X (S2 and X are
-// polynomials in the same matrix, so S2.X is symmetric and its pattern too).  Partial sums
+// square has A = B = L = X; the other products of a fixed-mu iteration (Algorithm 1's S2.X,
+// the Horner levels and the last product of P_{m,m} and P_{i,j}) multiply polynomials in the
+// same matrix, so A.B is symmetric and so is its pattern.  N2 (optional) receives the second
+// output d2 A.B + d1 L + d0 I with the same kept blocks (P_{i,j}'s first product).  Partial sums
 // land in slots [0, tiles) (product) and [tiles, tiles + nb) (kept norms); *slots = total.
 // eps_i >= 0 selects the error-controlled rule (tau2 is then derived from the block-norm
 // histogram of this product); eps_i < 0 keeps the fixed threshold tau2.
