@@ -8,11 +8,13 @@
 //                           K over the blocks (I, K) of A (integer work).
 //   3. bsr_tile_flags       128x128 super-tiles (4x4 blocks) of the upper triangle that hold
 //                           a candidate block.
-//   4. bsr_product_kernel   one workgroup per super-tile: the f32-MFMA 128x128 tile engine of
-//                           the dense path, whose k-stages are the block columns K present in
-//                           both row unions; stage K gathers blocks (K, I_a) of A's block row
-//                           K (A symmetric: A_{I,K} = A_{K,I}^T) and (K, J_b) of B's, zero
-//                           when absent.  With norm screening (squares only;
+//   4. bsr_product_kernel   one workgroup per super-tile: an f32-MFMA 128x128 tile engine
+//                           whose k-stages are the block columns K present in both row
+//                           unions; stage K gathers blocks (I_a, K) of A's block rows I_a and
+//                           (J_b, K) of B's block rows J_b (B symmetric: B_{K,J} = B_{J,K}^T),
+//                           so every operand comes from the super-tile's own 8 block rows,
+//                           read in column order, and sits in LDS with its k values
+//                           contiguous; zero when absent.  With norm screening (squares only;
 //                           bsr_block_norms_kernel first), a block pair whose norm product is
 //                           below the threshold is left out as if absent.  Fused epilogue:
 //                           Y = c2 P + c1 L + c0 I (L = X, or S2), FP64 sums, block norms;
@@ -30,6 +32,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "schedule_math.h"
@@ -169,8 +172,9 @@ struct BsrMat {                    // device view of one BSR matrix with its loo
 };
 
 struct BsrProductArgs {
-  BsrMat X;            // left operand A (A_IK = A_KI is read from block row K)
-  BsrMat Y;            // right operand B (the same matrix as X for a square)
+  BsrMat X;            // left operand A (A_IK is read from block row I)
+  BsrMat Y;            // right operand B (the same matrix as X for a square); symmetric:
+                       // B_KJ is read as the transpose of B_JK, from block row J
   BsrMat L;            // linear term of the epilogue (X for a square; S2 for Algorithm 1's
                        // second product)
   BsrMat P;            // candidate pattern of the output, values written here
@@ -208,28 +212,43 @@ __global__ __launch_bounds__(256) void bsr_block_norms_kernel(const float* __res
   if (lane == 0) nrm2[blk] = acc;
 }
 
-constexpr int kBsrLdsW = 128 + 16;   // LDS row stride (floats), as the dense f32 kernel
+constexpr int kBsrLdsK = kB + 4;    // LDS row stride (floats) of a panel row: 32 values of k
+                                    // and 4 of padding (16-byte reads of 16 rows hit
+                                    // distinct banks)
 constexpr int kChunkWords = 8;      // bitmap words per k-stage list chunk (256 columns)
 static_assert(kChunkWords * 32 <= 256, "a chunk's stages must fit waves 0-3 (compaction)");
 
-__global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __restrict__ st,
-                                                             BsrProductArgs g) {
-  if (st->stop) return;
-  __shared__ __attribute__((aligned(16))) float sA[2][kB][kBsrLdsW];
-  __shared__ __attribute__((aligned(16))) float sB[2][kB][kBsrLdsW];
-  __shared__ uint16_t klist[kChunkWords * 32];
-  // per k-stage of the chunk: bitmap words of block row K at the A and B panel columns and
-  // the value index of the first block of each panel (block row K's offset included)
-  __shared__ uint32_t kwa[kChunkWords * 32], kwb[kChunkWords * 32];
-  __shared__ int32_t kpa[kChunkWords * 32], kpb[kChunkWords * 32];
+// LDS of the numeric kernel, in one struct so that the small per-chunk tables sit at low
+// addresses (reachable through the 16-bit offset of the LDS instructions) and the panels
+// after them.
+struct BsrProductSmem {
+  double red[24];
+  // per k-stage: the rank of block (row, K) within the chunk's part of each panel row, one
+  // byte per row (A rows in krel[0], B rows in krel[1])
+  uint32_t krel[2][kChunkWords * 32];
+  // the chunk's bitmap words of the 8 panel rows (A rows I_0..I_3, then B rows J_0..J_3) and
+  // the value index of the first block of each word (row_ptr + prefix count)
+  uint32_t bmc[2 * kSup][kChunkWords];
+  int32_t prc[2 * kSup][kChunkWords];
+  uint32_t sw[kChunkWords];
+  int offs[kChunkWords + 1];
+  int wkeep[4];                 // stages kept per wave (screening)
+  uint32_t spres[2];
+  uint16_t klist[kChunkWords * 32];
   // per k-stage: the block pairs (A block a, B block b) the stage multiplies, bit 4 a + b
   // (both present and, with screening, norm product at or above the threshold)
-  __shared__ uint16_t kmask[kChunkWords * 32];
-  __shared__ int wkeep[4];             // stages kept per wave (screening)
-  __shared__ uint32_t sw[kChunkWords];
-  __shared__ int offs[kChunkWords + 1];
-  __shared__ uint32_t spres[2];
-  __shared__ double red[24];
+  uint16_t kmask[kChunkWords * 32];
+  // panels of stage K: row 32 a + i holds row i of block (I_a, K) (A side) or (J_b, K)
+  // (B side), its 32 values of k contiguous
+  __attribute__((aligned(16))) float sA[2][kSup * kB][kBsrLdsK];
+  __attribute__((aligned(16))) float sB[2][kSup * kB][kBsrLdsK];
+};
+
+// 512 threads, at least 4 waves per SIMD (two workgroups per compute unit: <= 128 VGPRs)
+__global__ __launch_bounds__(512, 4) void bsr_product_kernel(const SnfState* __restrict__ st,
+                                                             BsrProductArgs g) {
+  if (st->stop) return;
+  __shared__ BsrProductSmem sm;
 
   const int packed = g.tiles[blockIdx.x];
   const int TI = packed >> 16, TJ = packed & 0xFFFF;
@@ -240,7 +259,7 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
   // the super-tile only still spreads its MFMAs over all four SIMDs
   const int wr = wid < 4 ? (wid >> 1) : 3 - ((wid - 4) >> 1);
   const int wc = wid < 4 ? (wid & 1) : 1 - ((wid - 4) & 1);
-  const int ci0 = kSup * TI, cj0 = kSup * TJ;   // first block column of the A / B panels
+  const int ci0 = kSup * TI, cj0 = kSup * TJ;   // first block row of the A / B panels
 
   // 8 waves: wave (wr, wc) holds A block row wr (32 rows) against B blocks 2 wc, 2 wc + 1
   flt4 acc[2][4];
@@ -249,113 +268,147 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[m][q] = flt4{0.f, 0.f, 0.f, 0.f};
 
-  // Threads 0-255 move the A panel, 256-511 the B panel: one 16-byte piece of each of the 4
-  // blocks of their side, block row k = t / 8, columns 4 (t % 8) .. +3 (t = tid mod 256).
-  const int side = tid >> 8, lk = (tid & 255) >> 3, lc = (tid & 7) * 4;
-  const float* valS = side ? g.Y.val : g.X.val;   // this thread's operand
-  u32x4 rA[kSup], rB[kSup];
+  // Wave wid moves one block of the stage: side wid / 4 (A, B), block ab = wid % 4, i.e. block
+  // (I_ab, K) of A's row I_ab or (J_ab, K) of B's row J_ab (A_{I,K} is that block itself; B is
+  // symmetric, so B_{K,J} is the transpose of block (J, K)).  Lane l moves the 16-byte pieces
+  // l + 64 q (q = 0..3): row (l / 8) + 8 q, values of k 4 (l % 8) .. + 3.
+  const int side = wid >> 2, ab = wid & 3, prow = side * kSup + ab;
+  const float* valS = side ? g.Y.val : g.X.val;   // this wave's operand
+  const int lrow = lane >> 3, lcol = 4 * (lane & 7);
+  u32x4 rA[4], rB[4];
   uint32_t pA = 0, pB = 0;   // block pairs of the stage (kmask)
-  auto gload = [&](int s, u32x4 (&rv)[kSup], uint32_t& pres) {
-    // the 4 panel columns of each side share one bitmap word of block row K; a block is
-    // loaded when some pair of the stage uses it, else it stays zero
-    const uint32_t m = kmask[s];
+  int rowbase = 0;           // value index of the first block of this wave's row in the chunk
+  auto gload = [&](int s, u32x4 (&rv)[4], uint32_t& pres) {
+    // the block is loaded when some pair of the stage uses it, else it stays zero (the
+    // stage tables are the same for every lane: read as wave-uniform values)
+    const uint32_t m = __builtin_amdgcn_readfirstlane(sm.kmask[s]);
     pres = m;
-    const uint32_t needA = ((m & 0x000Fu) ? 1u : 0u) | ((m & 0x00F0u) ? 2u : 0u) |
-                           ((m & 0x0F00u) ? 4u : 0u) | ((m & 0xF000u) ? 8u : 0u);
-    const uint32_t needB = (m | (m >> 4) | (m >> 8) | (m >> 12)) & 0xFu;
-    const uint32_t wv = side ? kwb[s] : kwa[s], need = side ? needB : needA;
-    const int c0v = side ? cj0 : ci0, p0 = side ? kpb[s] : kpa[s];
+    const uint32_t need = side ? ((m | (m >> 4) | (m >> 8) | (m >> 12)) >> ab) & 1u
+                               : (((m >> (4 * ab)) & 0xFu) != 0u ? 1u : 0u);
+    if (need) {
+      const int pos =
+          rowbase + (int)((__builtin_amdgcn_readfirstlane(sm.krel[side][s]) >> (8 * ab)) & 0xFFu);
+      const float* src = valS + (size_t)pos * kBB + 4 * lane;
 #pragma unroll
-    for (int a = 0; a < kSup; ++a) {
-      const uint32_t bit = 1u << ((c0v + a) & 31);
-      rv[a] = ((need >> a) & 1u)
-                  ? bsr_gload16(valS + (size_t)(p0 + __popc(wv & (bit - 1u))) * kBB +
-                                lk * kB + lc)
-                  : u32x4{0, 0, 0, 0};
+      for (int q = 0; q < 4; ++q) rv[q] = bsr_gload16(src + 256 * q);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rv[q] = u32x4{0, 0, 0, 0};
     }
   };
-  auto lstore = [&](int buf, const u32x4 (&rv)[kSup], uint32_t pres) {
-    float(*dst)[kBsrLdsW] = side ? sB[buf] : sA[buf];
+  auto lstore = [&](int buf, const u32x4 (&rv)[4], uint32_t pres) {
+    float(*dst)[kBsrLdsK] = side ? sm.sB[buf] : sm.sA[buf];
 #pragma unroll
-    for (int a = 0; a < kSup; ++a) *(u32x4*)(&dst[lk][a * kB + lc]) = rv[a];
-    if (tid == 0) spres[buf] = pres;
+    for (int q = 0; q < 4; ++q) *(u32x4*)(&dst[ab * kB + lrow + 8 * q][lcol]) = rv[q];
+    if (tid == 0) sm.spres[buf] = pres;
   };
 
+  // MFMA operands: lane (fr, fk) takes row fr of its 16-row piece at k = 8 fk + t in step t
+  // (t = 0..7; each step sums over the four fk), read as two 16-byte pieces.  The products
+  // of B blocks q0 / 2 .. (q1 - 1) / 2 of this wave's pair.
   const int fr = lane & 15, fk = lane >> 4;
-  auto compute = [&](int buf) {
-    // this wave's A block (row wr) and two B blocks; the MFMAs of pairs the stage leaves
-    // out (a block absent, or screened) are skipped (the test is uniform across the wave)
-    const uint32_t pm = spres[buf];
-    const bool pb0 = (pm >> (4 * wr + 2 * wc)) & 1u, pb1 = (pm >> (4 * wr + 2 * wc + 1)) & 1u;
-    if (pb0 || pb1) {
+  auto mfma_pairs = [&](int buf, auto q0c, auto q1c) {
+    constexpr int q0 = decltype(q0c)::value, q1 = decltype(q1c)::value;
 #pragma unroll
-      for (int kk = 0; kk < kB; kk += 4) {
-        float a[2], b[4];
+    for (int h = 0; h < 2; ++h) {
+      flt4 a[2], b[4];
 #pragma unroll
-        for (int m = 0; m < 2; ++m) a[m] = sA[buf][kk + fk][wr * kB + m * 16 + fr];
+      for (int m = 0; m < 2; ++m)
+        a[m] = *(const flt4*)(&sm.sA[buf][wr * kB + m * 16 + fr][8 * fk + 4 * h]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) b[q] = sB[buf][kk + fk][wc * 64 + q * 16 + fr];
+      for (int q = q0; q < q1; ++q)
+        b[q] = *(const flt4*)(&sm.sB[buf][wc * 64 + q * 16 + fr][8 * fk + 4 * h]);
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          if (!(bj ? pb1 : pb0)) continue;
+      for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+        for (int q = q0; q < q1; ++q)
 #pragma unroll
           for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int qq = 0; qq < 2; ++qq) {
-              const int q = 2 * bj + qq;
-              acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], b[q], acc[m][q], 0, 0, 0);
-            }
-        }
-      }
+            acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m][tt], b[q][tt], acc[m][q], 0, 0, 0);
+      // the second half's reads stay behind the first half's MFMAs (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
     }
+  };
+  auto compute = [&](int buf) {
+    // this wave's A block (row wr) and two B blocks; the MFMAs of pairs the stage leaves
+    // out (a block absent, or screened) are skipped (uniform across the wave)
+    const uint32_t pm = __builtin_amdgcn_readfirstlane(sm.spres[buf]);
+    const uint32_t pp = (pm >> (4 * wr + 2 * wc)) & 3u;
+    if (pp == 3u)
+      mfma_pairs(buf, std::integral_constant<int, 0>(), std::integral_constant<int, 4>());
+    else if (pp == 1u)
+      mfma_pairs(buf, std::integral_constant<int, 0>(), std::integral_constant<int, 2>());
+    else if (pp == 2u)
+      mfma_pairs(buf, std::integral_constant<int, 2>(), std::integral_constant<int, 4>());
   };
   // k-stages: block columns K present in both (rows I_a) and (rows J_b), taken in chunks
   // of kChunkWords bitmap words
   for (int w0 = 0; w0 < W; w0 += kChunkWords) {
-    __syncthreads();                       // the previous chunk is done with klist / LDS
-    if (tid < kChunkWords) {
-      const int w = w0 + tid;
-      uint32_t ua = 0u, ub = 0u;
-      if (w < W) {
-        for (int a = 0; a < kSup; ++a) {
-          if (ci0 + a < nb) ua |= g.X.bm[(size_t)(ci0 + a) * W + w];
-          if (cj0 + a < nb) ub |= g.Y.bm[(size_t)(cj0 + a) * W + w];
-        }
+    __syncthreads();                       // the previous chunk is done with its tables / LDS
+    if (tid < 2 * kSup * kChunkWords) {
+      const int r = tid / kChunkWords, t = tid % kChunkWords, w = w0 + t;
+      const int row = r < kSup ? ci0 + r : cj0 + (r - kSup);
+      const BsrMat& M = r < kSup ? g.X : g.Y;
+      uint32_t word = 0u;
+      int base = 0;
+      if (row < nb && w < W) {
+        word = M.bm[(size_t)row * W + w];
+        base = M.row_ptr[row] + M.pre[(size_t)row * W + w];
       }
-      sw[tid] = ua & ub;
+      sm.bmc[r][t] = word;
+      sm.prc[r][t] = base;
+    }
+    __syncthreads();
+    if (tid < kChunkWords) {
+      uint32_t ua = 0u, ub = 0u;
+#pragma unroll
+      for (int a = 0; a < kSup; ++a) {
+        ua |= sm.bmc[a][tid];
+        ub |= sm.bmc[kSup + a][tid];
+      }
+      sm.sw[tid] = ua & ub;
     }
     __syncthreads();
     if (tid == 0) {
       int acc_n = 0;
       for (int t = 0; t < kChunkWords; ++t) {
-        offs[t] = acc_n;
-        acc_n += __popc(sw[t]);
+        sm.offs[t] = acc_n;
+        acc_n += __popc(sm.sw[t]);
       }
-      offs[kChunkWords] = acc_n;
+      sm.offs[kChunkWords] = acc_n;
     }
     __syncthreads();
     if (tid < kChunkWords) {
-      uint32_t bits = sw[tid];
-      int pos = offs[tid];
+      uint32_t bits = sm.sw[tid];
+      int pos = sm.offs[tid];
       while (bits) {
         const int b = __ffs(bits) - 1;
-        klist[pos++] = (uint16_t)((w0 + tid) * 32 + b);
+        sm.klist[pos++] = (uint16_t)((w0 + tid) * 32 + b);
         bits &= bits - 1u;
       }
     }
     __syncthreads();
-    int nk = offs[kChunkWords];
+    int nk = sm.offs[kChunkWords];
+    rowbase = __builtin_amdgcn_readfirstlane(sm.prc[prow][0]);
     for (int t = tid; t < nk; t += 512) {
-      const int K = klist[t];
-      const uint32_t wa = g.X.bm[(size_t)K * W + (ci0 >> 5)];
-      const uint32_t wb = g.Y.bm[(size_t)K * W + (cj0 >> 5)];
-      const int pa0 = g.X.row_ptr[K] + g.X.pre[(size_t)K * W + (ci0 >> 5)];
-      const int pb0 = g.Y.row_ptr[K] + g.Y.pre[(size_t)K * W + (cj0 >> 5)];
-      kwa[t] = wa;
-      kwb[t] = wb;
-      kpa[t] = pa0;
-      kpb[t] = pb0;
-      const uint32_t ba = (wa >> (ci0 & 31)) & 0xFu, bb = (wb >> (cj0 & 31)) & 0xFu;
+      const int K = sm.klist[t];
+      const int wl = (K >> 5) - w0;
+      const uint32_t lo = (1u << (K & 31)) - 1u, bit = 1u << (K & 31);
+      uint32_t ba = 0u, bb = 0u, ra = 0u, rb = 0u;
+      int pa[kSup], pb[kSup];
+#pragma unroll
+      for (int a = 0; a < kSup; ++a) {
+        const uint32_t wa = sm.bmc[a][wl], wb = sm.bmc[kSup + a][wl];
+        // rank within the chunk: below 32 * kChunkWords = 256, one byte
+        const int qa = sm.prc[a][wl] - sm.prc[a][0] + __popc(wa & lo);
+        const int qb = sm.prc[kSup + a][wl] - sm.prc[kSup + a][0] + __popc(wb & lo);
+        ba |= (wa & bit) ? (1u << a) : 0u;
+        bb |= (wb & bit) ? (1u << a) : 0u;
+        ra |= (uint32_t)(qa & 0xFF) << (8 * a);
+        rb |= (uint32_t)(qb & 0xFF) << (8 * a);
+        pa[a] = sm.prc[a][0] + qa;
+        pb[a] = sm.prc[kSup + a][0] + qb;
+      }
       uint32_t m = 0u;
 #pragma unroll
       for (int a = 0; a < kSup; ++a)
@@ -364,46 +417,46 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
         double na[kSup], nbv[kSup];
 #pragma unroll
         for (int a = 0; a < kSup; ++a) {
-          const uint32_t bita = 1u << ((ci0 + a) & 31), bitb = 1u << ((cj0 + a) & 31);
-          na[a] = ((ba >> a) & 1u) ? g.nrmX[pa0 + __popc(wa & (bita - 1u))] : 0.0;
-          nbv[a] = ((bb >> a) & 1u) ? g.nrmX[pb0 + __popc(wb & (bitb - 1u))] : 0.0;
+          na[a] = ((ba >> a) & 1u) ? g.nrmX[pa[a]] : 0.0;
+          nbv[a] = ((bb >> a) & 1u) ? g.nrmX[pb[a]] : 0.0;
         }
+        uint32_t drop = 0u;
 #pragma unroll
-        for (int a = 0; a < kSup; ++a)
+        for (int a = 0; a < kSup; ++a) {
+          uint32_t da = 0u;
 #pragma unroll
-          for (int b = 0; b < kSup; ++b)
-            if (na[a] * nbv[b] < g.screen2) m &= ~(1u << (4 * a + b));
+          for (int b = 0; b < kSup; ++b) da |= na[a] * nbv[b] < g.screen2 ? (1u << b) : 0u;
+          drop |= da << (4 * a);
+        }
+        m &= ~drop;
       }
-      kmask[t] = (uint16_t)m;
+      sm.krel[0][t] = ra;
+      sm.krel[1][t] = rb;
+      sm.kmask[t] = (uint16_t)m;
     }
     __syncthreads();
     if (g.screen2 > 0.0) {
       // drop the stages whose every pair is screened out, keeping the order of the rest
       // (nk <= kChunkWords * 32 = 256: thread t < nk holds stage t)
-      const bool keep = tid < nk && kmask[tid] != 0;
+      const bool keep = tid < nk && sm.kmask[tid] != 0;
       const unsigned long long bal = __ballot(keep);
-      if (lane == 0 && wid < 4) wkeep[wid] = __popcll(bal);
-      uint32_t ewa = 0u, ewb = 0u;
-      int epa = 0, epb = 0;
+      if (lane == 0 && wid < 4) sm.wkeep[wid] = __popcll(bal);
+      uint32_t era = 0u, erb = 0u;
       uint16_t em = 0;
       if (keep) {
-        ewa = kwa[tid];
-        ewb = kwb[tid];
-        epa = kpa[tid];
-        epb = kpb[tid];
-        em = kmask[tid];
+        era = sm.krel[0][tid];
+        erb = sm.krel[1][tid];
+        em = sm.kmask[tid];
       }
       __syncthreads();                     // every entry read before any is overwritten
       if (keep) {
         int pos = __popcll(bal & ((1ull << lane) - 1ull));
-        for (int v = 0; v < wid; ++v) pos += wkeep[v];
-        kwa[pos] = ewa;
-        kwb[pos] = ewb;
-        kpa[pos] = epa;
-        kpb[pos] = epb;
-        kmask[pos] = em;
+        for (int v = 0; v < wid; ++v) pos += sm.wkeep[v];
+        sm.krel[0][pos] = era;
+        sm.krel[1][pos] = erb;
+        sm.kmask[pos] = em;
       }
-      nk = wkeep[0] + wkeep[1] + wkeep[2] + wkeep[3];
+      nk = sm.wkeep[0] + sm.wkeep[1] + sm.wkeep[2] + sm.wkeep[3];
       __syncthreads();
     }
     if (nk == 0) continue;
@@ -493,16 +546,16 @@ __global__ __launch_bounds__(512, 2) void bsr_product_kernel(const SnfState* __r
   e2 = bsr_wave_sum(e2);
   t1 = bsr_wave_sum(t1);
   if (lane == 0) {
-    red[wid * 3 + 0] = e2;
-    red[wid * 3 + 1] = t1;
-    red[wid * 3 + 2] = t2;
+    sm.red[wid * 3 + 0] = e2;
+    sm.red[wid * 3 + 1] = t1;
+    sm.red[wid * 3 + 2] = t2;
   }
   __syncthreads();
   if (tid == 0) {
     double se = 0.0, st1 = 0.0;
     for (int k = 0; k < 8; ++k) {       // wave order
-      se += red[k * 3 + 0];
-      st1 += red[k * 3 + 1];
+      se += sm.red[k * 3 + 0];
+      st1 += sm.red[k * 3 + 1];
     }
     g.partials[blockIdx.x * 4 + 0] = se;
     g.partials[blockIdx.x * 4 + 1] = st1;
