@@ -230,8 +230,7 @@ struct BsrProductSmem {
   // the value index of the first block of each word (row_ptr + prefix count)
   uint32_t bmc[2 * kSup][kChunkWords];
   int32_t prc[2 * kSup][kChunkWords];
-  uint32_t sw[kChunkWords];
-  int offs[kChunkWords + 1];
+  int offs[1];                  // stages of the chunk
   int wkeep[4];                 // stages kept per wave (screening)
   uint32_t spres[2];
   uint16_t klist[kChunkWords * 32];
@@ -343,52 +342,54 @@ __global__ __launch_bounds__(512, 4) void bsr_product_kernel(const SnfState* __r
   };
   // k-stages: block columns K present in both (rows I_a) and (rows J_b), taken in chunks
   // of kChunkWords bitmap words
+  // Wave 0 holds the bitmap word and the value index base of (panel row lane / 8, word
+  // lane % 8) of the next chunk; it fetches them while the current chunk's stages run.
+  uint32_t nword = 0u;
+  int nbase = 0;
+  auto fetch_rows = [&](int w0n) {
+    const int r = lane >> 3, w = w0n + (lane & 7);
+    const int row = r < kSup ? ci0 + r : cj0 + (r - kSup);
+    nword = 0u;
+    nbase = 0;
+    if (row < nb && w < W) {
+      const BsrMat& M = r < kSup ? g.X : g.Y;
+      nword = M.bm[(size_t)row * W + w];
+      nbase = M.row_ptr[row] + M.pre[(size_t)row * W + w];
+    }
+  };
+  if (wid == 0) fetch_rows(0);
   for (int w0 = 0; w0 < W; w0 += kChunkWords) {
     __syncthreads();                       // the previous chunk is done with its tables / LDS
-    if (tid < 2 * kSup * kChunkWords) {
-      const int r = tid / kChunkWords, t = tid % kChunkWords, w = w0 + t;
-      const int row = r < kSup ? ci0 + r : cj0 + (r - kSup);
-      const BsrMat& M = r < kSup ? g.X : g.Y;
-      uint32_t word = 0u;
-      int base = 0;
-      if (row < nb && w < W) {
-        word = M.bm[(size_t)row * W + w];
-        base = M.row_ptr[row] + M.pre[(size_t)row * W + w];
-      }
-      sm.bmc[r][t] = word;
-      sm.prc[r][t] = base;
-    }
-    __syncthreads();
-    if (tid < kChunkWords) {
-      uint32_t ua = 0u, ub = 0u;
+    if (wid == 0) {
+      // the chunk's words, the stage list (the columns set in the union of the A rows and in
+      // the union of the B rows, ascending), then the next chunk's words
+      sm.bmc[lane >> 3][lane & 7] = nword;
+      sm.prc[lane >> 3][lane & 7] = nbase;
+      uint32_t u = nword;
+      u |= __shfl_xor(u, 8);
+      u |= __shfl_xor(u, 16);              // OR over the 4 rows of this lane's side
+      const uint32_t sw = u & __shfl_xor(u, 32);
+      const int cnt = __popc(sw);
+      int incl = cnt;                      // inclusive prefix over the 8 words (lanes 0-7)
 #pragma unroll
-      for (int a = 0; a < kSup; ++a) {
-        ua |= sm.bmc[a][tid];
-        ub |= sm.bmc[kSup + a][tid];
+      for (int o = 1; o < kChunkWords; o <<= 1) {
+        const int v = __shfl_up(incl, o, kChunkWords);
+        if ((lane & (kChunkWords - 1)) >= o) incl += v;
       }
-      sm.sw[tid] = ua & ub;
+      if (lane < kChunkWords) {
+        uint32_t bits = sw;
+        int pos = incl - cnt;
+        while (bits) {
+          const int b = __ffs(bits) - 1;
+          sm.klist[pos++] = (uint16_t)((w0 + lane) * 32 + b);
+          bits &= bits - 1u;
+        }
+        if (lane == kChunkWords - 1) sm.offs[0] = incl;
+      }
+      if (w0 + kChunkWords < W) fetch_rows(w0 + kChunkWords);
     }
     __syncthreads();
-    if (tid == 0) {
-      int acc_n = 0;
-      for (int t = 0; t < kChunkWords; ++t) {
-        sm.offs[t] = acc_n;
-        acc_n += __popc(sm.sw[t]);
-      }
-      sm.offs[kChunkWords] = acc_n;
-    }
-    __syncthreads();
-    if (tid < kChunkWords) {
-      uint32_t bits = sm.sw[tid];
-      int pos = sm.offs[tid];
-      while (bits) {
-        const int b = __ffs(bits) - 1;
-        sm.klist[pos++] = (uint16_t)((w0 + tid) * 32 + b);
-        bits &= bits - 1u;
-      }
-    }
-    __syncthreads();
-    int nk = sm.offs[kChunkWords];
+    int nk = sm.offs[0];
     rowbase = __builtin_amdgcn_readfirstlane(sm.prc[prow][0]);
     for (int t = tid; t < nk; t += 512) {
       const int K = sm.klist[t];
