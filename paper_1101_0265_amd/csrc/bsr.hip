@@ -674,6 +674,29 @@ __global__ __launch_bounds__(256) void bsr_compact_kernel(const int32_t* __restr
 }
 
 // ---- f0 on blocks -----------------------------------------------------------------------
+// Copy of X that reads only its upper blocks (I <= J, upper half of diagonal blocks): every
+// lower block is written as the transpose of its mirror, so the copy is exactly symmetric
+// (the numeric kernel reads both halves of the block rows of its super-tile).
+__global__ __launch_bounds__(256) void bsr_sym_copy_kernel(const int32_t* __restrict__ row_ptr,
+                                                           const int32_t* __restrict__ col,
+                                                           const uint32_t* __restrict__ bm,
+                                                           const int32_t* __restrict__ pre,
+                                                           int W, const float* __restrict__ vin,
+                                                           float* __restrict__ vout, int nbrows) {
+  for (int I = blockIdx.x; I < nbrows; I += gridDim.x) {
+    for (int p = row_ptr[I]; p < row_ptr[I + 1]; ++p) {
+      const int J = col[p];
+      const int src = (I <= J) ? p : bsr_find(row_ptr, bm, pre, W, J, I);
+      for (int e = threadIdx.x; e < kBB; e += blockDim.x) {
+        const int r = e / kB, c = e % kB;
+        const bool direct = I < J || (I == J && r <= c);
+        vout[(size_t)p * kBB + e] = direct ? vin[(size_t)src * kBB + r * kB + c]
+                                           : vin[(size_t)src * kBB + c * kB + r];
+      }
+    }
+  }
+}
+
 // X_0 = (lambda_max I - F)/(lambda_max - lambda_min), block by block, reading only F's
 // upper blocks (I <= J, upper half of diagonal blocks) and mirroring.
 __global__ __launch_bounds__(256) void bsr_f0_kernel(const int32_t* __restrict__ row_ptrF,
@@ -1407,8 +1430,10 @@ int snf_step_bsr(const snf_bsr* Xin, double c2, double c1, double c0, double tru
   X.nnzb = Xin->nnzb;
   BSR_HIP(hipMemcpyAsync(X.row_ptr.p, Xin->row_ptr, (nb + 1) * 4, hipMemcpyDeviceToDevice, s));
   BSR_HIP(hipMemcpyAsync(X.col.p, Xin->col_idx, Xin->nnzb * 4, hipMemcpyDeviceToDevice, s));
-  BSR_HIP(hipMemcpyAsync(X.val.p, Xin->val, (size_t)Xin->nnzb * kBB * 4, hipMemcpyDeviceToDevice, s));
   if ((rc = build_lookup(X, nb, W, s))) return rc;
+  hipLaunchKernelGGL(bsr_sym_copy_kernel, dim3(kF0Blocks), dim3(256), 0, s, X.row_ptr.p, X.col.p,
+                     X.bm.p, X.pre.p, W, Xin->val, X.val.p, nb);
+  BSR_HIP(hipGetLastError());
   int slots = 0;
   if ((rc = bsr_step(w, X, X, X, w->X[1], nb, W, trunc_tau * trunc_tau, &slots, w->ev[2],
                      w->ev[3], s, -1.0, screen_tau * screen_tau)))

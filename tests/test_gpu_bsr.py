@@ -80,6 +80,32 @@ def test_step_matches_masked_numpy(snf, L, tau):
     assert abs(sums[2] - np.sum(Y * Y)) <= 1e-5 * np.sum(Y * Y)
 
 
+def test_step_reads_only_upper_blocks(snf):
+    """snf_step_bsr reads blocks (I, J) with I <= J and the upper half of diagonal blocks only
+    (the documented contract): noise in the lower blocks and in the lower halves of the
+    diagonal blocks leaves the result bitwise unchanged."""
+    m, h = H.lattice_bsr((8, 8, 4), seed=11)
+    n = m.n
+    X = (h.lambda_max * np.eye(n) - m.to_dense()) / (h.lambda_max - h.lambda_min)
+    Xm = H.dense_to_bsr(X, 32)
+    noisy = Xm.val.astype(np.float32).copy()
+    rng = np.random.default_rng(5)
+    low = np.tril(np.ones((32, 32), bool), -1)
+    for i in range(m.nb):
+        for p in range(Xm.row_ptr[i], Xm.row_ptr[i + 1]):
+            j = Xm.col_idx[p]
+            if j < i:
+                noisy[p] = rng.standard_normal((32, 32))
+            elif j == i:
+                noisy[p][low] = rng.standard_normal(int(low.sum()))
+    Xn = H.BSRMatrix(n=n, b=32, row_ptr=Xm.row_ptr, col_idx=Xm.col_idx, val=noisy)
+    args = (n, -1.44, 2.4, 0.0)
+    (rp0, ci0, va0), s0, _ = snf.step_bsr(*_dev_bsr(Xm), *args, trunc_tau=1e-6)
+    (rp1, ci1, va1), s1, _ = snf.step_bsr(*_dev_bsr(Xn), *args, trunc_tau=1e-6)
+    assert torch.equal(rp0, rp1) and torch.equal(ci0, ci1) and torch.equal(va0, va1)
+    assert s0 == s1
+
+
 @pytest.mark.parametrize("L", [(8, 8, 4), (8, 8, 8), (16, 16, 8)])
 @pytest.mark.parametrize("scheme", ["snf_varmu", "sp2", "tc2", "snf_fixmu", "mcweeny"])
 def test_purify_bsr_vs_masked_oracle(snf, L, scheme):
