@@ -22,11 +22,13 @@ includes that certifying product; Algorithm 1 counts two products per iteration.
 itself spends extra products (it forms X^2 for the check separately from the step) -- it is
 slow on purpose and the count it reports is the scheme's, not its own.
 
-``screen`` (optional, one-product schemes only): ``(b, tau_s)`` replaces X.X by the
-norm-screened block product (``screened_square``) in both the idempotency check and the step,
-and the step takes the printed polynomial in expanded form, c2 P + c1 X + c0 I, so that it
-uses that product.  Not in the paper: the screening is the other use of the decay of the
-blocks next to truncation, and its threshold rule is a reading.
+``screen`` (optional; the one-product schemes, Algorithm 1 and McWeeny): ``(b, tau_s)``
+replaces every block product by the norm-screened one (``screened_product``): X.X in the
+idempotency check, and in the step the printed polynomial in expanded form, c2 P + c1 X +
+c0 I for Algorithm 2's maps, and for Algorithm 1 S2 = Xs^2 written out from the screened X.X,
+then the screened S2.X (``step_expanded_alg1``).  Not in the paper: the screening is the
+other use of the decay of the blocks next to truncation, and its threshold rule is a
+reading.
 
 ``mask`` (optional): a callable applied to each new X, used by the block-truncation oracle
 (drop blocks below a threshold after every step, the BSR reading).  A mask with
@@ -85,23 +87,32 @@ def step(X: np.ndarray, branch: str, alpha: float, st: "sch.SchemeState" = None)
     return Y
 
 
-def screened_square(X: np.ndarray, b: int, tau_s: float) -> np.ndarray:
-    """X.X with every block product X_IK X_KJ whose factors have Frobenius norms with
+def screened_product(A: np.ndarray, B: np.ndarray, b: int, tau_s: float) -> np.ndarray:
+    """A.B with every block product A_IK B_KJ whose factors have Frobenius norms with
     product below ``tau_s`` left out of block (I, J): P = sum over block columns K of the
-    outer product of block column K and block row K, each block (I, J) of it kept iff
-    ||X_IK||_F ||X_KJ||_F >= tau_s.  Each term left out has norm below tau_s
+    outer product of block column K of A and block row K of B, each block (I, J) of it kept
+    iff ||A_IK||_F ||B_KJ||_F >= tau_s.  Each term left out has norm below tau_s
     (||AB||_F <= ||A||_F ||B||_F).  tau_s = 0 keeps every term."""
-    n = X.shape[0]
+    n = A.shape[0]
     nb = n // b
-    blocks = X.reshape(nb, b, nb, b)
-    norms = np.sqrt(np.einsum("ibjc,ibjc->ij", blocks, blocks))
-    P = np.zeros_like(X)
+
+    def block_norms(M):
+        blocks = M.reshape(nb, b, nb, b)
+        return np.sqrt(np.einsum("ibjc,ibjc->ij", blocks, blocks))
+
+    na, nbn = block_norms(A), block_norms(B)
+    P = np.zeros_like(A)
     for K in range(nb):
-        col = X[:, K * b:(K + 1) * b]
-        row = X[K * b:(K + 1) * b, :]
-        keep = np.outer(norms[:, K], norms[K, :]) >= tau_s
+        col = A[:, K * b:(K + 1) * b]
+        row = B[K * b:(K + 1) * b, :]
+        keep = np.outer(na[:, K], nbn[K, :]) >= tau_s
         P += np.kron(keep, np.ones((b, b))) * (col @ row)
     return P
+
+
+def screened_square(X: np.ndarray, b: int, tau_s: float) -> np.ndarray:
+    """X.X norm-screened as in ``screened_product``."""
+    return screened_product(X, X, b, tau_s)
 
 
 def step_expanded(X: np.ndarray, P: np.ndarray, branch: str, alpha: float) -> np.ndarray:
@@ -114,6 +125,18 @@ def step_expanded(X: np.ndarray, P: np.ndarray, branch: str, alpha: float) -> np
     if branch == sch.FOLD:
         return 2.0 * (1.0 + alpha) * X - (1.0 + alpha) ** 2 * P
     raise ValueError("the expanded step covers the one-product schemes only")
+
+
+def step_expanded_alg1(X: np.ndarray, P: np.ndarray, alpha: float, b: int,
+                       tau_s: float) -> np.ndarray:
+    """Algorithm 1's step 3 Xs^2 - 2 Xs^3 (Xs = a X + c I, c = (1 - a)/2) written out with P
+    standing for X^2: S2 = Xs^2 = a^2 P + 2 a c X + c^2 I, Xs^3 = a S2.X + c S2, so
+    X_new = (3 - 2c) S2 - 2 a R with R = S2.X, the second product screened at tau_s."""
+    I = np.eye(X.shape[0])
+    c = 0.5 * (1.0 - alpha)
+    S2 = alpha * alpha * P + 2.0 * alpha * c * X + c * c * I
+    R = screened_product(S2, X, b, tau_s)
+    return (3.0 - 2.0 * c) * S2 - 2.0 * alpha * R
 
 
 def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
@@ -129,8 +152,9 @@ def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
     """
     if F.ndim != 2 or F.shape[0] != F.shape[1]:
         raise ValueError("F must be square")
-    if screen is not None and scheme not in ("sp2", "tc2", "snf_varmu"):
-        raise ValueError("norm screening applies to the one-product schemes")
+    if screen is not None and scheme not in ("sp2", "tc2", "snf_varmu", "snf_fixmu", "mcweeny"):
+        raise ValueError("norm screening applies to the one-product schemes, Algorithm 1 and "
+                         "McWeeny")
     st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi,
                          poly_ij=poly_ij)
     X = f0(np.asarray(F, dtype=np.float64), scheme, lambda_min, lambda_max, mu, st)
@@ -166,7 +190,12 @@ def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
                    margin=(sch.trace_margin(t1, t2, n_occ) if scheme == "sp2" else None))
         log.append(rec)
         branches.append(branch)
-        X = step(X, branch, alpha, st) if screen is None else step_expanded(X, X2, branch, alpha)
+        if screen is None:
+            X = step(X, branch, alpha, st)
+        elif branch == sch.MCW:
+            X = step_expanded_alg1(X, X2, alpha, *screen)
+        else:
+            X = step_expanded(X, X2, branch, alpha)
         st.advance(branch, alpha)
         if gap_mask:
             X = mask(X, st.betabar - st.beta)

@@ -4,9 +4,10 @@ Screening leaves the block product X_IK X_KJ out of (X.X)_IJ when ||X_IK||_F ||X
 below a threshold (the block-sparse path's use of the decay of the blocks next to
 truncation; the paper only says that the schemes combine with such approximations, the rule
 is a reading).  Pinned against: the library matrix product when nothing is screened, a
-brute-force loop over block triples on tiny inputs, the norm bound on what is left out, the
-empty product above every norm product, and the unscreened iteration, which a threshold
-below every term reproduces.
+brute-force loop over block triples on tiny inputs (a square and a product of two different,
+non-symmetric matrices), the norm bound on what is left out, the empty product above every
+norm product, Algorithm 1's printed map for its written-out step, and the unscreened
+iteration, which a threshold below every term reproduces.
 """
 import math
 
@@ -119,8 +120,66 @@ def test_screened_iteration_error_grows_with_the_threshold():
     assert errs[0] <= errs[1] <= errs[2]
 
 
-def test_screening_rejects_multi_product_schemes():
+def test_screening_rejects_higher_order_schemes():
     F = np.diag(np.linspace(-1, 1, 64))
-    with pytest.raises(ValueError):
-        dense.purify(F, "snf_fixmu", lambda_min=-1, lambda_max=1, mu=0.0, xi=0.1,
-                     screen=(32, 1e-6))
+    for scheme in ("snf_fixmu3", "pmm5"):
+        with pytest.raises(ValueError):
+            dense.purify(F, scheme, lambda_min=-1, lambda_max=1, mu=0.0, xi=0.1,
+                         screen=(32, 1e-6))
+
+
+@pytest.mark.parametrize("q", [0.2, 0.5, 0.8])
+def test_product_brute_force_block_triples(q):
+    """Two different, non-symmetric factors: a transposed operand or the norms of the wrong
+    factor would change which triples are kept.  The threshold lies halfway between two
+    neighbouring norm products near the q-quantile (no ties), so some triples are kept and
+    some left out."""
+    nb, b = 3, 4
+    A = _graded(nb, b, 17) + 0.3 * _graded(nb, b, 18) @ np.diag(np.arange(1.0, nb * b + 1))
+    B = _graded(nb, b, 19) * np.kron(np.triu(np.ones((nb, nb))) + 1e-4, np.ones((b, b)))
+    blk = lambda M, I, J: M[I * b:(I + 1) * b, J * b:(J + 1) * b]  # noqa: E731
+    prods = [np.linalg.norm(blk(A, I, K)) * np.linalg.norm(blk(B, K, J))
+             for I in range(nb) for J in range(nb) for K in range(nb)]
+    srt = np.sort(prods)
+    k = int(q * len(srt))
+    tau_s = float(0.5 * (srt[k] + srt[k + 1]))
+    P = np.zeros_like(A)
+    skipped = 0
+    for I in range(nb):
+        for J in range(nb):
+            acc = np.zeros((b, b))
+            for K in range(nb):
+                if np.linalg.norm(blk(A, I, K)) * np.linalg.norm(blk(B, K, J)) >= tau_s:
+                    acc += blk(A, I, K) @ blk(B, K, J)
+                else:
+                    skipped += 1
+            P[I * b:(I + 1) * b, J * b:(J + 1) * b] = acc
+    assert np.allclose(dense.screened_product(A, B, b, tau_s), P, rtol=1e-13, atol=1e-300)
+    assert 0 < skipped < nb ** 3
+    assert np.allclose(dense.screened_product(A, B, b, 0.0), A @ B, rtol=1e-13, atol=1e-300)
+
+
+@pytest.mark.parametrize("alpha", [0.2, 0.7, 1.0])
+def test_alg1_written_out_step_equals_the_printed_map(alpha):
+    """3 Xs^2 - 2 Xs^3 with Xs = a (X - I/2) + I/2, from the written-out form (X.X given,
+    S2.X formed); a = 1 is McWeeny's 3 X^2 - 2 X^3."""
+    X = _graded(4, 5, 23)
+    X = 0.5 * np.eye(X.shape[0]) + 0.4 * X / np.abs(np.linalg.eigvalsh(X)).max()
+    I = np.eye(X.shape[0])
+    Xs = alpha * (X - 0.5 * I) + 0.5 * I
+    printed = 3.0 * Xs @ Xs - 2.0 * Xs @ Xs @ Xs
+    got = dense.step_expanded_alg1(X, X @ X, alpha, 5, 0.0)
+    assert np.allclose(got, printed, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("scheme", ["snf_fixmu", "mcweeny"])
+def test_tiny_threshold_reproduces_the_unscreened_alg1_iteration(scheme):
+    m, h = H.lattice_bsr((4, 4, 4), seed=3, dtype=np.float64)
+    F = m.to_dense()
+    kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, mu=h.mu, xi=h.xi, tol=1e-10,
+              max_iter=60)
+    a = dense.purify(F, scheme, **kw)
+    b = dense.purify(F, scheme, screen=(32, 1e-300), **kw)
+    assert a["status"] == b["status"] == "ok"
+    assert a["branches"] == b["branches"] and a["products"] == b["products"]
+    assert np.linalg.norm(a["D"] - b["D"]) <= 1e-11 * math.sqrt(F.shape[0])
