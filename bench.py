@@ -535,17 +535,20 @@ def run_bsr(args):
             del D
     if args.bsr_fixmu:
         # Algorithm 1 (two products per iteration, truncation after the second) beside
-        # Algorithm 2 and the trace scheme, tau = 1e-6; accuracy from ||[F, D]||_F
+        # Algorithm 2 and the trace scheme, tau = 1e-6, unscreened and norm-screened at 1e-8;
+        # accuracy from ||[F, D]||_F
         kw1 = dict(kw, mu=h.mu, xi=h.xi)
-        for scheme in ("snf_fixmu", "snf_varmu", "sp2"):
+        for scheme, sigma in [(sc, sg) for sg in (0.0, 1e-8)
+                              for sc in ("snf_fixmu", "snf_varmu", "sp2")]:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            D, r = snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=1e-6, **kw1)
+            D, r = snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=1e-6,
+                                  **dict(kw1, screen_tau=sigma))
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3
             comm = _bsr_commutator((rp, ci, va), D, m.n)
             peak = max(x["phase"] for x in r["log"]) / m.nb
-            print(json.dumps(dict(scheme=scheme, tau=1e-6, ms=round(ms, 1),
+            print(json.dumps(dict(scheme=scheme, tau=1e-6, screen_tau=sigma, ms=round(ms, 1),
                                   products=r["products"], iterations=r["iterations"],
                                   status=r["status"], e=r["idem_err"],
                                   trace_err=r["trace_err"], commutator=comm,

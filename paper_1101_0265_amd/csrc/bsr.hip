@@ -14,9 +14,10 @@
 //                           (J_b, K) of B's block rows J_b (B symmetric: B_{K,J} = B_{J,K}^T),
 //                           so every operand comes from the super-tile's own 8 block rows,
 //                           read in column order, and sits in LDS with its k values
-//                           contiguous; zero when absent.  With norm screening (squares only;
-//                           bsr_block_norms_kernel first), a block pair whose norm product is
-//                           below the threshold is left out as if absent.  Fused epilogue:
+//                           contiguous; zero when absent.  With norm screening
+//                           (bsr_block_norms_kernel first, for each operand), a block pair
+//                           whose norm product is below the threshold is left out as if
+//                           absent.  Fused epilogue:
 //                           Y = c2 P + c1 L + c0 I (L = X, or S2), FP64 sums, block norms;
 //                           upper blocks written with their transposed mirror.
 //   5. bsr_truncate_kernel  keep (I,J) and (J,I) iff ||Y_IJ||_F >= tau (diagonal always; tau
@@ -183,7 +184,8 @@ struct BsrProductArgs {
   double* normP;       // squared Frobenius norm per candidate block
   const int32_t* tiles;  // (TI << 16) | TJ
   double* partials;    // [tiles][4]
-  const double* nrmX;  // squared Frobenius norm per block of X (screening only)
+  const double* nrmX;  // squared Frobenius norm per block of A (screening only)
+  const double* nrmY;  // the same for B (nrmX when B is A)
   double screen2;      // screening threshold squared; 0: no screening
   int nb, W;
 };
@@ -414,12 +416,12 @@ __global__ __launch_bounds__(512, 4) void bsr_product_kernel(const SnfState* __r
 #pragma unroll
       for (int a = 0; a < kSup; ++a)
         if ((ba >> a) & 1u) m |= bb << (4 * a);
-      if (g.screen2 > 0.0 && m) {          // (squares only: both sides index nrmX)
+      if (g.screen2 > 0.0 && m) {
         double na[kSup], nbv[kSup];
 #pragma unroll
         for (int a = 0; a < kSup; ++a) {
           na[a] = ((ba >> a) & 1u) ? g.nrmX[pa[a]] : 0.0;
-          nbv[a] = ((bb >> a) & 1u) ? g.nrmX[pb[a]] : 0.0;
+          nbv[a] = ((bb >> a) & 1u) ? g.nrmY[pb[a]] : 0.0;
         }
         uint32_t drop = 0u;
 #pragma unroll
@@ -822,7 +824,7 @@ struct BsrWorkspace {
   // the schedule's buffer indices 0..3 (operands, linear term and output of each product)
   BsrBuf& buf(int i) { return i == 0 ? X[0] : i == 1 ? X[1] : i == 2 ? S : T; }
   DevArr<double> normP, partials, sums;
-  DevArr<double> nrmX;          // norm screening: squared norms of the operand's blocks
+  DevArr<double> nrmX, nrmY;    // norm screening: squared norms of the operands' blocks
   DevArr<int32_t> cnt, rank, tiles;
   DevArr<int64_t> triples;
   int64_t last_triples = 0;
@@ -866,6 +868,7 @@ void bsr_release_all_devices() {
     w->partials.release();
     w->sums.release();
     w->nrmX.release();
+    w->nrmY.release();
     w->val2.release();
     w->cnt.release();
     w->rank.release();
@@ -982,12 +985,17 @@ static int bsr_step(BsrWorkspace* w, BsrBuf& X, BsrBuf& B, BsrBuf& L, BsrBuf& N,
                     BsrBuf* N2 = nullptr) {
   BsrBuf& P = w->P;
   int rc;
-  if (&B != &X) screen2 = 0.0;           // screening indexes one operand's norms
-  // 1b. operand block norms for the screening
+  // 1b. operand block norms for the screening (B's own when it is another matrix)
   if (screen2 > 0.0 && X.nnzb > 0) {
     if ((rc = w->nrmX.reserve(X.nnzb))) return rc;
     hipLaunchKernelGGL(bsr_block_norms_kernel, dim3((unsigned)((X.nnzb + 3) / 4)), dim3(256), 0,
                        s, X.val.p, X.nnzb, w->nrmX.p);
+    BSR_HIP(hipGetLastError());
+  }
+  if (screen2 > 0.0 && &B != &X && B.nnzb > 0) {
+    if ((rc = w->nrmY.reserve(B.nnzb))) return rc;
+    hipLaunchKernelGGL(bsr_block_norms_kernel, dim3((unsigned)((B.nnzb + 3) / 4)), dim3(256), 0,
+                       s, B.val.p, B.nnzb, w->nrmY.p);
     BSR_HIP(hipGetLastError());
   }
   // 2. symbolic
@@ -1049,6 +1057,7 @@ static int bsr_step(BsrWorkspace* w, BsrBuf& X, BsrBuf& B, BsrBuf& L, BsrBuf& N,
   args.tiles = w->tiles.p;
   args.partials = w->partials.p;
   args.nrmX = screen2 > 0.0 ? w->nrmX.p : nullptr;
+  args.nrmY = screen2 > 0.0 ? (&B == &X ? w->nrmX.p : w->nrmY.p) : nullptr;
   args.screen2 = screen2 > 0.0 ? screen2 : 0.0;
   args.nb = nb;
   args.W = W;
@@ -1252,10 +1261,12 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
   if (fixmu) {
     // the fixed-mu parameters as on the dense path (checked as for FP64, where the dense
     // path offers P_{m,m}; the block-sparse products are FP32 either way); the
-    // error-control budget and the screening follow Algorithm 2's one-product steps and are
-    // not offered here
+    // error-control budget follows Algorithm 2's one-product steps and is not offered here;
+    // norm screening is, for Algorithm 1 and McWeeny (both products of an iteration:
+    // X.X and S2.X), not for the P_{m,m} and P_{i,j} schemes
+    const bool alg1 = scheme == SNF_SNF_FIXMU || scheme == SNF_MCWEENY;
     if (validate(F ? F->n : 0, params, scheme, SNF_P_FP64) != SNF_OK ||
-        (p.flags & SNF_FLAG_TRUNC_ERROR_CONTROL) || p.screen_tau > 0.0)
+        (p.flags & SNF_FLAG_TRUNC_ERROR_CONTROL) || (p.screen_tau > 0.0 && !alg1))
       return fail(SNF_EINVAL);
   } else if (!isfinite(p.lambda_min) || !isfinite(p.lambda_max) ||
              !(p.lambda_min < p.lambda_max) || !(p.tol > 0.0) || p.max_iter < 1 ||
