@@ -22,13 +22,16 @@ includes that certifying product; Algorithm 1 counts two products per iteration.
 itself spends extra products (it forms X^2 for the check separately from the step) -- it is
 slow on purpose and the count it reports is the scheme's, not its own.
 
-``screen`` (optional; the one-product schemes, Algorithm 1 and McWeeny): ``(b, tau_s)``
-replaces every block product by the norm-screened one (``screened_product``): X.X in the
-idempotency check, and in the step the printed polynomial in expanded form, c2 P + c1 X +
-c0 I for Algorithm 2's maps, and for Algorithm 1 S2 = Xs^2 written out from the screened X.X,
-then the screened S2.X (``step_expanded_alg1``).  Not in the paper: the screening is the
-other use of the decay of the blocks next to truncation, and its threshold rule is a
-reading.
+``screen`` (optional): ``(b, tau_s)`` replaces every block product by the norm-screened one
+(``screened_product``): X.X in the idempotency check, and in the step the printed polynomial
+written out in products, c2 P + c1 X + c0 I for Algorithm 2's maps, for Algorithm 1
+S2 = Xs^2 from the screened X.X, then the screened S2.X (``step_expanded_alg1``), for
+P_{m,m} and P_{i,j} W = v^2 from the screened X.X, the Horner levels and the last product
+with v, each screened (``step_expanded_pmm``, ``step_expanded_pij``).  A screened product
+depends on the order of its factors (the norms of A's blocks meet those of B's), so the
+written-out steps fix it: W.T for P_{m,m}, T.W for P_{i,j}, X.T last.  Not in the paper: the
+screening is the other use of the decay of the blocks next to truncation, and its threshold
+rule is a reading.
 
 ``mask`` (optional): a callable applied to each new X, used by the block-truncation oracle
 (drop blocks below a threshold after every step, the BSR reading).  A mask with
@@ -40,6 +43,7 @@ Parity: pinned against the exact projector, its invariants and the spectral orac
 from __future__ import annotations
 
 import math
+from fractions import Fraction
 
 import numpy as np
 
@@ -139,6 +143,60 @@ def step_expanded_alg1(X: np.ndarray, P: np.ndarray, alpha: float, b: int,
     return (3.0 - 2.0 * c) * S2 - 2.0 * alpha * R
 
 
+def pmm_r_exact(m: int) -> list:
+    """r_0..r_m (``Fraction``) of P_{m,m}(1/2 + v) = 1/2 + v r(v^2), from the exact monomial
+    coefficients of P_{m,m} shifted to v = x - 1/2 (the odd powers of v)."""
+    p = poly.p_ij_exact(m, m)
+    c = [Fraction(0)] * len(p)
+    for deg, pd in enumerate(p):
+        for t in range(deg + 1):
+            c[t] += pd * math.comb(deg, t) * Fraction(1, 2) ** (deg - t)
+    return [c[2 * k + 1] for k in range(m + 1)]
+
+
+def pij_q(i: int, j: int, xs: float) -> list:
+    """q_0..q_(i+j) (FP64) of P_{i,j}(x* + v) = x* + v Q(v), Q(v) = sum_k q_k v^k: P's exact
+    monomial coefficients shifted to v = x - x*."""
+    p = [float(v) for v in poly.p_ij_exact(i, j)]
+    d = len(p) - 1
+    c = [sum(p[deg] * math.comb(deg, t) * xs ** (deg - t) for deg in range(t, d + 1))
+         for t in range(d + 1)]
+    return c[1:]
+
+
+def step_expanded_pmm(X: np.ndarray, P: np.ndarray, alpha: float, m: int, b: int,
+                      tau_s: float) -> np.ndarray:
+    """P_{m,m}(Xs) = I/2 + V r(W), V = a (X - I/2), W = V^2 = a^2 (P - X + I/4) with P
+    standing for X^2; r(W) by Horner's rule from the top, the first level from W.W, then
+    T <- W.T + r_k I; last V.T = a X.T - (a/2) T.  Products screened at tau_s."""
+    I = np.eye(X.shape[0])
+    r = [float(v) for v in pmm_r_exact(m)]
+    a2 = alpha * alpha
+    W = a2 * P - a2 * X + 0.25 * a2 * I
+    T = r[m] * screened_product(W, W, b, tau_s) + r[m - 1] * W + r[m - 2] * I
+    for k in range(m - 3, -1, -1):
+        T = screened_product(W, T, b, tau_s) + r[k] * I
+    return alpha * screened_product(X, T, b, tau_s) - 0.5 * alpha * T + 0.5 * I
+
+
+def step_expanded_pij(X: np.ndarray, P: np.ndarray, alpha: float, i: int, j: int, xs: float,
+                      b: int, tau_s: float) -> np.ndarray:
+    """P_{i,j}(Xs) = x* I + V Q(V), V = a (X - x* I), W = V^2 = a^2 (P - 2 x* X + x*^2 I) with
+    P standing for X^2, Q(V) = sum_k (q_2k I + q_(2k+1) V) W^k (h = (i + j)/2 levels): top
+    level T = q_2h W + q_(2h-1) V + q_(2h-2) I, then T <- T.W + q_(2k+1) V + q_2k I, last
+    V.T = a X.T - a x* T.  Products screened at tau_s."""
+    I = np.eye(X.shape[0])
+    q = pij_q(i, j, xs)
+    h = (i + j) // 2
+    a2 = alpha * alpha
+    W = a2 * P - 2.0 * a2 * xs * X + a2 * xs * xs * I
+    V = alpha * (X - xs * I)
+    T = q[2 * h] * W + q[2 * h - 1] * V + q[2 * h - 2] * I
+    for k in range(h - 2, -1, -1):
+        T = screened_product(T, W, b, tau_s) + q[2 * k + 1] * V + q[2 * k] * I
+    return alpha * screened_product(X, T, b, tau_s) - alpha * xs * T + xs * I
+
+
 def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
            n_occ: int = None, homo: float = None, lumo: float = None, mu: float = None,
            xi: float = None, tol: float = 1e-10, max_iter: int = 200, mask=None,
@@ -152,9 +210,6 @@ def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
     """
     if F.ndim != 2 or F.shape[0] != F.shape[1]:
         raise ValueError("F must be square")
-    if screen is not None and scheme not in ("sp2", "tc2", "snf_varmu", "snf_fixmu", "mcweeny"):
-        raise ValueError("norm screening applies to the one-product schemes, Algorithm 1 and "
-                         "McWeeny")
     st = sch.SchemeState(scheme, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi,
                          poly_ij=poly_ij)
     X = f0(np.asarray(F, dtype=np.float64), scheme, lambda_min, lambda_max, mu, st)
@@ -194,6 +249,10 @@ def purify(F: np.ndarray, scheme: str, *, lambda_min: float, lambda_max: float,
             X = step(X, branch, alpha, st)
         elif branch == sch.MCW:
             X = step_expanded_alg1(X, X2, alpha, *screen)
+        elif branch in sch.PMM.values():
+            X = step_expanded_pmm(X, X2, alpha, 3 if branch == sch.PMM[3] else 5, *screen)
+        elif branch == sch.PIJ:
+            X = step_expanded_pij(X, X2, alpha, st.i, st.j, st.xs, *screen)
         else:
             X = step_expanded(X, X2, branch, alpha)
         st.advance(branch, alpha)

@@ -14,7 +14,9 @@ import math
 import numpy as np
 import pytest
 
-from oracle import dense
+from fractions import Fraction
+
+from oracle import dense, polynomials, schedule
 from paper_1101_0265_amd import hamiltonians as H
 
 
@@ -120,14 +122,6 @@ def test_screened_iteration_error_grows_with_the_threshold():
     assert errs[0] <= errs[1] <= errs[2]
 
 
-def test_screening_rejects_higher_order_schemes():
-    F = np.diag(np.linspace(-1, 1, 64))
-    for scheme in ("snf_fixmu3", "pmm5"):
-        with pytest.raises(ValueError):
-            dense.purify(F, scheme, lambda_min=-1, lambda_max=1, mu=0.0, xi=0.1,
-                         screen=(32, 1e-6))
-
-
 @pytest.mark.parametrize("q", [0.2, 0.5, 0.8])
 def test_product_brute_force_block_triples(q):
     """Two different, non-symmetric factors: a transposed operand or the norms of the wrong
@@ -183,3 +177,79 @@ def test_tiny_threshold_reproduces_the_unscreened_alg1_iteration(scheme):
     assert a["status"] == b["status"] == "ok"
     assert a["branches"] == b["branches"] and a["products"] == b["products"]
     assert np.linalg.norm(a["D"] - b["D"]) <= 1e-11 * math.sqrt(F.shape[0])
+
+
+def _poly_eval(coeffs, x):
+    acc = Fraction(0)
+    for c in reversed(coeffs):
+        acc = acc * x + c
+    return acc
+
+
+@pytest.mark.parametrize("m", [1, 3, 5])
+def test_pmm_shifted_coefficients(m):
+    """r_k of P_{m,m}(1/2 + v) = 1/2 + v r(v^2): the closed form c_m C(m, k) (-1)^k
+    4^(k-m) / (2k + 1), c_m = (2m+1)! / (m!)^2 (integrating P' = c_m (1/4 - v^2)^m), and the
+    polynomial itself at rational points (so no even power of v is lost)."""
+    r = dense.pmm_r_exact(m)
+    cm = Fraction(math.factorial(2 * m + 1), math.factorial(m) ** 2)
+    for k in range(m + 1):
+        assert r[k] == cm * math.comb(m, k) * (-1) ** k * Fraction(4) ** (k - m) / (2 * k + 1)
+    p = polynomials.p_ij_exact(m, m)
+    for v in (Fraction(-2, 5), Fraction(1, 7), Fraction(3, 10)):
+        rv = sum(rk * (v * v) ** k for k, rk in enumerate(r))
+        assert _poly_eval(p, Fraction(1, 2) + v) == Fraction(1, 2) + v * rv
+
+
+@pytest.mark.parametrize("ij", [(1, 3), (3, 1), (3, 5), (5, 3), (1, 5)])
+def test_pij_shifted_coefficients(ij):
+    """q_k of P_{i,j}(x* + v) = x* + v Q(v): the polynomial at points around x* (x* its
+    unstable fixed point)."""
+    i, j = ij
+    xs = schedule.pij_xstar(i, j)
+    q = dense.pij_q(i, j, xs)
+    p = [float(c) for c in polynomials.p_ij_exact(i, j)]
+    assert len(q) == i + j + 1
+    for v in np.linspace(-xs, 1.0 - xs, 9):
+        lhs = xs + v * sum(qk * v ** k for k, qk in enumerate(q))
+        rhs = sum(pk * (xs + v) ** k for k, pk in enumerate(p))
+        assert abs(lhs - rhs) <= 1e-13
+
+
+def _unit_interval_matrix(seed, n=40):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    A = A + A.T
+    return 0.5 * np.eye(n) + 0.45 * A / np.abs(np.linalg.eigvalsh(A)).max()
+
+
+@pytest.mark.parametrize("m,alpha", [(3, 0.6), (3, 1.0), (5, 0.8), (5, 1.0)])
+def test_pmm_written_out_step_equals_the_printed_map(m, alpha):
+    X = _unit_interval_matrix(31)
+    got = dense.step_expanded_pmm(X, X @ X, alpha, m, 8, 0.0)
+    want = dense.step(X, schedule.PMM[m], alpha)
+    assert np.allclose(got, want, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("ij,alpha", [((1, 3), 0.7), ((3, 1), 1.0), ((3, 5), 0.9),
+                                      ((5, 1), 0.8)])
+def test_pij_written_out_step_equals_the_printed_map(ij, alpha):
+    X = _unit_interval_matrix(37)
+    st = schedule.SchemeState("snf_pij", -1.0, 1.0, mu=0.1, xi=0.05, poly_ij=ij)
+    got = dense.step_expanded_pij(X, X @ X, alpha, ij[0], ij[1], st.xs, 8, 0.0)
+    want = dense.step(X, schedule.PIJ, alpha, st)
+    assert np.allclose(got, want, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("scheme,pij", [("snf_fixmu3", None), ("pmm5", None),
+                                        ("snf_pij", (1, 3)), ("pij", (3, 1))])
+def test_tiny_threshold_reproduces_the_unscreened_higher_order_iteration(scheme, pij):
+    m, h = H.lattice_bsr((4, 4, 4), seed=3, dtype=np.float64)
+    F = m.to_dense()
+    kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, mu=h.mu, xi=h.xi, tol=1e-10,
+              max_iter=60, poly_ij=pij)
+    a = dense.purify(F, scheme, **kw)
+    b = dense.purify(F, scheme, screen=(32, 1e-300), **kw)
+    assert a["status"] == b["status"] == "ok"
+    assert a["branches"] == b["branches"] and a["products"] == b["products"]
+    assert np.linalg.norm(a["D"] - b["D"]) <= 1e-10 * math.sqrt(F.shape[0])
