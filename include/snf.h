@@ -141,9 +141,11 @@ typedef enum {
  *             ignored by the other schemes.  For these two schemes the log's beta is a and
  *             its beta-bar is 1 - a' (the bounds of the two parts above).
  *  screen_tau: snf_purify_bsr only: norm screening of the block products, >= 0 (0 = off);
- *             see snf_step_bsr; for Algorithm 1 and McWeeny both products of an iteration
- *             (X.X and S2.X, the block product S2_IK X_KJ left out when
- *             ||S2_IK||_F ||X_KJ||_F < screen_tau).  Its error is not part of the budget of
+ *             see snf_step_bsr; for the fixed-mu schemes every product of an iteration
+ *             (for A.B the block product A_IK B_KJ is left out when
+ *             ||A_IK||_F ||B_KJ||_F < screen_tau: Algorithm 1's S2.X, the Horner levels W.T of
+ *             P_{m,m} and T.W of P_{i,j}, their last product X.T).  Its error is not part of
+ *             the budget of
  *             SNF_FLAG_TRUNC_ERROR_CONTROL; with a fixed threshold,
  *             screen_tau <= trunc_tau / 100 left the accuracy of the lattice solves
  *             unchanged.  Ignored by the dense paths.
@@ -301,8 +303,8 @@ typedef struct {
  * products), SNF_SNF_FIXMU_PIJ and SNF_PIJ (P_{i,j}: the first product writes W and the top
  * Horner level, then the levels, then X.T; (i + j)/2 + 1 products).  A fixed-mu iteration's
  * intermediates keep every candidate block and the truncation applies to its result; these
- * schemes do not take SNF_FLAG_TRUNC_ERROR_CONTROL; screen_tau applies to SNF_SNF_FIXMU and
- * SNF_MCWEENY and is rejected (SNF_EINVAL) for the P_{m,m} and P_{i,j} schemes.
+ * schemes do not take SNF_FLAG_TRUNC_ERROR_CONTROL; screen_tau applies to every product of
+ * their iterations.
  *   F:      caller-owned, device arrays; the pattern must be symmetric with every diagonal
  *           block present; only blocks (I,J) with I <= J (and the upper triangle of diagonal
  *           blocks) are read, the rest is taken as their transpose.

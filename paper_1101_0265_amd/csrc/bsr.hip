@@ -1262,11 +1262,9 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
     // the fixed-mu parameters as on the dense path (checked as for FP64, where the dense
     // path offers P_{m,m}; the block-sparse products are FP32 either way); the
     // error-control budget follows Algorithm 2's one-product steps and is not offered here;
-    // norm screening is, for Algorithm 1 and McWeeny (both products of an iteration:
-    // X.X and S2.X), not for the P_{m,m} and P_{i,j} schemes
-    const bool alg1 = scheme == SNF_SNF_FIXMU || scheme == SNF_MCWEENY;
+    // norm screening is, for every product of an iteration (each operand's own block norms)
     if (validate(F ? F->n : 0, params, scheme, SNF_P_FP64) != SNF_OK ||
-        (p.flags & SNF_FLAG_TRUNC_ERROR_CONTROL) || (p.screen_tau > 0.0 && !alg1))
+        (p.flags & SNF_FLAG_TRUNC_ERROR_CONTROL))
       return fail(SNF_EINVAL);
   } else if (!isfinite(p.lambda_min) || !isfinite(p.lambda_max) ||
              !(p.lambda_min < p.lambda_max) || !(p.tol > 0.0) || p.max_iter < 1 ||

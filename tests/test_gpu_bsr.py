@@ -208,11 +208,9 @@ def test_bsr_invalid_inputs(snf):
     with pytest.raises(RuntimeError):            # no error-control budget for Algorithm 1
         snf.purify_bsr(rp, ci, va, n, "snf_fixmu", mu=h.mu, xi=h.xi,
                        flags=snf.FLAG_TRUNC_ERROR_CONTROL, **kw)
-    with pytest.raises(RuntimeError):            # no norm screening for P_{m,m}, P_{i,j}
-        snf.purify_bsr(rp, ci, va, n, "snf_fixmu3", mu=h.mu, xi=h.xi, screen_tau=1e-9, **kw)
-    with pytest.raises(RuntimeError):
-        snf.purify_bsr(rp, ci, va, n, "snf_pij", mu=h.mu, xi=h.xi, poly_ij=(1, 3),
-                       screen_tau=1e-9, **kw)
+    with pytest.raises(RuntimeError):            # nor for P_{m,m}
+        snf.purify_bsr(rp, ci, va, n, "snf_fixmu3", mu=h.mu, xi=h.xi,
+                       flags=snf.FLAG_TRUNC_ERROR_CONTROL, **kw)
     with pytest.raises(RuntimeError):            # P_{i,j} needs odd i, j
         snf.purify_bsr(rp, ci, va, n, "snf_pij", mu=h.mu, xi=h.xi, poly_ij=(2, 3), **kw)
     # drop one off-diagonal block: the pattern is no longer symmetric
@@ -339,19 +337,25 @@ def test_step_screened_matches_oracle(snf, tau_s):
     assert np.array_equal(Y, Y.T)
 
 
-@pytest.mark.parametrize("scheme", ["snf_varmu", "tc2", "snf_fixmu", "mcweeny"])
-def test_purify_bsr_screened_vs_oracle(snf, scheme):
+@pytest.mark.parametrize("scheme,pij", [("snf_varmu", None), ("tc2", None),
+                                        ("snf_fixmu", None), ("mcweeny", None),
+                                        ("snf_fixmu3", None), ("pmm3", None),
+                                        ("snf_pij", (1, 3)), ("pij", (3, 1))])
+def test_purify_bsr_screened_vs_oracle(snf, scheme, pij):
     """Whole solves with truncation (tau = 1e-6) and norm screening (1e-8) on the 8x8x8-site
     lattice against the oracle with the same truncation rule and the same screening of its
-    FP64 iterates: identical decisions, D as close as for truncation alone.  Algorithm 1 and
-    McWeeny screen both products of an iteration (X.X and S2.X)."""
+    FP64 iterates: identical decisions, D as close as for truncation alone.  The fixed-mu
+    schemes screen every product of an iteration (Algorithm 1's S2.X, the Horner levels
+    W.T of P_{m,m} and T.W of P_{i,j}, the last X.T), each with its operands' block norms."""
     tau, tau_s = 1e-6, 1e-8
     m, h = H.lattice_bsr((8, 8, 8), seed=3)
     n = m.n
     kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
               lumo=h.lumo, tol=1e-9, max_iter=60)
-    if scheme in ("snf_fixmu", "mcweeny"):
+    if scheme not in ("snf_varmu", "tc2", "sp2"):
         kw.update(mu=h.mu, xi=h.xi)
+    if pij is not None:
+        kw.update(poly_ij=pij)
     (rp, ci, va), r = snf.purify_bsr(*_dev_bsr(m), n, scheme, trunc_tau=tau,
                                       screen_tau=tau_s, **kw)
     assert r["status"] in ("ok", "ok_floor"), r["status"]
