@@ -336,12 +336,16 @@ def drop_bin_limit(bins: np.ndarray, weights: np.ndarray, eps_i: float) -> int:
     return k
 
 
-def predicted_iterations(scheme: str, *, lambda_min: float, lambda_max: float, homo: float,
-                         lumo: float, eps: float, max_iter: int = 200) -> int:
-    """Iterations the scalar recurrence takes until max(beta, 1 - beta-bar) <= eps (the trace
-    scheme, whose choice needs the matrix, is predicted by its alpha = 0 recurrence)."""
+def predicted_iterations(scheme: str, *, lambda_min: float, lambda_max: float,
+                         homo: float = None, lumo: float = None, eps: float,
+                         max_iter: int = 200, mu: float = None, xi: float = None,
+                         poly_ij=None) -> int:
+    """Iterations the scalar recurrence takes until its a-priori bound (max(beta, 1 - beta-bar),
+    for P_{i,j} max(a, a')) is at most eps (the trace scheme, whose choice needs the matrix,
+    is predicted by its alpha = 0 recurrence).  The fixed-mu schemes take mu and xi."""
     sch_name = "tc2" if scheme == "sp2" else scheme
-    st = sch.SchemeState(sch_name, lambda_min, lambda_max, homo=homo, lumo=lumo)
+    st = sch.SchemeState(sch_name, lambda_min, lambda_max, homo=homo, lumo=lumo, mu=mu, xi=xi,
+                         poly_ij=poly_ij)
     for it in range(max_iter):
         if st.bound() <= eps:
             return max(it, 1)

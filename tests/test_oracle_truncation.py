@@ -94,3 +94,50 @@ def test_predicted_iterations_reach_the_bound():
             assert st.bound() <= eps < bounds[-1]
     assert dense.predicted_iterations("sp2", eps=1e-6, **kw) == \
         dense.predicted_iterations("tc2", eps=1e-6, **kw)
+
+
+@pytest.mark.parametrize("scheme,pij", [("snf_fixmu", None), ("mcweeny", None),
+                                        ("snf_fixmu3", None), ("snf_pij", (1, 3)),
+                                        ("snf_pij", (3, 1))])
+def test_predicted_iterations_fixed_mu(scheme, pij):
+    """The fixed-mu schemes: N is the first iteration whose bound is at most eps, and the
+    spectral oracle, run on the interval ends and the gap edges with the same decisions,
+    has its eigenvalue error within eps there (the bound covers the spectrum)."""
+    from oracle import schedule as sch
+    from oracle import spectral
+    lmin, lmax, mu, xi = -1.3, 1.1, 0.07, 0.06
+    lam = np.array([lmin, mu - xi / 2, mu + xi / 2, lmax])
+    occ = lam < mu
+    for eps in (1e-2, 1e-6):
+        N = dense.predicted_iterations(scheme, eps=eps, lambda_min=lmin, lambda_max=lmax,
+                                       mu=mu, xi=xi, poly_ij=pij)
+        st = sch.SchemeState(scheme, lmin, lmax, mu=mu, xi=xi, poly_ij=pij)
+        x = spectral.f0_eigs(lam, scheme, lmin, lmax, mu, st)
+        bounds = []
+        for _ in range(N):
+            bounds.append(st.bound())
+            branch, alpha = st.choose()
+            x = spectral.apply_branch(x, branch, alpha, st)
+            st.advance(branch, alpha)
+        assert st.bound() <= eps < bounds[-1]
+        err = np.max(np.abs(x - occ.astype(float)))
+        assert err <= eps * (1 + 1e-9) + 1e-15
+
+
+@pytest.mark.parametrize("scheme,pij", [("snf_fixmu", None), ("snf_pij", (1, 3))])
+def test_error_budget_holds_on_lattice_fixed_mu(scheme, pij):
+    """The same rule on a fixed-mu iteration (truncation of each iteration's result, the gap
+    of its bounds): the result stays within eps of the exact projector."""
+    eps = 1e-2
+    m, h = H.lattice_bsr((16, 8, 8), seed=3, dtype=np.float64)
+    Fd = m.to_dense()
+    D_ref = exact.projector(F=Fd, n_occ=h.n_occ)
+    kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, mu=h.mu, xi=h.xi,
+              poly_ij=pij)
+    N = dense.predicted_iterations(scheme, eps=eps, **kw)
+    mk = dense.ErrorControlledTruncation(32, eps, N)
+    o = dense.purify(Fd, scheme, n_occ=h.n_occ, tol=1e-12, max_iter=N + 6, mask=mk, **kw)
+    assert np.linalg.norm(o["D"] - D_ref) <= eps
+    assert any(d > 0.0 for _, _, d in mk.history)
+    for eps_i, _, dropped2 in mk.history:
+        assert dropped2 <= eps_i ** 2
