@@ -562,13 +562,17 @@ def run_bsr(args):
         D, _ = snf.purify_bsr(rp, ci, va, m.n, "tc2", trunc_tau=1e-2, want_log=False,
                               **dict(kw, flags=kw["flags"] | snf.FLAG_TRUNC_ERROR_CONTROL))
         del D
-        runs = [(sc, "tau", 1e-6) for sc in ("tc2", "snf_varmu")]
-        runs += [(sc, "eps", e) for sc in ("tc2", "snf_varmu") for e in (1e-1, 3e-2, 1e-2, 3e-3)]
+        runs = [(sc, "tau", 1e-6) for sc in ("tc2", "snf_varmu", "snf_fixmu")]
+        runs += [(sc, "eps", e) for sc in ("tc2", "snf_varmu", "snf_fixmu")
+                 for e in (1e-1, 3e-2, 1e-2, 3e-3)]
         for scheme, kind, val in runs:
             fl = kw["flags"] | (snf.FLAG_TRUNC_ERROR_CONTROL if kind == "eps" else 0)
+            skw = dict(kw, flags=fl)
+            if scheme == "snf_fixmu":                  # Algorithm 1: mu mid-gap, xi the gap
+                skw.update(mu=h.mu, xi=h.xi)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            D, r = snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=val, **dict(kw, flags=fl))
+            D, r = snf.purify_bsr(rp, ci, va, m.n, scheme, trunc_tau=val, **skw)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3
             comm = _bsr_commutator((rp, ci, va), D, m.n)

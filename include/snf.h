@@ -303,8 +303,10 @@ typedef struct {
  * products), SNF_SNF_FIXMU_PIJ and SNF_PIJ (P_{i,j}: the first product writes W and the top
  * Horner level, then the levels, then X.T; (i + j)/2 + 1 products).  A fixed-mu iteration's
  * intermediates keep every candidate block and the truncation applies to its result; these
- * schemes do not take SNF_FLAG_TRUNC_ERROR_CONTROL; screen_tau applies to every product of
- * their iterations.
+ * schemes' error-control budget (SNF_FLAG_TRUNC_ERROR_CONTROL) applies to each iteration's
+ * result, with the gap of the bounds of the iterate it produces (for P_{i,j} 1 - a - a') and
+ * N from the scheme's own recurrence; screen_tau applies to every product of their
+ * iterations.
  *   F:      caller-owned, device arrays; the pattern must be symmetric with every diagonal
  *           block present; only blocks (I,J) with I <= J (and the upper triangle of diagonal
  *           blocks) are read, the rest is taken as their transpose.

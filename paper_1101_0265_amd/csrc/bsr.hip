@@ -1220,17 +1220,71 @@ static int predicted_iterations(snf_scheme scheme, double beta, double betabar, 
   return 200;
 }
 
+// The fixed-mu schemes' scalar recurrence on the host, with the FP64 expressions the device's
+// schedule uses: the alpha an iteration takes from the bounds, and the bounds of the iterate
+// it produces (beta, beta-bar; for P_{i,j} also a' = 1 - beta-bar).
+static double fixmu_alpha(snf_scheme scheme, const SnfState& s) {
+#pragma clang fp contract(off)
+  if (scheme_is_pij(scheme)) {
+    if (scheme != SNF_SNF_FIXMU_PIJ) return 1.0;
+    const double lo = sched::pij_alpha_side_tab(s.pij_i, s.pij_j, s.pbin[0], s.xstar, s.beta);
+    const double hi =
+        sched::pij_alpha_side_tab(s.pij_j, s.pij_i, s.pbin[1], 1.0 - s.xstar, s.abar);
+    return lo < hi ? lo : hi;
+  }
+  if (scheme_pmm_m(scheme))
+    return (scheme == SNF_SNF_FIXMU3 || scheme == SNF_SNF_FIXMU5)
+               ? sched::pmm_alpha_tab(s.pmm_m, s.pbin[0], s.beta)
+               : 1.0;
+  return scheme == SNF_SNF_FIXMU ? sched::alg1_alpha(s.beta) : 1.0;
+}
+
+static void fixmu_advance(SnfState& s, double a) {
+#pragma clang fp contract(off)
+  if (s.pij_i) {
+    const double xs = s.xstar;
+    const double an = sched::pij_side_next_tab(s.pij_i, s.pij_j, s.pbin[0], xs, s.beta, a);
+    const double bn = sched::pij_side_next_tab(s.pij_j, s.pij_i, s.pbin[1], 1.0 - xs, s.abar, a);
+    s.beta = an;
+    s.abar = bn;
+    s.betabar = 1.0 - bn;
+  } else if (s.pmm_m) {
+    s.beta = sched::pij_eval_tab(s.pmm_m, s.pmm_m, s.pbin[0], a * (s.beta - 0.5) + 0.5);
+    s.betabar = 1.0 - s.beta;
+  } else {
+    s.beta = sched::alg1_beta_next(s.beta, a);
+    s.betabar = 1.0 - s.beta;
+  }
+}
+
+// Iterations until the fixed-mu recurrence's bound (max(beta, 1 - beta-bar); for P_{i,j}
+// max(a, a')) is at most eps.
+static int predicted_iterations_fixmu(snf_scheme scheme, SnfState s, double eps) {
+  for (int it = 0; it < 200; ++it) {
+    const double bound = s.pij_i ? (s.beta > s.abar ? s.beta : s.abar)
+                                 : (s.beta > 1.0 - s.betabar ? s.beta : 1.0 - s.betabar);
+    if (bound <= eps) return it > 1 ? it : 1;
+    fixmu_advance(s, fixmu_alpha(scheme, s));
+  }
+  return 200;
+}
+
 // Truncation budget of the pending step: eps g / (sqrt 2 N), g the X-space gap of the iterate
-// the step produces (beta, beta-bar advanced by the step's branch and alpha).
+// the step produces (its bounds advanced by the step's branch and alpha).
 static double error_control_eps(const SnfState* sh, double eps, int n_pred) {
 #pragma clang fp contract(off)
   double b = sh->beta, bb = sh->betabar;
   if (sh->branch == SNF_BRANCH_SQUARE) {
     b = sched::alg2_square_map(b, sh->alpha);
     bb = sched::alg2_square_map(bb, sh->alpha);
-  } else {
+  } else if (sh->branch == SNF_BRANCH_FOLD) {
     b = sched::alg2_fold_map(b, sh->alpha);
     bb = sched::alg2_fold_map(bb, sh->alpha);
+  } else {                                  // the fixed-mu iterations
+    SnfState t = *sh;
+    fixmu_advance(t, sh->alpha);
+    b = t.beta;
+    bb = t.betabar;
   }
   return eps * (bb - b) / (kSqrt2 * (double)n_pred);
 }
@@ -1261,11 +1315,9 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
   if (fixmu) {
     // the fixed-mu parameters as on the dense path (checked as for FP64, where the dense
     // path offers P_{m,m}; the block-sparse products are FP32 either way); the
-    // error-control budget follows Algorithm 2's one-product steps and is not offered here;
-    // norm screening is, for every product of an iteration (each operand's own block norms)
-    if (validate(F ? F->n : 0, params, scheme, SNF_P_FP64) != SNF_OK ||
-        (p.flags & SNF_FLAG_TRUNC_ERROR_CONTROL))
-      return fail(SNF_EINVAL);
+    // error-control budget applies to each iteration's result, the norm screening to every
+    // product of an iteration (each operand's own block norms)
+    if (validate(F ? F->n : 0, params, scheme, SNF_P_FP64) != SNF_OK) return fail(SNF_EINVAL);
   } else if (!isfinite(p.lambda_min) || !isfinite(p.lambda_max) ||
              !(p.lambda_min < p.lambda_max) || !(p.tol > 0.0) || p.max_iter < 1 ||
              p.max_iter >= SNF_LOG_MAX || !isfinite(p.homo) || !isfinite(p.lumo) ||
@@ -1317,7 +1369,9 @@ static int purify_bsr_body(const snf_bsr* F, const snf_params* params, snf_schem
 
   const bool ec = (p.flags & SNF_FLAG_TRUNC_ERROR_CONTROL) != 0;
   const double tau2 = ec ? 0.0 : trunc_tau * trunc_tau;
-  const int n_pred = ec ? predicted_iterations(scheme, sh->beta, sh->betabar, trunc_tau) : 1;
+  const int n_pred = !ec ? 1
+                     : fixmu ? predicted_iterations_fixmu(scheme, *sh, trunc_tau)
+                             : predicted_iterations(scheme, sh->beta, sh->betabar, trunc_tau);
   // the pending product's kind, branch and alpha (which product runs next; the truncation
   // budget of error control)
   BSR_HIP(hipMemcpyAsync(sh, w->state, sizeof(SnfState), hipMemcpyDeviceToHost, s));

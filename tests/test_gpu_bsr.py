@@ -205,11 +205,8 @@ def test_bsr_invalid_inputs(snf):
     rp, ci, va = _dev_bsr(m)
     with pytest.raises(RuntimeError):            # Algorithm 1 needs mu and xi
         snf.purify_bsr(rp, ci, va, n, "snf_fixmu", **kw)
-    with pytest.raises(RuntimeError):            # no error-control budget for Algorithm 1
-        snf.purify_bsr(rp, ci, va, n, "snf_fixmu", mu=h.mu, xi=h.xi,
-                       flags=snf.FLAG_TRUNC_ERROR_CONTROL, **kw)
-    with pytest.raises(RuntimeError):            # nor for P_{m,m}
-        snf.purify_bsr(rp, ci, va, n, "snf_fixmu3", mu=h.mu, xi=h.xi,
+    with pytest.raises(RuntimeError):            # an error-control budget must be positive
+        snf.purify_bsr(rp, ci, va, n, "snf_fixmu", mu=h.mu, xi=h.xi, trunc_tau=0.0,
                        flags=snf.FLAG_TRUNC_ERROR_CONTROL, **kw)
     with pytest.raises(RuntimeError):            # P_{i,j} needs odd i, j
         snf.purify_bsr(rp, ci, va, n, "snf_pij", mu=h.mu, xi=h.xi, poly_ij=(2, 3), **kw)
@@ -249,13 +246,16 @@ def test_bsr_full_lattice_65536(snf):
           f"device {r['device_ms']:.0f} ms")
 
 
-@pytest.mark.parametrize("scheme", ["tc2", "snf_varmu", "sp2"])
+@pytest.mark.parametrize("scheme,pij", [("tc2", None), ("snf_varmu", None), ("sp2", None),
+                                        ("snf_fixmu", None), ("snf_fixmu3", None),
+                                        ("snf_pij", (1, 3))])
 @pytest.mark.parametrize("eps", [1e-2, 1e-3])
-def test_error_controlled_truncation(snf, scheme, eps):
+def test_error_controlled_truncation(snf, scheme, pij, eps):
     """Error-controlled truncation (budget eps for ||D - D_exact||_F) on the 16x8x8-site
     lattice (n = 2048).  Bars: decisions equal the oracle's; ||D_gpu - D_exact||_F within eps
     plus the FP32 floor of the same solve without truncation; stored blocks of D within 5% of
-    the oracle's (FP32 block norms near a bin edge may fall on the other side)."""
+    the oracle's (FP32 block norms near a bin edge may fall on the other side).  The fixed-mu
+    schemes truncate each iteration's result, with the gap of its bounds."""
     m, h = H.lattice_bsr((16, 8, 8), seed=3)
     n = m.n
     m64, _ = H.lattice_bsr((16, 8, 8), seed=3, dtype=np.float64)
@@ -263,6 +263,10 @@ def test_error_controlled_truncation(snf, scheme, eps):
     D_ref = exact.projector(F=Fd, n_occ=h.n_occ)
     kw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, n_occ=h.n_occ, homo=h.homo,
               lumo=h.lumo, tol=1e-9, max_iter=60)
+    pkw = dict(lambda_min=h.lambda_min, lambda_max=h.lambda_max, homo=h.homo, lumo=h.lumo)
+    if scheme not in ("tc2", "snf_varmu", "sp2"):
+        kw.update(mu=h.mu, xi=h.xi, poly_ij=pij)
+        pkw.update(mu=h.mu, xi=h.xi, poly_ij=pij)
     (rp, ci, va), r = snf.purify_bsr(*_dev_bsr(m), n, scheme, trunc_tau=eps,
                                       flags=snf.FLAG_TRUNC_ERROR_CONTROL, **kw)
     assert r["status"] in ("ok", "ok_floor"), r["status"]
@@ -270,8 +274,7 @@ def test_error_controlled_truncation(snf, scheme, eps):
     floor = float(np.linalg.norm(_to_dense(rp0, ci0, va0, n) - D_ref))
     Dg = _to_dense(rp, ci, va, n)
     err = float(np.linalg.norm(Dg - D_ref))
-    N = dense.predicted_iterations(scheme, eps=eps, lambda_min=h.lambda_min,
-                                   lambda_max=h.lambda_max, homo=h.homo, lumo=h.lumo)
+    N = dense.predicted_iterations(scheme, eps=eps, **pkw)
     mk = dense.ErrorControlledTruncation(32, eps, N)
     okw = dict(kw)
     okw.update(tol=0.0, max_iter=r["iterations"])
