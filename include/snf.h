@@ -23,7 +23,8 @@
  *   SNF_PMM5        SNF_SNF_FIXMU5 with alpha = 1.
  *   The P_{m,m} schemes evaluate P_{m,m}(1/2 + v) = 1/2 + v r(v^2) (the polynomial is
  *   point-symmetric about (1/2, 1/2); r has degree m): v^2, r by Horner's rule, then v r.
- *   They take the inputs of Algorithm 1 and run in SNF_P_FP64 only.
+ *   They take the inputs of Algorithm 1; the dense entry points run them in SNF_P_FP64
+ *   only (the block-sparse path computes every scheme in FP32).
  *   SNF_SNF_FIXMU_PIJ  fixed-mu scale-and-fold with P_{i,j}, i and j odd (poly_i, poly_j in
  *                   snf_params, each 1, 3 or 5), scaled about the polynomial's unstable
  *                   fixed point x* (the remark closing the P_{m,m} paragraph before
@@ -37,7 +38,8 @@
  *                   smaller root: the largest scaling that speeds up both sides.  For
  *                   i = j this is SNF_SNF_FIXMU / SNF_SNF_FIXMU3 / SNF_SNF_FIXMU5.
  *                   Evaluation: P(x* + v) = x* + v Q(v), Q by Horner's rule in v^2 with
- *                   coefficients linear in v.  Inputs of Algorithm 1; SNF_P_FP64 only;
+ *                   coefficients linear in v.  Inputs of Algorithm 1; SNF_P_FP64 only on
+ *                   the dense entry points;
  *                   SNF_EINVAL for poly_i / poly_j outside {1, 3, 5} or a gap edge that
  *                   falls outside [0, 1] (xi / (2 gamma) >= min(x*, 1 - x*)).
  *   SNF_PIJ         SNF_SNF_FIXMU_PIJ with alpha = 1 (unscaled grand-canonical P_{i,j}).
