@@ -374,15 +374,17 @@ typedef struct snf_server snf_server;
    max_slots: at most this many requests in flight (1..4096).  *out receives the server. */
 int snf_serve_create(size_t hbm_budget_bytes, int32_t max_slots, snf_server** out);
 
-/* Device bytes one request of order n and this precision occupies in the arena. */
+/* Device bytes one request of order n and this precision occupies in the arena (the schemes
+   with one or two products per iteration; a P_{m,m} or P_{i,j} request, FP64 only, holds one
+   more n_pad x n_pad FP64 buffer, n_pad = n rounded up to a multiple of 128). */
 size_t snf_serve_request_bytes(int64_t n, snf_precision precision);
 
 /* Queue a purification of the host n x n FP64 matrix F_host (row-major, copied before the
  * call returns, so the caller may reuse it).  D_host_out (n x n FP64, row-major) receives D
  * and must stay valid until snf_serve_poll reports completion.  Never waits for the GPU.
  * Returns SNF_OK and a ticket; SNF_EINVAL for bad arguments (checked as for
- * snf_purify_dense; the P_{m,m} schemes are not served); SNF_ENOMEM if the request alone
- * exceeds the budget. */
+ * snf_purify_dense, so the P_{m,m} and P_{i,j} schemes are served in SNF_P_FP64 only);
+ * SNF_ENOMEM if the request alone exceeds the budget. */
 int snf_serve_submit(snf_server* server, const double* F_host, int64_t n,
                      const snf_params* params, snf_scheme scheme, snf_precision precision,
                      double* D_host_out, uint64_t* ticket);

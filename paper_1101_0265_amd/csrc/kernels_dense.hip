@@ -1635,21 +1635,24 @@ __device__ __forceinline__ ProductGrid slot_grid(const SlotDesc& sd) {
   return g;
 }
 
-template <typename T, int PREC>
+// DUAL: the FP64 variant whose epilogue also writes the second output (the first product of
+// a P_{i,j} iteration); each request's state selects exactly one of the two FP64 variants.
+template <typename T, int PREC, bool DUAL = false>
 __global__ __launch_bounds__(Layout<T>::NT, 2) void grouped_product_kernel(const SlotDesc* __restrict__ slots,
                                                                  const int* __restrict__ active,
                                                                  const int* __restrict__ offs,
                                                                  int nactive) {
   const int a = group_find(offs, nactive, blockIdx.x);
   const SlotDesc sd = slots[active[a]];
-  if (sd.st->stop || sd.st->prec != PREC) return;
+  if (sd.st->stop || sd.st->prec != PREC || (PREC == kPrecF64 && (sd.st->dual != 0) != DUAL))
+    return;
   const ProductGrid g = slot_grid(sd);
   WorkItem wi;
   wi.tile = blockIdx.x - offs[a];
   wi.piece = -1;
   wi.kt_begin = 0;
   wi.kt_end = (int)(sd.np / Mfma<T>::kBK);
-  product_body<T, PREC>(sd.st, sd.bufs, g, wi);
+  product_body<T, PREC, DUAL>(sd.st, sd.bufs, g, wi);
 }
 
 __global__ __launch_bounds__(256, 2) void grouped_product_bf16_kernel(const SlotDesc* __restrict__ slots,
@@ -1678,7 +1681,11 @@ __global__ __launch_bounds__(kReduceThreads) void grouped_schedule_kernel(const 
 __global__ void grouped_stop_kernel(const SlotDesc* __restrict__ slots, const int* __restrict__ active,
                                     int nactive, int32_t* __restrict__ stop_out) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a < nactive) stop_out[a] = slots[active[a]].st->stop;
+  // 0 while running; once stopped, 1 + the index of the buffer holding the result
+  if (a < nactive) {
+    const SnfState* st = slots[active[a]].st;
+    stop_out[a] = st->stop ? 1 + st->cur : 0;
+  }
 }
 
 void launch_grouped_step(int prec_mask, const SlotDesc* slots, const int* active,
@@ -1700,6 +1707,9 @@ void launch_grouped_step(int prec_mask, const SlotDesc* slots, const int* active
                        slots, active, offs, nactive);
   if (prec_mask & (1 << kPrecF64))
     hipLaunchKernelGGL((grouped_product_kernel<double, kPrecF64>), dim3(total_tiles),
+                       dim3(Layout<double>::NT), 0, s, slots, active, offs, nactive);
+  if (prec_mask & kGroupedDualBit)
+    hipLaunchKernelGGL((grouped_product_kernel<double, kPrecF64, true>), dim3(total_tiles),
                        dim3(Layout<double>::NT), 0, s, slots, active, offs, nactive);
   if (split && (hipEventRecord(join, s2) != hipSuccess ||
                 hipStreamWaitEvent(s, join, 0) != hipSuccess))

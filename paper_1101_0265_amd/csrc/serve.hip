@@ -59,27 +59,38 @@ struct ServeRequest {
   hipEvent_t ev = nullptr;
   bool started = false;     // admission work enqueued: takes part in the next grouped step
   bool finished = false;    // its stop flag came back: retired behind the next step
+  int result_buf = 0;       // the iterate buffer holding D (from the stop flag)
   int status = SNF_PENDING;
   snf_result result;
 };
 
 struct RequestLayout {   // byte offsets of one request's workspace inside its arena block
-  size_t x[3], lp[3], partials, total;
+  size_t x[4], lp[4], partials, total;
+  int nbuf;              // iterate-sized buffers: 3, or 4 for the P_{m,m} and P_{i,j} schemes
 };
 
-static RequestLayout request_layout(int64_t n, snf_precision prec) {
+// buffers a request of this scheme needs: X (two, ping-pong) and an intermediate (Algorithm
+// 1's S2, and F at admission); the P_{m,m} and P_{i,j} iterations keep W and two Horner
+// levels beside X
+static int request_buffers(snf_scheme scheme) {
+  return (scheme_pmm_m(scheme) || scheme_is_pij(scheme)) ? 4 : 3;
+}
+
+static RequestLayout request_layout(int64_t n, snf_precision prec, int nbuf = 3) {
   RequestLayout L;
+  L.nbuf = nbuf;
   const int64_t np = (n + kTile - 1) / kTile * kTile;
   const size_t mat = (size_t)np * np * sizeof(double);
   const size_t lpb = (size_t)np * np * lowp_bytes_for(prec);
   const int tiles = num_product_tiles(np, 1);
   const size_t slots = (size_t)(tiles > kF0Blocks ? tiles : kF0Blocks);
   size_t o = 0;
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 4; ++i) L.x[i] = L.lp[i] = 0;
+  for (int i = 0; i < nbuf; ++i) {
     L.x[i] = o;
     o += (mat + 255) & ~(size_t)255;
   }
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < nbuf; ++i) {
     L.lp[i] = o;
     o += (lpb + 255) & ~(size_t)255;
   }
@@ -201,15 +212,14 @@ static hipEvent_t take_event_locked(snf_server* sv) {
 // the initial schedule -- all stream-ordered, no host waits.
 static int start_request(snf_server* sv, ServeRequest* r, hipStream_t s) {
   const int k = r->slot;
-  const RequestLayout L = request_layout(r->n, r->prec);
+  const RequestLayout L = request_layout(r->n, r->prec, request_buffers(r->scheme));
   char* base = sv->arena_base + r->off;
   Buffers& b = sv->bufs_stage[k];
-  for (int i = 0; i < 3; ++i) {
-    b.x[i] = (double*)(base + L.x[i]);
-    b.lp[i] = lowp_bytes_for(r->prec) ? (void*)(base + L.lp[i]) : nullptr;
+  for (int i = 0; i < 4; ++i) {
+    const bool have = i < L.nbuf;
+    b.x[i] = have ? (double*)(base + L.x[i]) : nullptr;
+    b.lp[i] = have && lowp_bytes_for(r->prec) ? (void*)(base + L.lp[i]) : nullptr;
   }
-  b.x[3] = nullptr;      // the fourth buffer serves only the P_{m,m} schemes, not served
-  b.lp[3] = nullptr;
   SlotDesc& d = sv->desc_stage[k];
   d.st = sv->states + k;
   d.bufs = sv->bufs + k;
@@ -242,8 +252,11 @@ static int retire_request(snf_server* sv, ServeRequest* r, hipStream_t s) {
   if (r->device_io) {
     launch_copy_out(sv->states + k, sv->bufs + k, r->n, r->np, r->D_dev, r->n, s);
   } else {
-    launch_copy_out(sv->states + k, sv->bufs + k, r->n, r->np, b.x[2], r->n, s);
-    SV_HIP(hipMemcpyAsync(r->D_pin, b.x[2], (size_t)r->n * r->n * sizeof(double),
+    // D leaves through an iterate buffer other than the one holding it (x[2] unless D is
+    // there: a P_{m,m} or P_{i,j} iteration rotates its result over all four)
+    double* stage = b.x[r->result_buf == 2 ? 0 : 2];
+    launch_copy_out(sv->states + k, sv->bufs + k, r->n, r->np, stage, r->n, s);
+    SV_HIP(hipMemcpyAsync(r->D_pin, stage, (size_t)r->n * r->n * sizeof(double),
                           hipMemcpyDeviceToHost, s));
   }
   SV_HIP(hipMemcpyAsync(r->st_pin, sv->states + k, sizeof(SnfState), hipMemcpyDeviceToHost, s));
@@ -311,6 +324,7 @@ static void scheduler(snf_server* sv) {
         active.push_back(i);
         if (r->prec == SNF_P_FP32 || r->prec == SNF_P_FP32_REF64) prec_mask |= 1 << kPrecF32;
         if (r->prec == SNF_P_BF16_REF64) prec_mask |= 1 << kPrecBF16;
+        if (scheme_is_pij(r->scheme)) prec_mask |= kGroupedDualBit;
       }
     }
     // largest orders first: their tiles run the longest k-loops, so dispatching them first
@@ -429,6 +443,7 @@ static void scheduler(snf_server* sv) {
           if (!sv->stop_stage[a]) continue;
           ServeRequest* r = sv->slot_req[active[a]];
           r->finished = true;
+          r->result_buf = sv->stop_stage[a] - 1;
           r->t_finish = Clock::now();
           finished.push_back(r);
         }
@@ -473,7 +488,7 @@ static ServeRequest* new_request(snf_server* sv, int64_t n, const snf_params* pa
   r->params = *params;
   r->scheme = scheme;
   r->prec = precision;
-  r->bytes = request_layout(n, precision).total;
+  r->bytes = request_layout(n, precision, request_buffers(scheme)).total;
   memset(&r->result, 0, sizeof(r->result));
   r->result.status = SNF_PENDING;
   r->t_submit = Clock::now();
@@ -548,8 +563,6 @@ int snf_serve_submit(snf_server* sv, const double* F_host, int64_t n, const snf_
                      uint64_t* ticket) {
   if (!sv || !F_host || !D_host_out || !ticket) return SNF_EINVAL;
   int rc = validate(n, params, scheme, precision);
-  if (rc == SNF_OK && (scheme_pmm_m(scheme) || scheme_is_pij(scheme)))
-    rc = SNF_EINVAL;   // three buffers per request
   if (rc != SNF_OK) return rc;
   ServeRequest* r = new_request(sv, n, params, scheme, precision);
   r->D_host = D_host_out;
@@ -574,8 +587,6 @@ int snf_serve_submit_device(snf_server* sv, const double* F_dev, int64_t n,
   if (!sv || !F_dev || !D_dev_out || !ticket || (const void*)F_dev == (const void*)D_dev_out)
     return SNF_EINVAL;
   int rc = validate(n, params, scheme, precision);
-  if (rc == SNF_OK && (scheme_pmm_m(scheme) || scheme_is_pij(scheme)))
-    rc = SNF_EINVAL;   // three buffers per request
   if (rc != SNF_OK) return rc;
   ServeRequest* r = new_request(sv, n, params, scheme, precision);
   r->device_io = true;

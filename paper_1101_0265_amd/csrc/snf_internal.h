@@ -215,10 +215,13 @@ struct SlotDesc {
   int64_t np, n;
 };
 
-// One step of every active request: product variants selected by prec_mask (bit kPrec*),
-// each request's schedule, and the stop flags gathered into stop_out[nactive].  With s2 and
+// One step of every active request: product variants selected by prec_mask (bit kPrec*, and
+// kGroupedDualBit for the FP64 variant with a second output that P_{i,j} requests take),
+// each request's schedule, and the stop flags gathered into stop_out[nactive] (0 while a
+// request runs; 1 + the buffer index of its result once it stopped).  With s2 and
 // the two events, the FP32 / BF16 product launches run on s2 beside the FP64 one on s.
 // offs[a] = first workgroup of active request a (offs[nactive] = total_tiles).
+constexpr int kGroupedDualBit = 1 << 8;
 void launch_grouped_step(int prec_mask, const SlotDesc* slots, const int* active,
                          const int* offs, int nactive, int total_tiles, int32_t* stop_out,
                          hipStream_t s, hipStream_t s2 = nullptr, hipEvent_t fork = nullptr,

@@ -74,6 +74,40 @@ def test_alone_equals_mix_bitwise(snf, scheme, prec):
         assert err <= 1e-8 * math.sqrt(target.n)
 
 
+@pytest.mark.parametrize("scheme,pij", [("snf_fixmu3", None), ("pmm5", None),
+                                        ("snf_pij", (1, 3)), ("pij", (3, 1))])
+def test_higher_order_schemes_served(snf, scheme, pij):
+    """P_{m,m} and P_{i,j} requests (FP64; a fourth iterate buffer per request, and for
+    P_{i,j} the grouped product with a second output) alone and in a mix with requests of
+    other schemes, sizes and precisions: bitwise the same, with the oracle's decisions,
+    product count and D."""
+    target = _req(300, 140, seed=43)
+    kwt = dict(_kw(target), poly_ij=pij)
+    others = [(_req(n, n // 2 + 3, seed=n + 1), s, p, pp) for n, s, p, pp in
+              [(200, "snf_pij", "fp64", (3, 1)), (640, "snf_varmu", "fp32_ref64", None),
+               (130, "snf_fixmu5", "fp64", None), (257, "sp2", "fp64", None),
+               (96, "snf_fixmu", "fp64", None)]]
+    with snf.Server(4 * GB, max_slots=16) as sv:
+        t = sv.submit(target.F, scheme, "fp64", **kwt)
+        D_alone, r_alone = sv.wait(t)
+        D_alone = D_alone.copy()
+    with snf.Server(4 * GB, max_slots=16) as sv:
+        tickets = [sv.submit(h.F, s, p, **dict(_kw(h), poly_ij=pp)) for h, s, p, pp in others[:2]]
+        t = sv.submit(target.F, scheme, "fp64", **kwt)
+        tickets += [sv.submit(h.F, s, p, **dict(_kw(h), poly_ij=pp)) for h, s, p, pp in others[2:]]
+        D_mix, r_mix = sv.wait(t)
+        others_res = [sv.wait(x) for x in tickets]
+    assert r_alone["status"] == r_mix["status"] == "ok"
+    assert np.array_equal(D_alone, D_mix)
+    for (h, s, p, pp), (D, r) in zip(others, others_res):
+        assert r["status"] == "ok", (h.n, s, p, r["status"])
+    o = dense.purify(target.F, scheme, **kwt)
+    err = np.linalg.norm(D_mix - o["D"])
+    print(f"\nserved {scheme} {pij}: products {r_mix['products']} |D-D_oracle|_F = {err:.2e}")
+    assert r_mix["branches"] == o["branches"] and r_mix["products"] == o["products"]
+    assert err <= 1e-8 * math.sqrt(target.n)
+
+
 def test_results_match_oracle_fp64(snf):
     hs = [_req(n, n // 2 - 5, seed=100 + n, gap=0.08) for n in (64, 200, 385, 640)]
     with snf.Server(2 * GB, max_slots=8) as sv:
