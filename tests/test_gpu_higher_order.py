@@ -104,15 +104,16 @@ def test_workspace_growth_between_schemes(snf):
         assert np.linalg.norm(D.cpu().numpy() - D_ref) <= 1e-8 * math.sqrt(h.n)
 
 
-def test_higher_order_rejects_low_precision_and_other_paths(snf):
+def test_higher_order_rejects_low_precision(snf):
     h = H.small_gap_256()
     F = torch.tensor(h.F, device="cuda:0")
     with pytest.raises(RuntimeError):
         snf.purify_dense(F, "snf_fixmu3", "fp32_ref64", **_kw(h))
-    # (the block-sparse path runs them: tests/test_gpu_bsr.py)
+    # (the block-sparse path runs them in FP32: tests/test_gpu_bsr.py; serving in FP64:
+    # tests/test_gpu_serve.py)
     srv = snf.Server(64 << 20, max_slots=4)
     try:
         with pytest.raises(RuntimeError):
-            srv.submit(h.F, "pmm3", **_kw(h))
+            srv.submit(h.F, "pmm3", "fp32_ref64", **_kw(h))
     finally:
         srv.close()

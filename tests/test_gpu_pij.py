@@ -151,7 +151,9 @@ def test_rejects_bad_polynomials_modes_and_paths(snf):
         snf.purify_dense(F, "snf_pij", **kw)
     srv = snf.Server(64 << 20, max_slots=4)
     try:
-        with pytest.raises(RuntimeError):
-            srv.submit(h.F, "snf_pij", **_kw(h, (3, 1)))
+        with pytest.raises(RuntimeError):            # served in FP64 only
+            srv.submit(h.F, "snf_pij", "fp32_ref64", **_kw(h, (3, 1)))
+        with pytest.raises(RuntimeError):            # checked as for the dense path
+            srv.submit(h.F, "snf_pij", **_kw(h, (2, 1)))
     finally:
         srv.close()
