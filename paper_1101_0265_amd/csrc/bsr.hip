@@ -1036,8 +1036,16 @@ static int bsr_step(BsrWorkspace* w, BsrBuf& X, BsrBuf& B, BsrBuf& L, BsrBuf& N,
   BSR_HIP(hipStreamSynchronize(s));
   int32_t* tl = (int32_t*)(hf + ((nflags + 63) / 64) * 64);
   int ntiles = 0;
-  for (int64_t t = 0; t < nflags; ++t)
-    if (hf[t]) tl[ntiles++] = (int32_t)(((t / NT) << 16) | (t % NT));
+  // super-tiles in squares of SQ x SQ (squares in row-major order of the upper triangle,
+  // tiles row-major inside): the ~512 workgroups resident at once cover 8 bands of A rows and
+  // 64 of B rows instead of one band and 512, and an XCD (workgroups go to the 8 XCDs in
+  // turn) takes one column of each square, whose 8 tiles stream the same B rows
+  constexpr int SQ = 8;
+  for (int sa = 0; sa < NT; sa += SQ)
+    for (int sb = sa; sb < NT; sb += SQ)
+      for (int ti = sa; ti < sa + SQ && ti < NT; ++ti)
+        for (int tj = sb; tj < sb + SQ && tj < NT; ++tj)
+          if (hf[(int64_t)ti * NT + tj]) tl[ntiles++] = (int32_t)((ti << 16) | tj);
   if ((rc = w->tiles.reserve(ntiles + 1)) || (rc = w->partials.reserve((size_t)(ntiles + nb) * 4)))
     return rc;
   // pinned source: the copy runs in stream order, before any later read-back reuses it
