@@ -796,8 +796,8 @@ __device__ __forceinline__ void product_bf16_body(const SnfState* __restrict__ s
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[m][q] = flt4{0.f, 0.f, 0.f, 0.f};
 
-  u32x4 ra[PASSES], rb[PASSES];
-  auto gload = [&](int64_t k0) {
+  u32x4 ra0[PASSES], rb0[PASSES], ra1[PASSES], rb1[PASSES];
+  auto gload = [&](u32x4 (&ra)[PASSES], u32x4 (&rb)[PASSES], int64_t k0) {
 #pragma unroll
     for (int p = 0; p < PASSES; ++p) {
       const int64_t r = p * RPP + lrow;
@@ -805,7 +805,7 @@ __device__ __forceinline__ void product_bf16_body(const SnfState* __restrict__ s
       rb[p] = gload16(B + (j0 + r) * np + k0 + lvec * 8);
     }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](const u32x4 (&ra)[PASSES], const u32x4 (&rb)[PASSES], int buf) {
 #pragma unroll
     for (int p = 0; p < PASSES; ++p) {
       const int rr = p * RPP + lrow, pc = (lvec ^ ((rr >> 1) & 7)) * 8;
@@ -813,15 +813,8 @@ __device__ __forceinline__ void product_bf16_body(const SnfState* __restrict__ s
       *(u32x4*)(&sB[buf][rr][pc]) = rb[p];
     }
   };
-
-  gload((int64_t)wi.kt_begin * BK);
-  lstore(0);
-  __syncthreads();
   const int fr = lane & 15, fk = (lane >> 4) * 8;
-  for (int kt = wi.kt_begin; kt < wi.kt_end; ++kt) {
-    const int buf = (kt - wi.kt_begin) & 1;
-    const bool more = kt + 1 < wi.kt_end;
-    if (more) gload((int64_t)(kt + 1) * BK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 32) {
       bf16x8 a[4], b[4];
@@ -841,8 +834,36 @@ __device__ __forceinline__ void product_bf16_body(const SnfState* __restrict__ s
         for (int q = 0; q < 4; ++q)
           acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[q], acc[m][q], 0, 0, 0);
     }
-    if (more) lstore(buf ^ 1);
-    __syncthreads();
+  };
+
+  // Operands two stages ahead in two register sets: stage kt computes from LDS buffer
+  // (kt - kb) & 1, stores stage kt + 1 (loaded during the previous stage) into the other
+  // buffer and loads stage kt + 2.  The loads are issued on every path (past the end the
+  // last stage again, never stored): with a conditional load the compiler's wait before the
+  // LDS stores would also cover the newer set and the second stage of lead would be lost.
+  const int kb = wi.kt_begin, ke = wi.kt_end;
+  gload(ra0, rb0, (int64_t)kb * BK);
+  lstore(ra0, rb0, 0);
+  gload(ra1, rb1, (int64_t)min(kb + 1, ke - 1) * BK);
+  __syncthreads();
+  int kt = kb;
+  while (true) {
+    {
+      const int buf = (kt - kb) & 1;
+      gload(ra0, rb0, (int64_t)min(kt + 2, ke - 1) * BK);
+      compute(buf);
+      if (kt + 1 < ke) lstore(ra1, rb1, buf ^ 1);
+      __syncthreads();
+      if (++kt >= ke) break;
+    }
+    {
+      const int buf = (kt - kb) & 1;
+      gload(ra1, rb1, (int64_t)min(kt + 2, ke - 1) * BK);
+      compute(buf);
+      if (kt + 1 < ke) lstore(ra0, rb0, buf ^ 1);
+      __syncthreads();
+      if (++kt >= ke) break;
+    }
   }
 
   if (wi.piece >= 0) {
