@@ -698,12 +698,17 @@ __device__ __forceinline__ void small_tile_product(const SnfState* __restrict__ 
         for (int q = 0; q < 2; ++q)
           acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m][s], b[q][s], acc[m][q], 0, 0, 0);
   };
-  // the wave's range is a multiple of 32 (np is a multiple of 128)
+  // the wave's range is a multiple of 32 (np is a multiple of 128).  The next chunk is
+  // loaded on every path (past the end the last chunk again, never used) and ahead of this
+  // chunk's MFMAs (scheduling barrier): with a conditional load the compiler's wait before
+  // the MFMAs would also cover the next chunk's loads, and they would not overlap.
   gload(kw0, ra0, rb0);
   for (int64_t kc = kw0; kc < kw1; kc += 64) {
-    if (kc + 32 < kw1) gload(kc + 32, ra1, rb1);
+    gload(min(kc + 32, kw1 - 32), ra1, rb1);
+    __builtin_amdgcn_sched_barrier(0);
     compute(ra0, rb0);
-    if (kc + 64 < kw1) gload(kc + 64, ra0, rb0);
+    gload(min(kc + 64, kw1 - 32), ra0, rb0);
+    __builtin_amdgcn_sched_barrier(0);
     if (kc + 32 < kw1) compute(ra1, rb1);
   }
   // accumulator of lane l, register v: row (l / 16) + 4 v, column l % 16 of block (m, q)
