@@ -48,10 +48,6 @@ constexpr int kB = 32;            // block size
 constexpr int kBB = kB * kB;      // values per block
 constexpr int kSup = 4;           // blocks per super-tile side (128 = 4 x 32)
 
-__device__ __forceinline__ u32x4 bsr_gload16(const float* p) {
-  return *(const __attribute__((address_space(1))) u32x4*)(p);
-}
-
 __device__ __forceinline__ double bsr_wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -217,7 +213,10 @@ __global__ __launch_bounds__(256) void bsr_block_norms_kernel(const float* __res
 constexpr int kBsrLdsK = kB + 4;    // LDS row stride (floats) of a panel row: 32 values of k
                                     // and 4 of padding (16-byte reads of 16 rows hit
                                     // distinct banks)
-constexpr int kChunkWords = 8;      // bitmap words per k-stage list chunk (256 columns)
+constexpr int kChunkWords = 8;
+// word 3 of a raw buffer resource on this GPU family (no format conversion; loads at or past
+// the buffer's size return zero)
+constexpr int kBufferFlags = 0x00020000;      // bitmap words per k-stage list chunk (256 columns)
 static_assert(kChunkWords * 32 <= 256, "a chunk's stages must fit waves 0-3 (compaction)");
 
 // LDS of the numeric kernel, in one struct so that the small per-chunk tables sit at low
@@ -279,23 +278,30 @@ __global__ __launch_bounds__(512, 4) void bsr_product_kernel(const SnfState* __r
   u32x4 rA[4], rB[4];
   uint32_t pA = 0, pB = 0;   // block pairs of the stage (kmask)
   int rowbase = 0;           // value index of the first block of this wave's row in the chunk
-  auto gload = [&](int s, u32x4 (&rv)[4], uint32_t& pres) {
-    // the block is loaded when some pair of the stage uses it, else it stays zero (the
-    // stage tables are the same for every lane: read as wave-uniform values)
-    const uint32_t m = __builtin_amdgcn_readfirstlane(sm.kmask[s]);
+  auto gload = [&](int s, int nk, u32x4 (&rv)[4], uint32_t& pres) {
+    // The block is loaded when some pair of the stage uses it.  The four loads are buffer
+    // loads issued on every path: for a block no pair uses, or a stage past the end, the
+    // buffer's size is 0 and they return zeros without touching memory.  So the number of
+    // loads in flight is the same on every path, and the wait before a stage's LDS stores
+    // leaves the next stage's loads in flight.  (The stage tables are the same for every
+    // lane: read as wave-uniform values.)
+    const int si = min(s, nk - 1);
+    const uint32_t m = s < nk ? __builtin_amdgcn_readfirstlane(sm.kmask[si]) : 0u;
     pres = m;
     const uint32_t need = side ? ((m | (m >> 4) | (m >> 8) | (m >> 12)) >> ab) & 1u
                                : (((m >> (4 * ab)) & 0xFu) != 0u ? 1u : 0u);
-    if (need) {
-      const int pos =
-          rowbase + (int)((__builtin_amdgcn_readfirstlane(sm.krel[side][s]) >> (8 * ab)) & 0xFFu);
-      const float* src = valS + (size_t)pos * kBB + 4 * lane;
+    const int pos =
+        rowbase + (int)((__builtin_amdgcn_readfirstlane(sm.krel[side][si]) >> (8 * ab)) & 0xFFu);
+    const uint64_t addr = (uint64_t)(need ? valS + (size_t)pos * kBB : valS);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)addr);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(addr >> 32));
+    const int bytes = __builtin_amdgcn_readfirstlane(need ? kBB * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(((uint64_t)hi << 32) | lo), 0, bytes, kBufferFlags);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) rv[q] = bsr_gload16(src + 256 * q);
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) rv[q] = u32x4{0, 0, 0, 0};
-    }
+    for (int q = 0; q < 4; ++q)
+      rv[q] = __builtin_bit_cast(
+          u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * lane + 1024 * q, 0, 0));
   };
   auto lstore = [&](int buf, const u32x4 (&rv)[4], uint32_t pres) {
     float(*dst)[kBsrLdsK] = side ? sm.sB[buf] : sm.sA[buf];
@@ -465,17 +471,17 @@ __global__ __launch_bounds__(512, 4) void bsr_product_kernel(const SnfState* __r
     if (nk == 0) continue;
     // two stages in flight in registers: stage s in LDS buffer s & 1, s + 1 loaded into
     // registers, s + 2 being loaded
-    gload(0, rA, pA);
-    if (nk > 1) gload(1, rB, pB);
+    gload(0, nk, rA, pA);
+    gload(1, nk, rB, pB);
     lstore(0, rA, pA);
     __syncthreads();
     for (int s = 0; s < nk; s += 2) {
-      if (s + 2 < nk) gload(s + 2, rA, pA);
+      gload(s + 2, nk, rA, pA);
       compute(0);
       if (s + 1 < nk) lstore(1, rB, pB);
       __syncthreads();
       if (s + 1 >= nk) break;
-      if (s + 3 < nk) gload(s + 3, rB, pB);
+      gload(s + 3, nk, rB, pB);
       compute(1);
       if (s + 2 < nk) lstore(0, rA, pA);
       __syncthreads();
