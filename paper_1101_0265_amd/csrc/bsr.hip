@@ -214,8 +214,9 @@ constexpr int kBsrLdsK = kB + 4;    // LDS row stride (floats) of a panel row: 3
                                     // and 4 of padding (16-byte reads of 16 rows hit
                                     // distinct banks)
 constexpr int kChunkWords = 8;
-// word 3 of a raw buffer resource on this GPU family (no format conversion; loads at or past
-// the buffer's size return zero)
+// Word 3 of a buffer resource on the gfx9 family (32-bit data format; the value AMD's
+// composable_kernel library uses for these parts).  The untyped loads below ignore the
+// format; a load at or past the resource's size returns zero.
 constexpr int kBufferFlags = 0x00020000;      // bitmap words per k-stage list chunk (256 columns)
 static_assert(kChunkWords * 32 <= 256, "a chunk's stages must fit waves 0-3 (compaction)");
 
