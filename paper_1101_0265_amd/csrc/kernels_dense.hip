@@ -574,8 +574,8 @@ __device__ __forceinline__ void product_body(const SnfState* __restrict__ st,
 #pragma unroll
     for (int q = 0; q < QT; ++q) acc[m][q] = typename M::acc_t{0, 0, 0, 0};
 
-  u32x4 ra[PASSES], rb[PASSES];
-  auto gload = [&](int64_t k0) {
+  u32x4 ra0[PASSES], rb0[PASSES], ra1[PASSES], rb1[PASSES];
+  auto gload = [&](u32x4 (&ra)[PASSES], u32x4 (&rb)[PASSES], int64_t k0) {
 #pragma unroll
     for (int p = 0; p < PASSES; ++p) {
       const int64_t k = k0 + p * RPP + lrow;
@@ -583,22 +583,15 @@ __device__ __forceinline__ void product_body(const SnfState* __restrict__ st,
       rb[p] = gload16(B + k * np + j0 + lvec * VE);
     }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](const u32x4 (&ra)[PASSES], const u32x4 (&rb)[PASSES], int buf) {
 #pragma unroll
     for (int p = 0; p < PASSES; ++p) {
       *(u32x4*)(&sA[buf][p * RPP + lrow][lvec * VE]) = ra[p];
       *(u32x4*)(&sB[buf][p * RPP + lrow][lvec * VE]) = rb[p];
     }
   };
-
-  gload((int64_t)wi.kt_begin * BK);
-  lstore(0);
-  __syncthreads();
   const int fr = lane & 15, fk = lane >> 4;
-  for (int kt = wi.kt_begin; kt < wi.kt_end; ++kt) {
-    const int buf = (kt - wi.kt_begin) & 1;
-    const bool more = kt + 1 < wi.kt_end;
-    if (more) gload((int64_t)(kt + 1) * BK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T a[MT], b[QT];
@@ -611,8 +604,46 @@ __device__ __forceinline__ void product_body(const SnfState* __restrict__ st,
 #pragma unroll
         for (int q = 0; q < QT; ++q) acc[m][q] = M::mma(a[m], b[q], acc[m][q]);
     }
-    if (more) lstore(buf ^ 1);
+  };
+  // FP32: operands two stages ahead in two register sets, the loads issued on every path
+  // (past the end the last stage again, never stored) so that the wait before the LDS stores
+  // leaves the newer set in flight.  FP64: one stage ahead (a stage's 32 MFMAs per wave take
+  // long enough to cover the loads, and the FP64 kernel has no registers to spare).
+  const int kb = wi.kt_begin, ke = wi.kt_end;
+  gload(ra0, rb0, (int64_t)kb * BK);
+  lstore(ra0, rb0, 0);
+  if constexpr (PREC == kPrecF32) {
+    gload(ra1, rb1, (int64_t)min(kb + 1, ke - 1) * BK);
     __syncthreads();
+    int kt = kb;
+    while (true) {
+      {
+        const int buf = (kt - kb) & 1;
+        gload(ra0, rb0, (int64_t)min(kt + 2, ke - 1) * BK);
+        compute(buf);
+        if (kt + 1 < ke) lstore(ra1, rb1, buf ^ 1);
+        __syncthreads();
+        if (++kt >= ke) break;
+      }
+      {
+        const int buf = (kt - kb) & 1;
+        gload(ra1, rb1, (int64_t)min(kt + 2, ke - 1) * BK);
+        compute(buf);
+        if (kt + 1 < ke) lstore(ra0, rb0, buf ^ 1);
+        __syncthreads();
+        if (++kt >= ke) break;
+      }
+    }
+  } else {
+    __syncthreads();
+    for (int kt = kb; kt < ke; ++kt) {
+      const int buf = (kt - kb) & 1;
+      const bool more = kt + 1 < ke;
+      if (more) gload(ra0, rb0, (int64_t)(kt + 1) * BK);
+      compute(buf);
+      if (more) lstore(ra0, rb0, buf ^ 1);
+      __syncthreads();
+    }
   }
 
   if (wi.piece >= 0) {
